@@ -1,0 +1,161 @@
+/*
+ * hm.h -- C ABI of libhm: evaluation Y = K~ W of a compressed H^2 (HMatrix)
+ * kernel matrix on an AMD Instinct MI355X (gfx950).
+ *
+ * The operation (MatRox, arXiv 1812.07152, Section 2.1 "Evaluation", with the
+ * compressed representation of Section 3.1): K~ is the N x N matrix made of
+ *   - near blocks  K~[I_a, I_b] = D_ab (dense, leaf pairs in the near lists),
+ *   - far blocks   K~[I_a, I_b] = Pc_a^T B_ab Pc_b for the far pairs, where the
+ *     nested basis Pc_a is the leaf interpolation matrix P_a for a leaf and
+ *     T_a * blockdiag(Pc_left, Pc_right) for an internal node (the V/U
+ *     generators; U = V for the symmetric kernels the paper targets).
+ * Evaluation computes Y = K~ W without assembling K~: a bottom-up pass over
+ * the cluster tree (skeleton weights), the far-field reduction over B, a
+ * top-down pass, and the near-field reduction over D (the two loop types the
+ * paper distinguishes: reduction loops and tree loops).
+ *
+ * Conventions for every entry point:
+ *   - Every function returns hm_status (HM_OK = 0) and never throws; on a
+ *     non-OK status hm_last_error() describes the failure (thread-local).
+ *   - Arguments are validated before any device work; an invalid argument
+ *     returns HM_ERR_INVALID and launches nothing.
+ *   - W and Y are caller-owned DEVICE pointers (HIP global memory), row-major
+ *     N x Q with leading dimensions ldw, ldy (in elements, >= Q), in the
+ *     caller's original point order unless HM_TREE_ORDER is set.  Y is
+ *     overwritten, never accumulated.  Both must stay alive until the work
+ *     enqueued on the stream has completed.
+ *   - hm_eval is asynchronous on the caller's hipStream_t (NULL = the null
+ *     stream); W may be reused or freed only after the stream has completed.
+ *   - The library owns the device copy of the compressed representation and
+ *     all workspaces; they live until hm_free().
+ */
+#ifndef HM_H
+#define HM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HM_OK = 0,
+    HM_ERR_INVALID = -1,  /* bad argument (null pointer, Q < 0, ld < Q, precision not loaded, ...) */
+    HM_ERR_FORMAT = -2,   /* malformed compressed representation (file or host arrays) */
+    HM_ERR_NOMEM = -3,    /* device or host allocation failed */
+    HM_ERR_DEVICE = -4,   /* a HIP call failed */
+    HM_ERR_BUSY = -5,     /* admission refused (server): retry later */
+    HM_ERR_PENDING = -6,  /* result not ready yet */
+    HM_ERR_INTERNAL = -7
+} hm_status;
+
+/* Element type of W and Y. */
+typedef enum { HM_F64 = 0, HM_F32 = 1 } hm_dtype;
+
+/* Arithmetic used for the block products.
+ *   HM_PREC_FP64: FP64 everywhere (W, Y in FP64).
+ *   HM_PREC_FP32: FP32 blocks and FP32 accumulation (W, Y in FP32). */
+typedef enum { HM_PREC_FP64 = 0, HM_PREC_FP32 = 1 } hm_prec;
+
+/* Bit for hm_load_*'s prec_mask: which precisions to keep on the device. */
+#define HM_PRECBIT(p) (1u << (unsigned)(p))
+
+/* hm_eval flags */
+#define HM_TREE_ORDER 1u  /* W and Y are already in tree order: skip both permutes */
+#define HM_PROFILE 2u     /* record HIP events around each phase (see hm_profile_read) */
+
+typedef struct hm_matrix_s *hm_matrix;
+
+/* Host view of a compressed representation (the HMC1 file's content).  All
+ * pointers are borrowed and only read during hm_load_compressed_mem.  Arrays
+ * are indexed by node 0..n_nodes-1 (node 0 is the root) or by pair.
+ *   perm[t]       original index of the point at tree position t (N entries)
+ *   start,size    each node owns tree positions [start, start+size)
+ *   parent,left,right  tree links (-1 when absent); a node has 0 or 2 children
+ *   level         depth from the root; rank = k_a (0 = no basis)
+ *   basis_off     offset (in doubles) of the node's basis in basis[]: the
+ *                 k_a x size_a matrix P_a (leaf) or k_a x (k_l + k_r) transfer
+ *                 T_a (internal), row-major, columns [skeleton(l), skeleton(r)]
+ *   far_ptr/far_col/far_off, B   far pairs, CSR by row node a: B_ab is
+ *                 k_a x k_b row-major at B + far_off[e]
+ *   near_ptr/near_col/near_off, D near pairs (leaves only): D_ab is
+ *                 size_a x size_b row-major at D + near_off[e], rows and columns
+ *                 in tree order
+ *   skel_ptr/skel optional (may be NULL): skeleton point indices per node. */
+typedef struct {
+    int64_t N, d;
+    int32_t n_nodes, depth;
+    uint32_t flags;                 /* bit0: built with HSS admissibility (metadata) */
+    int32_t kernel;                 /* metadata: 0 Gaussian, 1 Laplace-type */
+    double h, tol, tau;             /* metadata */
+    int32_t rmax, m;                /* metadata */
+    int64_t n_far, n_near, basis_len, B_len, D_len, skel_len;
+    const int64_t *perm, *start, *size;
+    const int32_t *parent, *left, *right, *level, *rank;
+    const int64_t *basis_off;
+    const double *basis;
+    const int64_t *far_ptr;
+    const int32_t *far_col;
+    const int64_t *far_off;
+    const double *B;
+    const int64_t *near_ptr;
+    const int32_t *near_col;
+    const int64_t *near_off;
+    const double *D;
+    const int64_t *skel_ptr, *skel;
+} hm_host_repr;
+
+typedef struct {
+    int64_t N;
+    int32_t n_nodes, depth, max_rank, device;
+    int64_t n_far, n_near;
+    int64_t E_V, E_T, E_B, E_D;     /* stored entries of leaf bases, transfers, B, D */
+    double flops_per_col;           /* algorithmic flops per column of W: 2(2E_V+2E_T+E_B+E_D) */
+    double bytes_fp64, bytes_fp32;  /* device bytes of the block store per precision (0 = not loaded) */
+    int32_t n_phases;               /* launches of one evaluation (excluding permutes) */
+} hm_info_t;
+
+/* Load the compressed representation from an HMC1 file (the inspector's
+ * output: 128-byte little-endian header "HMC1", version 1, then the arrays of
+ * hm_host_repr in its field order) onto HIP device `device`, keeping the
+ * precisions in prec_mask (HM_PRECBIT(HM_PREC_FP64) | ...).  The file is
+ * parsed and validated on the host first: HM_ERR_FORMAT for a bad magic,
+ * version, size or inconsistent structure (nothing is allocated on the device
+ * then).  On success *out owns the device copy. */
+hm_status hm_load_compressed(const char *path, int device, unsigned prec_mask, hm_matrix *out);
+
+/* Same, from host arrays (copied; the caller may free them on return). */
+hm_status hm_load_compressed_mem(const hm_host_repr *repr, int device, unsigned prec_mask,
+                                 hm_matrix *out);
+
+/* Sizes and algorithmic cost of a loaded matrix. */
+hm_status hm_info(hm_matrix h, hm_info_t *out);
+
+/* Release the device copy and workspaces.  NULL is accepted.  The caller must
+ * make sure no enqueued hm_eval on h is still running. */
+hm_status hm_free(hm_matrix h);
+
+/* Y = K~ W for Q columns on `stream` (a hipStream_t, NULL = null stream).
+ * dtype must be HM_F64 with HM_PREC_FP64 and HM_F32 with HM_PREC_FP32; the
+ * precision must have been loaded.  Q = 0 is a valid no-op.  Workspaces grow
+ * on demand (the first call at a larger Q allocates).  Calls on the same h
+ * must be serialized by the caller (they share workspaces). */
+hm_status hm_eval(hm_matrix h, const void *W, int64_t ldw, void *Y, int64_t ldy, int64_t Q,
+                  hm_dtype dtype, hm_prec prec, unsigned flags, void *stream);
+
+/* Per-phase timings of evaluations run with HM_PROFILE since the last reset:
+ * for phase i (0 permute-in, 1 up pass, 2 down pass (far reduction and
+ * transfers), 3 leaf pass (near field and leaf basis), 4 permute-out) writes the
+ * summed milliseconds to ms[i] and the number of launches to launches[i].
+ * Synchronizes with the recorded events. */
+hm_status hm_profile_read(hm_matrix h, double ms[5], int64_t launches[5]);
+hm_status hm_profile_reset(hm_matrix h);
+
+/* Message for the last non-OK status returned on this thread. */
+const char *hm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HM_H */

@@ -1,0 +1,9 @@
+"""MI355X-native evaluation Y = K~ W of compressed H^2 kernel matrices
+(the evaluation phase of MatRox, arXiv 1812.07152).
+
+The compute path is libhm.so (HIP kernels for gfx950) behind the C ABI of
+include/hm.h; this package is its Python binding.
+"""
+from .hm import (HM_F32, HM_F64, HM_PREC_FP32, HM_PREC_FP64, HM_PROFILE, HM_TREE_ORDER,  # noqa: F401
+                 HMError, Matrix, hm_eval, hm_free, hm_info, hm_last_error, hm_load_compressed,
+                 hm_load_compressed_mem, hm_profile_read, hm_profile_reset, precbit)

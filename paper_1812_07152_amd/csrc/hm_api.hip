@@ -1,0 +1,240 @@
+// hm_api.hip -- the extern "C" entry points declared in include/hm.h.
+#include <algorithm>
+#include <cstdio>
+#include <new>
+#include <string>
+
+#include "hm_internal.h"
+
+namespace hm {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+hm_status fail(hm_status s, const std::string &msg) {
+    g_last_error = msg;
+    return s;
+}
+
+namespace {
+
+#define HM_HIP(call)                                                                  \
+    do {                                                                              \
+        hipError_t e_ = (call);                                                       \
+        if (e_ != hipSuccess)                                                         \
+            return fail(e_ == hipErrorOutOfMemory ? HM_ERR_NOMEM : HM_ERR_DEVICE,     \
+                        std::string(#call ": ") + hipGetErrorString(e_));            \
+    } while (0)
+
+struct DeviceScope {
+    int prev = -1;
+    hipError_t err = hipSuccess;
+    explicit DeviceScope(int dev) {
+        err = hipGetDevice(&prev);
+        if (err == hipSuccess && prev != dev) err = hipSetDevice(dev);
+    }
+    ~DeviceScope() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+// Grow workspace `b` of element size `es` (slot 0: 8 bytes, 1: 4 bytes) to `bytes`.
+hm_status ensure_ws(hm_matrix h, int slot, int b, size_t bytes) {
+    bytes = std::max<size_t>(bytes, 256);
+    if (h->ws_bytes[slot][b] >= bytes) return HM_OK;
+    if (h->ws[slot][b]) {
+        HM_HIP(hipDeviceSynchronize());
+        HM_HIP(hipFree(h->ws[slot][b]));
+        h->ws[slot][b] = nullptr;
+        h->ws_bytes[slot][b] = 0;
+    }
+    HM_HIP(hipMalloc(&h->ws[slot][b], bytes));
+    h->ws_bytes[slot][b] = bytes;
+    return HM_OK;
+}
+
+// Phase group of a Phase.kind for profiling: 1 up, 2 down, 3 leaf.
+int group_of(int kind) { return kind; }
+
+hm_status record(hm_matrix h, int group, hipStream_t s, hipEvent_t *ev) {
+    HM_HIP(hipEventCreate(ev));
+    HM_HIP(hipEventRecord(*ev, s));
+    (void)h;
+    (void)group;
+    return HM_OK;
+}
+
+}  // namespace
+}  // namespace hm
+
+using namespace hm;
+
+extern "C" {
+
+const char *hm_last_error(void) { return g_last_error.c_str(); }
+
+hm_status hm_load_compressed(const char *path, int device, unsigned prec_mask, hm_matrix *out) {
+    if (!out) return fail(HM_ERR_INVALID, "hm_load_compressed: out is NULL");
+    *out = nullptr;
+    if (!(prec_mask & (HM_PRECBIT(HM_PREC_FP64) | HM_PRECBIT(HM_PREC_FP32))))
+        return fail(HM_ERR_INVALID, "hm_load_compressed: prec_mask selects no precision");
+    HostRepr r;
+    hm_status st = read_file(path, r);
+    if (st != HM_OK) return st;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count)
+        return fail(HM_ERR_INVALID, "hm_load_compressed: no such HIP device");
+    return build_matrix(r, device, prec_mask, out);
+}
+
+hm_status hm_load_compressed_mem(const hm_host_repr *repr, int device, unsigned prec_mask,
+                                 hm_matrix *out) {
+    if (!out) return fail(HM_ERR_INVALID, "hm_load_compressed_mem: out is NULL");
+    *out = nullptr;
+    if (!repr) return fail(HM_ERR_INVALID, "hm_load_compressed_mem: repr is NULL");
+    if (!(prec_mask & (HM_PRECBIT(HM_PREC_FP64) | HM_PRECBIT(HM_PREC_FP32))))
+        return fail(HM_ERR_INVALID, "hm_load_compressed_mem: prec_mask selects no precision");
+    HostRepr r;
+    hm_status st = from_view(*repr, r);
+    if (st != HM_OK) return st;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count)
+        return fail(HM_ERR_INVALID, "hm_load_compressed_mem: no such HIP device");
+    return build_matrix(r, device, prec_mask, out);
+}
+
+hm_status hm_info(hm_matrix h, hm_info_t *o) {
+    if (!h || !o) return fail(HM_ERR_INVALID, "hm_info: NULL argument");
+    o->N = h->N;
+    o->n_nodes = h->n_nodes;
+    o->depth = h->depth;
+    o->max_rank = h->max_rank;
+    o->device = h->device;
+    o->n_far = h->n_far;
+    o->n_near = h->n_near;
+    o->E_V = h->E_V;
+    o->E_T = h->E_T;
+    o->E_B = h->E_B;
+    o->E_D = h->E_D;
+    o->flops_per_col = 2.0 * (2.0 * h->E_V + 2.0 * h->E_T + (double)h->E_B + (double)h->E_D);
+    o->bytes_fp64 = (double)h->prec[HM_PREC_FP64].bytes;
+    o->bytes_fp32 = (double)h->prec[HM_PREC_FP32].bytes;
+    o->n_phases = (int32_t)h->phases.size();
+    return HM_OK;
+}
+
+hm_status hm_free(hm_matrix h) {
+    if (!h) return HM_OK;
+    DeviceScope ds(h->device);
+    for (int i = 0; i < 2; i++)
+        if (h->prec[i].blocks) (void)hipFree(h->prec[i].blocks);
+    for (int s = 0; s < 2; s++)
+        for (int b = 0; b < BUF_COUNT; b++)
+            if (h->ws[s][b]) (void)hipFree(h->ws[s][b]);
+    if (h->d_perm) (void)hipFree(h->d_perm);
+    if (h->d_tasks) (void)hipFree(h->d_tasks);
+    if (h->d_segs) (void)hipFree(h->d_segs);
+    for (int g = 0; g < 5; g++)
+        for (auto &pr : h->prof.pending[g]) {
+            (void)hipEventDestroy(pr.first);
+            (void)hipEventDestroy(pr.second);
+        }
+    delete h;
+    return HM_OK;
+}
+
+hm_status hm_eval(hm_matrix h, const void *W, int64_t ldw, void *Y, int64_t ldy, int64_t Q,
+                  hm_dtype dtype, hm_prec prec, unsigned flags, void *stream) {
+    if (!h) return fail(HM_ERR_INVALID, "hm_eval: matrix handle is NULL");
+    if (Q < 0) return fail(HM_ERR_INVALID, "hm_eval: Q < 0");
+    if (Q == 0) return HM_OK;
+    if (!W || !Y) return fail(HM_ERR_INVALID, "hm_eval: W or Y is NULL");
+    if (ldw < Q || ldy < Q) return fail(HM_ERR_INVALID, "hm_eval: leading dimension < Q");
+    if (flags & ~(HM_TREE_ORDER | HM_PROFILE)) return fail(HM_ERR_INVALID, "hm_eval: unknown flags");
+    if (!((dtype == HM_F64 && prec == HM_PREC_FP64) || (dtype == HM_F32 && prec == HM_PREC_FP32)))
+        return fail(HM_ERR_INVALID, "hm_eval: dtype and precision do not match");
+    if (!h->prec[prec].blocks) return fail(HM_ERR_INVALID, "hm_eval: precision was not loaded");
+    if (Q > (int64_t)1 << 24) return fail(HM_ERR_INVALID, "hm_eval: Q too large");
+    DeviceScope ds(h->device);
+    if (ds.err != hipSuccess) return fail(HM_ERR_DEVICE, "hm_eval: cannot select the device");
+    hipStream_t s = (hipStream_t)stream;
+    const int es = dtype == HM_F64 ? 8 : 4, slot = dtype == HM_F64 ? 0 : 1;
+    const int64_t Qp = (Q + 15) / 16 * 16;
+    const size_t rows[BUF_COUNT] = {(size_t)h->N, (size_t)h->N, (size_t)h->skel_rows,
+                                    (size_t)h->skel_rows};
+    for (int b = 0; b < BUF_COUNT; b++) {
+        hm_status st = ensure_ws(h, slot, b, rows[b] * (size_t)Qp * es);
+        if (st != HM_OK) return st;
+    }
+    void *bufs[BUF_COUNT];
+    for (int b = 0; b < BUF_COUNT; b++) bufs[b] = h->ws[slot][b];
+    const bool prof = (flags & HM_PROFILE) != 0;
+    const int64_t *perm = (flags & HM_TREE_ORDER) ? nullptr : h->d_perm;
+
+    auto mark = [&](int group, bool begin) -> hm_status {
+        if (!prof) return HM_OK;
+        hipEvent_t ev;
+        hm_status st = record(h, group, s, &ev);
+        if (st != HM_OK) return st;
+        if (begin)
+            h->prof.pending[group].push_back({ev, nullptr});
+        else
+            h->prof.pending[group].back().second = ev;
+        return HM_OK;
+    };
+    hm_status st;
+    if ((st = mark(0, true)) != HM_OK) return st;
+    HM_HIP(launch_permute_in(W, ldw, bufs[BUF_WT], Qp, perm, h->N, Q, es, s));
+    if ((st = mark(0, false)) != HM_OK) return st;
+    int open_group = -1;
+    for (const Phase &ph : h->phases) {
+        int g = group_of(ph.kind);
+        if (g != open_group) {
+            if (open_group >= 0 && (st = mark(open_group, false)) != HM_OK) return st;
+            if ((st = mark(g, true)) != HM_OK) return st;
+            open_group = g;
+        }
+        HM_HIP(launch_phase(h, ph, es, Qp, bufs, s));
+    }
+    if (open_group >= 0 && (st = mark(open_group, false)) != HM_OK) return st;
+    if ((st = mark(4, true)) != HM_OK) return st;
+    HM_HIP(launch_permute_out(bufs[BUF_YT], Qp, Y, ldy, perm, h->N, Q, es, s));
+    if ((st = mark(4, false)) != HM_OK) return st;
+    return HM_OK;
+}
+
+hm_status hm_profile_read(hm_matrix h, double ms[5], int64_t launches[5]) {
+    if (!h || !ms || !launches) return fail(HM_ERR_INVALID, "hm_profile_read: NULL argument");
+    DeviceScope ds(h->device);
+    for (int g = 0; g < 5; g++) {
+        for (auto &pr : h->prof.pending[g]) {
+            HM_HIP(hipEventSynchronize(pr.second));
+            float t = 0.f;
+            HM_HIP(hipEventElapsedTime(&t, pr.first, pr.second));
+            h->prof.ms[g] += t;
+            h->prof.launches[g] += 1;
+            (void)hipEventDestroy(pr.first);
+            (void)hipEventDestroy(pr.second);
+        }
+        h->prof.pending[g].clear();
+        ms[g] = h->prof.ms[g];
+        launches[g] = h->prof.launches[g];
+    }
+    return HM_OK;
+}
+
+hm_status hm_profile_reset(hm_matrix h) {
+    if (!h) return fail(HM_ERR_INVALID, "hm_profile_reset: NULL argument");
+    double ms[5];
+    int64_t l[5];
+    hm_status st = hm_profile_read(h, ms, l);
+    if (st != HM_OK) return st;
+    for (int g = 0; g < 5; g++) {
+        h->prof.ms[g] = 0;
+        h->prof.launches[g] = 0;
+    }
+    return HM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,329 @@
+// hm_build.hip -- turn a validated representation into the device block store
+// and the per-phase task tables of the evaluation.
+//
+// Phases, in launch order (Section 2.1 "Evaluation"; the loop structure of
+// the paper's executor, re-cut into one launch per tree level):
+//   up(l), l = deepest..1   nodes at level l with k > 0:
+//                           What_a = P_a Wt[I_a] (leaf) or T_a [What_l; What_r]
+//   down(l), l = 1..deepest nodes at level l with k > 0:
+//                           Yhat_a = sum_{b in Far(a)} B_ab What_b
+//                                    + T_p[:, cols(a)]^T Yhat_p   (p = parent)
+//                           (the far reduction fused with the top-down pass)
+//   leaf                    every leaf a:
+//                           Yt[I_a] = sum_{b in Near(a)} D_ab Wt[I_b] + P_a^T Yhat_a
+//                           (near reduction fused with the leaf far part and
+//                           the final sum)
+// The root has no far pairs (it overlaps every node), so it is skipped.
+#include <algorithm>
+#include <cstring>
+
+#include "hm_internal.h"
+
+namespace hm {
+
+namespace {
+
+int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+struct Block {            // one output block of a phase before tiling
+    int32_t out_buf;
+    int64_t out_row;
+    int32_t M;
+    std::vector<Seg> segs;
+    int64_t work() const {
+        int64_t k = 0;
+        for (const Seg &s : segs) k += s.K;
+        return k;
+    }
+};
+
+struct Planner {
+    int64_t store_off = 0;
+    std::vector<RepackJob> jobs[3];  // per source: 0 basis, 1 B, 2 D
+    std::vector<Task> tasks;
+    std::vector<Seg> segs;
+    std::vector<Phase> phases;
+
+    // Reserve a K-major block of `krows` stored rows of `ld` elements.
+    int64_t alloc(int64_t krows, int64_t ld) {
+        int64_t off = store_off;
+        store_off += round_up(krows * ld, 32);  // keep every block 256-byte aligned
+        return off;
+    }
+
+    void add_phase(int kind, int level, std::vector<Block> &blocks) {
+        if (blocks.empty()) return;
+        Phase ph{};
+        ph.kind = kind;
+        ph.level = level;
+        int32_t maxM = 0;
+        for (const Block &b : blocks) maxM = std::max(maxM, b.M);
+        ph.bm = maxM <= 64 ? 64 : 128;
+        // longest contraction first: the hardware dispatcher then fills the
+        // machine greedily (longest-processing-time order)
+        std::stable_sort(blocks.begin(), blocks.end(),
+                         [](const Block &x, const Block &y) { return x.work() > y.work(); });
+        ph.task_begin = (int32_t)tasks.size();
+        double flops = 0;
+        for (const Block &b : blocks) {
+            int32_t sb = (int32_t)segs.size();
+            for (const Seg &s : b.segs) {
+                segs.push_back(s);
+                flops += 2.0 * b.M * s.K;
+            }
+            int32_t se = (int32_t)segs.size();
+            for (int32_t m0 = 0; m0 < std::max(b.M, 1); m0 += ph.bm) {
+                Task t{};
+                t.out_row = b.out_row + m0;
+                t.out_buf = b.out_buf;
+                t.M = std::min(ph.bm, b.M - m0);
+                t.m0 = m0;
+                t.seg_begin = sb;
+                t.seg_end = se;
+                tasks.push_back(t);
+            }
+        }
+        ph.task_count = (int32_t)tasks.size() - ph.task_begin;
+        ph.seg_count = 0;
+        ph.flops_per_col = flops;
+        phases.push_back(ph);
+    }
+};
+
+struct DevicePtrs {
+    void *p[8] = {nullptr};
+    int n = 0;
+    void add(void *q) { p[n++] = q; }
+    ~DevicePtrs() {
+        for (int i = 0; i < n; i++)
+            if (p[i]) (void)hipFree(p[i]);
+    }
+};
+
+#define HM_HIP(call)                                                                  \
+    do {                                                                              \
+        hipError_t e_ = (call);                                                       \
+        if (e_ != hipSuccess)                                                         \
+            return fail(e_ == hipErrorOutOfMemory ? HM_ERR_NOMEM : HM_ERR_DEVICE,     \
+                        std::string(#call ": ") + hipGetErrorString(e_));            \
+    } while (0)
+
+// Stage one source array through device memory in chunks and repack its jobs.
+hm_status repack_source(const double *host, std::vector<RepackJob> &jobs, double *store,
+                        double *stage, int64_t stage_elems, RepackJob *d_jobs, int64_t max_jobs,
+                        hipStream_t s) {
+    std::sort(jobs.begin(), jobs.end(),
+              [](const RepackJob &a, const RepackJob &b) { return a.src_off < b.src_off; });
+    size_t i = 0;
+    while (i < jobs.size()) {
+        const int64_t c0 = jobs[i].src_off;
+        int64_t c1 = c0;
+        size_t j = i;
+        while (j < jobs.size() && (int64_t)(j - i) < max_jobs) {
+            int64_t end = jobs[j].src_off + (int64_t)jobs[j].rows * jobs[j].cols;
+            if (end - c0 > stage_elems) break;
+            c1 = std::max(c1, end);
+            j++;
+        }
+        if (j == i) return fail(HM_ERR_INTERNAL, "repack: block larger than the staging buffer");
+        std::vector<RepackJob> chunk(jobs.begin() + i, jobs.begin() + j);
+        for (RepackJob &r : chunk) r.src_off -= c0;
+        HM_HIP(hipMemcpyAsync(stage, host + c0, sizeof(double) * (size_t)(c1 - c0),
+                              hipMemcpyHostToDevice, s));
+        HM_HIP(hipMemcpyAsync(d_jobs, chunk.data(), sizeof(RepackJob) * chunk.size(),
+                              hipMemcpyHostToDevice, s));
+        HM_HIP(launch_repack(stage, d_jobs, (int)chunk.size(), store, s));
+        HM_HIP(hipStreamSynchronize(s));
+        i = j;
+    }
+    return HM_OK;
+}
+
+}  // namespace
+
+hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_matrix *out) {
+    const int32_t n = r.n_nodes;
+    auto leaf = [&](int a) { return r.left[a] < 0; };
+    std::vector<int64_t> wrow((size_t)n + 1, 0);
+    for (int a = 0; a < n; a++) wrow[a + 1] = wrow[a] + r.rank[a];
+
+    Planner P;
+    std::vector<std::vector<int>> by_level((size_t)r.depth + 1);
+    for (int a = 0; a < n; a++) by_level[(size_t)r.level[a]].push_back(a);
+
+    int64_t E_V = 0, E_T = 0;
+    // up pass
+    for (int lvl = r.depth; lvl >= 1; lvl--) {
+        std::vector<Block> blocks;
+        for (int a : by_level[(size_t)lvl]) {
+            const int32_t k = r.rank[a];
+            if (k == 0) continue;
+            const int32_t kp = (int32_t)round_up(k, 16);
+            Block b{BUF_WHAT, wrow[a], k, {}};
+            if (leaf(a)) {
+                const int32_t m = (int32_t)r.size[a];
+                int64_t off = P.alloc(m, kp);
+                P.jobs[0].push_back({r.basis_off[a], off, k, m, 0, 0, 0, kp});
+                b.segs.push_back({off, r.start[a], kp, m, BUF_WT, 0});
+                E_V += (int64_t)k * m;
+            } else {
+                const int32_t kl = r.rank[r.left[a]], kr = r.rank[r.right[a]];
+                int64_t off = P.alloc(kl + kr, kp);
+                P.jobs[0].push_back({r.basis_off[a], off, k, kl + kr, 0, 0, 0, kp});
+                if (kl > 0) b.segs.push_back({off, wrow[r.left[a]], kp, kl, BUF_WHAT, 0});
+                if (kr > 0) b.segs.push_back({off + (int64_t)kl * kp, wrow[r.right[a]], kp, kr, BUF_WHAT, 0});
+                E_T += (int64_t)k * (kl + kr);
+            }
+            blocks.push_back(std::move(b));
+        }
+        P.add_phase(1, lvl, blocks);
+    }
+    // down pass (far reduction fused with the top-down transfers)
+    int64_t E_B = 0;
+    for (int lvl = 1; lvl <= r.depth; lvl++) {
+        std::vector<Block> blocks;
+        for (int a : by_level[(size_t)lvl]) {
+            const int32_t ka = r.rank[a];
+            if (ka == 0) continue;
+            const int32_t kap = (int32_t)round_up(ka, 16);
+            Block b{BUF_YHAT, wrow[a], ka, {}};
+            for (int64_t e = r.far_ptr[a]; e < r.far_ptr[a + 1]; e++) {
+                const int32_t bn = r.far_col[e], kb = r.rank[bn];
+                if (kb == 0) continue;
+                int64_t off = P.alloc(kb, kap);
+                P.jobs[1].push_back({r.far_off[e], off, ka, kb, 0, 0, 0, kap});
+                b.segs.push_back({off, wrow[bn], kap, kb, BUF_WHAT, 0});
+                E_B += (int64_t)ka * kb;
+            }
+            const int32_t p = r.parent[a];
+            if (p >= 0 && r.level[p] >= 1 && r.rank[p] > 0) {
+                const int32_t kpar = r.rank[p], kl = r.rank[r.left[p]], kr = r.rank[r.right[p]];
+                const int32_t c0 = (a == r.left[p]) ? 0 : kl;
+                int64_t off = P.alloc(kpar, kap);
+                P.jobs[0].push_back({r.basis_off[p], off, kpar, kl + kr, 1, c0, ka, kap});
+                b.segs.push_back({off, wrow[p], kap, kpar, BUF_YHAT, 0});
+            }
+            blocks.push_back(std::move(b));
+        }
+        P.add_phase(2, lvl, blocks);
+    }
+    // leaf pass (near reduction + leaf far part + final sum)
+    int64_t E_D = 0;
+    {
+        std::vector<Block> blocks;
+        for (int a = 0; a < n; a++) {
+            if (!leaf(a)) continue;
+            const int32_t ma = (int32_t)r.size[a], map = (int32_t)round_up(ma, 16);
+            Block b{BUF_YT, r.start[a], ma, {}};
+            for (int64_t e = r.near_ptr[a]; e < r.near_ptr[a + 1]; e++) {
+                const int32_t bn = r.near_col[e];
+                const int32_t mb = (int32_t)r.size[bn];
+                int64_t off = P.alloc(mb, map);
+                P.jobs[2].push_back({r.near_off[e], off, ma, mb, 0, 0, 0, map});
+                b.segs.push_back({off, r.start[bn], map, mb, BUF_WT, 0});
+                E_D += (int64_t)ma * mb;
+            }
+            const int32_t k = r.rank[a];
+            if (k > 0 && r.level[a] >= 1) {
+                int64_t off = P.alloc(k, map);
+                P.jobs[0].push_back({r.basis_off[a], off, k, ma, 1, 0, ma, map});
+                b.segs.push_back({off, wrow[a], map, k, BUF_YHAT, 0});
+            }
+            blocks.push_back(std::move(b));
+        }
+        P.add_phase(3, r.depth, blocks);
+    }
+
+    // ---- device side
+    int prev = 0;
+    HM_HIP(hipGetDevice(&prev));
+    HM_HIP(hipSetDevice(device));
+    struct Restore {
+        int d;
+        ~Restore() { (void)hipSetDevice(d); }
+    } restore{prev};
+
+    hm_matrix h = new (std::nothrow) hm_matrix_s();
+    if (!h) return fail(HM_ERR_NOMEM, "hm_load: host allocation failed");
+    struct Guard {
+        hm_matrix h;
+        bool keep = false;
+        ~Guard() {
+            if (!keep) hm_free(h);
+        }
+    } guard{h};
+    h->device = device;
+    h->N = r.N;
+    h->n_nodes = n;
+    h->depth = r.depth;
+    for (int a = 0; a < n; a++) h->max_rank = std::max(h->max_rank, r.rank[a]);
+    h->n_far = (int64_t)r.far_col.size();
+    h->n_near = (int64_t)r.near_col.size();
+    h->E_V = E_V;
+    h->E_T = E_T;
+    h->E_B = E_B;
+    h->E_D = E_D;
+    h->skel_rows = wrow[n];
+    h->store_elems = std::max<int64_t>(P.store_off, 32);
+    h->phases = P.phases;
+
+    hipStream_t s = nullptr;
+    HM_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    struct StreamGuard {
+        hipStream_t s;
+        ~StreamGuard() { (void)hipStreamDestroy(s); }
+    } sg{s};
+
+    double *store64 = nullptr;
+    HM_HIP(hipMalloc(&store64, sizeof(double) * (size_t)h->store_elems));
+    h->prec[HM_PREC_FP64].blocks = store64;
+    h->prec[HM_PREC_FP64].bytes = sizeof(double) * (size_t)h->store_elems;
+    HM_HIP(hipMemsetAsync(store64, 0, sizeof(double) * (size_t)h->store_elems, s));
+    {
+        const int64_t max_src = std::max({r.basis_len, r.B_len, r.D_len, (int64_t)1});
+        const int64_t stage_elems = std::min<int64_t>(max_src, (int64_t)64 << 20);  // <= 512 MiB
+        const int64_t max_jobs = 1 << 16;
+        DevicePtrs tmp;
+        double *stage = nullptr;
+        RepackJob *d_jobs = nullptr;
+        HM_HIP(hipMalloc(&stage, sizeof(double) * (size_t)stage_elems));
+        tmp.add(stage);
+        HM_HIP(hipMalloc(&d_jobs, sizeof(RepackJob) * (size_t)max_jobs));
+        tmp.add(d_jobs);
+        const double *src[3] = {r.basis_ptr(), r.B_ptr(), r.D_ptr()};
+        for (int k = 0; k < 3; k++) {
+            hm_status st = repack_source(src[k], P.jobs[k], store64, stage, stage_elems, d_jobs,
+                                         max_jobs, s);
+            if (st != HM_OK) return st;
+        }
+    }
+    if (prec_mask & HM_PRECBIT(HM_PREC_FP32)) {
+        float *store32 = nullptr;
+        HM_HIP(hipMalloc(&store32, sizeof(float) * (size_t)h->store_elems));
+        h->prec[HM_PREC_FP32].blocks = store32;
+        h->prec[HM_PREC_FP32].bytes = sizeof(float) * (size_t)h->store_elems;
+        HM_HIP(launch_convert_f64_to_f32(store64, store32, h->store_elems, s));
+    }
+    HM_HIP(hipMalloc(&h->d_perm, sizeof(int64_t) * (size_t)r.N));
+    HM_HIP(hipMemcpyAsync(h->d_perm, r.perm.data(), sizeof(int64_t) * (size_t)r.N,
+                          hipMemcpyHostToDevice, s));
+    HM_HIP(hipMalloc(&h->d_tasks, sizeof(Task) * std::max<size_t>(P.tasks.size(), 1)));
+    HM_HIP(hipMalloc(&h->d_segs, sizeof(Seg) * std::max<size_t>(P.segs.size(), 1)));
+    if (!P.tasks.empty())
+        HM_HIP(hipMemcpyAsync(h->d_tasks, P.tasks.data(), sizeof(Task) * P.tasks.size(),
+                              hipMemcpyHostToDevice, s));
+    if (!P.segs.empty())
+        HM_HIP(hipMemcpyAsync(h->d_segs, P.segs.data(), sizeof(Seg) * P.segs.size(),
+                              hipMemcpyHostToDevice, s));
+    HM_HIP(hipStreamSynchronize(s));
+    if (!(prec_mask & HM_PRECBIT(HM_PREC_FP64))) {
+        HM_HIP(hipFree(store64));
+        h->prec[HM_PREC_FP64].blocks = nullptr;
+        h->prec[HM_PREC_FP64].bytes = 0;
+    }
+    guard.keep = true;
+    *out = h;
+    return HM_OK;
+}
+
+}  // namespace hm

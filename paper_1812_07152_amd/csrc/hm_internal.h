@@ -1,0 +1,148 @@
+// hm_internal.h -- internal types of libhm (host side and kernel interface).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/hm.h"
+
+namespace hm {
+
+// Workspace buffers the block products read from and write to.  Each is
+// row-major with leading dimension Qp (Q rounded up to a multiple of 16).
+enum Buf : int32_t {
+    BUF_WT = 0,    // N x Qp   W in tree order
+    BUF_YT = 1,    // N x Qp   Y in tree order
+    BUF_WHAT = 2,  // R x Qp   skeleton weights, node a at rows [wrow[a], wrow[a]+k_a)
+    BUF_YHAT = 3,  // R x Qp   skeleton potentials, same rows
+    BUF_COUNT = 4
+};
+
+// One operand pair of a block product: the A block (stored K-major: element
+// (row i, contraction t) at a_off + t*lda + i, zero-padded to lda >= M rows)
+// times K rows of workspace buffer b_buf starting at row b_row.
+struct Seg {
+    int64_t a_off;  // element offset into the block store
+    int64_t b_row;
+    int32_t lda;    // padded row count of the A block (multiple of 16)
+    int32_t K;      // contraction length (> 0)
+    int32_t b_buf;
+    int32_t pad_;
+};
+
+// One output block: rows [out_row, out_row + M) of buffer out_buf (M <= tile
+// height) receive the sum over segments [seg_begin, seg_end) (overwritten).
+// m0 is the first row of the A blocks this task covers (tasks taller than the
+// tile are split).
+struct Task {
+    int64_t out_row;
+    int32_t out_buf;
+    int32_t M;
+    int32_t m0;
+    int32_t seg_begin;
+    int32_t seg_end;
+    int32_t pad_;
+};
+
+// A phase = one launch: a contiguous task range with a common tile height.
+struct Phase {
+    int32_t kind;         // 1 up, 2 down, 3 leaf
+    int32_t level;
+    int32_t task_begin;
+    int32_t task_count;
+    int32_t bm;           // tile height (64 or 128)
+    int64_t seg_count;
+    double flops_per_col; // algorithmic flops of this phase per column
+};
+
+// Validated host-side copy of the compressed representation.
+struct HostRepr {
+    int64_t N = 0, d = 0;
+    int32_t n_nodes = 0, depth = 0;
+    uint32_t flags = 0;
+    int32_t kernel = 0, rmax = 0, m = 0;
+    double h = 0, tol = 0, tau = 0;
+    std::vector<int64_t> perm, start, size, basis_off, far_ptr, far_off, near_ptr, near_off;
+    std::vector<int32_t> parent, left, right, level, rank, far_col, near_col;
+    std::vector<double> basis, B, D;          // owned values (file loads)
+    const double *basis_ext = nullptr;         // borrowed values (host-array loads)
+    const double *B_ext = nullptr;
+    const double *D_ext = nullptr;
+    int64_t basis_len = 0, B_len = 0, D_len = 0;
+    const double *basis_ptr() const { return basis_ext ? basis_ext : basis.data(); }
+    const double *B_ptr() const { return B_ext ? B_ext : B.data(); }
+    const double *D_ptr() const { return D_ext ? D_ext : D.data(); }
+};
+
+// One block copy of the device repack (see k_repack).
+struct RepackJob {
+    int64_t src_off;  // offset into the staged source chunk
+    int64_t dst_off;  // offset into the block store
+    int32_t rows, cols;
+    int32_t mode;     // 0 transpose, 1 column slice
+    int32_t c0, ncols;
+    int32_t ld;       // padded length of a stored row
+};
+
+struct PrecStore {
+    void *blocks = nullptr;   // device block store (FP64 or FP32 elements)
+    size_t bytes = 0;
+};
+
+struct ProfileAcc {
+    double ms[5] = {0, 0, 0, 0, 0};
+    int64_t launches[5] = {0, 0, 0, 0, 0};
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[5];
+};
+
+}  // namespace hm
+
+struct hm_matrix_s {
+    int device = 0;
+    int64_t N = 0;
+    int32_t n_nodes = 0, depth = 0, max_rank = 0;
+    int64_t n_far = 0, n_near = 0;
+    int64_t E_V = 0, E_T = 0, E_B = 0, E_D = 0;
+    int64_t skel_rows = 0;                 // rows of the What / Yhat buffers
+    int64_t store_elems = 0;               // elements of the padded block store
+    hm::PrecStore prec[2];                 // [HM_PREC_FP64], [HM_PREC_FP32]
+    int64_t *d_perm = nullptr;             // tree position -> original index
+    hm::Task *d_tasks = nullptr;
+    hm::Seg *d_segs = nullptr;
+    std::vector<hm::Phase> phases;
+    // workspaces (per element size), grown on demand
+    void *ws[2][hm::BUF_COUNT] = {{nullptr}};
+    size_t ws_bytes[2][hm::BUF_COUNT] = {{0}};
+    hm::ProfileAcc prof;
+};
+
+namespace hm {
+
+// Thread-local error reporting.
+hm_status fail(hm_status s, const std::string &msg);
+
+// Parse an HMC1 file into a HostRepr (host only; no device work).
+hm_status read_file(const char *path, HostRepr &out);
+// Copy and validate host arrays.
+hm_status from_view(const hm_host_repr &v, HostRepr &out);
+// Structural validation shared by both loaders.
+hm_status validate(const HostRepr &r);
+
+// Build the device store, tables and phases for a validated representation.
+hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_matrix *out);
+
+// Kernel launchers (hm_kernels.hip).
+hipError_t launch_phase(const hm_matrix_s *h, const Phase &ph, int elem_bytes, int64_t Qp,
+                        void *const bufs[BUF_COUNT], hipStream_t s);
+hipError_t launch_permute_in(const void *W, int64_t ldw, void *Wt, int64_t Qp, const int64_t *perm,
+                             int64_t N, int64_t Q, int elem_bytes, hipStream_t s);
+hipError_t launch_permute_out(const void *Yt, int64_t Qp, void *Y, int64_t ldy, const int64_t *perm,
+                              int64_t N, int64_t Q, int elem_bytes, hipStream_t s);
+hipError_t launch_convert_f64_to_f32(const double *src, float *dst, int64_t n, hipStream_t s);
+hipError_t launch_repack(const double *stage, const RepackJob *jobs, int njobs, double *store,
+                         hipStream_t s);
+
+}  // namespace hm

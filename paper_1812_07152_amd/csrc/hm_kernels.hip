@@ -1,0 +1,338 @@
+// hm_kernels.hip -- HIP kernels of the evaluation Y = K~ W for gfx950.
+//
+// Every step of the evaluation (Section 2.1 "Evaluation": the bottom-up V
+// loop, the reduction over the far blocks B, the top-down U loop and the
+// reduction over the near blocks D) is a set of small dense products
+//     out_block (M x Q) = sum_s A_s (M x K_s) * B_s (K_s x Q)
+// with A_s a stored block and B_s a row range of a workspace.  One kernel,
+// k_block_products, runs a whole phase of them: one workgroup per (output
+// block, column tile) accumulates all of its segments in registers and writes
+// its block once (a single writer per output row block, as in the paper's
+// blocking, Section 3.2, so no atomics are needed and results are
+// deterministic).
+//
+// Tiling: a BM x BN output tile per workgroup, split over WAVES_M x WAVES_N
+// wave64s, each wave owning (BM/WAVES_M) x (BN/WAVES_N) = FM x FN MFMA
+// 16x16 fragments.  The contraction runs in chunks of BK = 16: A and B chunks
+// are loaded with 16-byte vector loads into registers, written to one of two
+// LDS buffers while the other is consumed by the MFMAs (one barrier per
+// chunk).  Lane mapping of the 16x16x4 MFMAs (checked on the device): lane l
+// supplies A[l%16][l/16] and B[l/16][l%16]; accumulator register r of lane l
+// holds D[4r + l/16][l%16] for FP64 and D[4(l/16) + r][l%16] for FP32.
+#include "hm_internal.h"
+
+namespace hm {
+
+namespace {
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct Mfma;
+
+template <>
+struct Mfma<double> {
+    typedef d4_t acc_t;
+    typedef double2 vec_t;  // 16 bytes
+    static constexpr int kVec = 2;
+    static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int r) { return 4 * r + (lane >> 4); }
+};
+
+template <>
+struct Mfma<float> {
+    typedef f4_t acc_t;
+    typedef float4 vec_t;
+    static constexpr int kVec = 4;
+    static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+
+constexpr int kBK = 16;
+
+template <typename T, int BM, int BN, int WAVES_M, int WAVES_N>
+__global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void k_block_products(
+    const Task *__restrict__ tasks, const Seg *__restrict__ segs, int task_begin,
+    const T *__restrict__ store, T *buf0, T *buf1, T *buf2, T *buf3, int64_t Qp) {
+    using M_ = Mfma<T>;
+    using acc_t = typename M_::acc_t;
+    using vec_t = typename M_::vec_t;
+    constexpr int NT = 64 * WAVES_M * WAVES_N;
+    constexpr int WM = BM / WAVES_M, WN = BN / WAVES_N;
+    constexpr int FM = WM / 16, FN = WN / 16;
+    constexpr int VEC = M_::kVec;
+    constexpr int A_ROWV = BM / VEC, B_ROWV = BN / VEC;        // vectors per chunk row
+    constexpr int A_VECS = kBK * A_ROWV, B_VECS = kBK * B_ROWV;
+    constexpr int A_PER = (A_VECS + NT - 1) / NT, B_PER = (B_VECS + NT - 1) / NT;
+    static_assert(FM >= 1 && FN >= 1 && WM % 16 == 0 && WN % 16 == 0, "bad tile");
+
+    __shared__ __attribute__((aligned(16))) T As[2][kBK][BM];
+    __shared__ __attribute__((aligned(16))) T Bs[2][kBK][BN];
+
+    const Task task = tasks[task_begin + blockIdx.x];
+    const int64_t n0 = (int64_t)blockIdx.y * BN;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave / WAVES_N, wn = wave % WAVES_N;
+    // buffer select without a dynamically indexed private array (which the
+    // compiler would otherwise place in LDS)
+    auto bufp = [&](int b) { return b == 0 ? buf0 : b == 1 ? buf1 : b == 2 ? buf2 : buf3; };
+
+    acc_t acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; i++)
+#pragma unroll
+        for (int j = 0; j < FN; j++) acc[i][j] = acc_t{0, 0, 0, 0};
+
+    vec_t ra[A_PER], rb[B_PER];
+    const vec_t zero = {};
+
+    // Global -> registers for the chunk starting at contraction row kk of segment s.
+    auto load = [&](int s, int kk) {
+        const Seg sg = segs[s];
+        const T *A = store + sg.a_off + task.m0;
+        const T *Bp = bufp(sg.b_buf) + sg.b_row * Qp + n0;
+#pragma unroll
+        for (int u = 0; u < A_PER; u++) {
+            const int idx = tid + u * NT;
+            const int kr = idx / A_ROWV, c = (idx % A_ROWV) * VEC;
+            const bool ok = idx < A_VECS && kk + kr < sg.K && task.m0 + c < sg.lda;
+            ra[u] = ok ? *reinterpret_cast<const vec_t *>(A + (int64_t)(kk + kr) * sg.lda + c) : zero;
+        }
+#pragma unroll
+        for (int u = 0; u < B_PER; u++) {
+            const int idx = tid + u * NT;
+            const int kr = idx / B_ROWV, c = (idx % B_ROWV) * VEC;
+            const bool ok = idx < B_VECS && kk + kr < sg.K && n0 + c < Qp;
+            rb[u] = ok ? *reinterpret_cast<const vec_t *>(Bp + (int64_t)(kk + kr) * Qp + c) : zero;
+        }
+    };
+    auto stash = [&](int b) {
+#pragma unroll
+        for (int u = 0; u < A_PER; u++) {
+            const int idx = tid + u * NT;
+            if (idx < A_VECS)
+                *reinterpret_cast<vec_t *>(&As[b][idx / A_ROWV][(idx % A_ROWV) * VEC]) = ra[u];
+        }
+#pragma unroll
+        for (int u = 0; u < B_PER; u++) {
+            const int idx = tid + u * NT;
+            if (idx < B_VECS)
+                *reinterpret_cast<vec_t *>(&Bs[b][idx / B_ROWV][(idx % B_ROWV) * VEC]) = rb[u];
+        }
+    };
+    auto compute = [&](int b) {
+#pragma unroll
+        for (int ks = 0; ks < kBK; ks += 4) {
+            T af[FM], bf[FN];
+            const int kr = ks + (lane >> 4);
+#pragma unroll
+            for (int i = 0; i < FM; i++) af[i] = As[b][kr][wm * WM + i * 16 + (lane & 15)];
+#pragma unroll
+            for (int j = 0; j < FN; j++) bf[j] = Bs[b][kr][wn * WN + j * 16 + (lane & 15)];
+#pragma unroll
+            for (int i = 0; i < FM; i++)
+#pragma unroll
+                for (int j = 0; j < FN; j++) acc[i][j] = M_::mma(af[i], bf[j], acc[i][j]);
+        }
+    };
+
+    if (task.seg_begin < task.seg_end) {
+        int s = task.seg_begin, kk = 0, b = 0;
+        load(s, kk);
+        stash(0);
+        __syncthreads();
+        while (true) {
+            int ns = s, nkk = kk + kBK;
+            if (nkk >= segs[s].K) {
+                ns = s + 1;
+                nkk = 0;
+            }
+            const bool more = ns < task.seg_end;
+            if (more) load(ns, nkk);
+            compute(b);
+            if (more) stash(b ^ 1);
+            __syncthreads();
+            if (!more) break;
+            s = ns;
+            kk = nkk;
+            b ^= 1;
+        }
+    }
+
+    T *out = bufp(task.out_buf) + task.out_row * Qp + n0;
+#pragma unroll
+    for (int i = 0; i < FM; i++)
+#pragma unroll
+        for (int j = 0; j < FN; j++)
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int row = wm * WM + i * 16 + M_::row(lane, r);
+                const int col = wn * WN + j * 16 + (lane & 15);
+                if (row < task.M && n0 + col < Qp) out[(int64_t)row * Qp + col] = acc[i][j][r];
+            }
+}
+
+// Row gather W (original order, leading dimension ldw) -> Wt (tree order, Qp),
+// zero-filling the padding columns; perm == nullptr means identity.
+template <typename T>
+__global__ void k_permute_in(const T *__restrict__ W, int64_t ldw, T *__restrict__ Wt, int64_t Qp,
+                             const int64_t *__restrict__ perm, int64_t N, int64_t Q) {
+    const int64_t total = N * Qp;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t t = e / Qp, c = e % Qp;
+        const int64_t src = perm ? perm[t] : t;
+        Wt[e] = c < Q ? W[src * ldw + c] : T(0);
+    }
+}
+
+// Row scatter Yt (tree order, Qp) -> Y (original order, ldy), first Q columns.
+template <typename T>
+__global__ void k_permute_out(const T *__restrict__ Yt, int64_t Qp, T *__restrict__ Y, int64_t ldy,
+                              const int64_t *__restrict__ perm, int64_t N, int64_t Q) {
+    const int64_t total = N * Q;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t t = e / Q, c = e % Q;
+        const int64_t dst = perm ? perm[t] : t;
+        Y[dst * ldy + c] = Yt[t * Qp + c];
+    }
+}
+
+// Repack one source block per workgroup into the K-major padded store.
+//   mode 0 (transpose): src is rows x cols row-major; dst row t (t < cols)
+//     holds src[:, t] in its first `rows` entries.
+//   mode 1 (slice):     src is rows x cols row-major; dst row t (t < rows)
+//     holds src[t, c0 : c0 + ncols].
+// Entries [valid, ld) of every dst row are zero.
+__global__ void k_repack(const double *__restrict__ stage, const RepackJob *__restrict__ jobs,
+                         double *__restrict__ store) {
+    __shared__ double tile[32][33];
+    const RepackJob j = jobs[blockIdx.x];
+    const double *src = stage + j.src_off;
+    double *dst = store + j.dst_off;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+    if (j.mode == 0) {
+        for (int i0 = 0; i0 < j.ld; i0 += 32)
+            for (int t0 = 0; t0 < j.cols; t0 += 32) {
+                for (int y = ty; y < 32; y += 8) {
+                    const int i = i0 + y, t = t0 + tx;
+                    tile[y][tx] = (i < j.rows && t < j.cols) ? src[(int64_t)i * j.cols + t] : 0.0;
+                }
+                __syncthreads();
+                for (int y = ty; y < 32; y += 8) {
+                    const int t = t0 + y, i = i0 + tx;
+                    if (t < j.cols && i < j.ld) dst[(int64_t)t * j.ld + i] = tile[tx][y];
+                }
+                __syncthreads();
+            }
+    } else {
+        for (int t = ty; t < j.rows; t += 8)
+            for (int i = tx; i < j.ld; i += 32)
+                dst[(int64_t)t * j.ld + i] = i < j.ncols ? src[(int64_t)t * j.cols + j.c0 + i] : 0.0;
+    }
+}
+
+__global__ void k_f64_to_f32(const double *__restrict__ s, float *__restrict__ d, int64_t n) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * blockDim.x)
+        d[e] = (float)s[e];
+}
+
+int grid_for(int64_t work, int block) {
+    int64_t g = (work + block - 1) / block;
+    return (int)std::min<int64_t>(std::max<int64_t>(g, 1), 65536);
+}
+
+template <typename T, int BM, int BN, int WM_, int WN_>
+hipError_t run(const Phase &ph, const hm_matrix_s *h, const T *store, void *const bufs[4],
+               int64_t Qp, hipStream_t s) {
+    dim3 grid((unsigned)ph.task_count, (unsigned)((Qp + BN - 1) / BN));
+    hipLaunchKernelGGL((k_block_products<T, BM, BN, WM_, WN_>), grid, dim3(64 * WM_ * WN_), 0, s,
+                       h->d_tasks, h->d_segs, ph.task_begin, store, (T *)bufs[0], (T *)bufs[1],
+                       (T *)bufs[2], (T *)bufs[3], Qp);
+    return hipGetLastError();
+}
+
+// Column tile from the padded width: the smallest tile that covers Qp, at most 256.
+int pick_bn(int64_t Qp) {
+    if (Qp <= 16) return 16;
+    if (Qp <= 32) return 32;
+    if (Qp <= 64) return 64;
+    if (Qp <= 128) return 128;
+    return 256;
+}
+
+template <typename T>
+hipError_t dispatch(const hm_matrix_s *h, const Phase &ph, int64_t Qp, void *const bufs[4],
+                    hipStream_t s) {
+    const T *store = (const T *)h->prec[sizeof(T) == 8 ? HM_PREC_FP64 : HM_PREC_FP32].blocks;
+    const int bn = pick_bn(Qp);
+    if (ph.bm == 128) {
+        switch (bn) {
+            case 16: return run<T, 128, 16, 4, 1>(ph, h, store, bufs, Qp, s);
+            case 32: return run<T, 128, 32, 4, 1>(ph, h, store, bufs, Qp, s);
+            case 64: return run<T, 128, 64, 2, 2>(ph, h, store, bufs, Qp, s);
+            case 128: return run<T, 128, 128, 2, 2>(ph, h, store, bufs, Qp, s);
+            default: return run<T, 128, 256, 2, 4>(ph, h, store, bufs, Qp, s);
+        }
+    }
+    switch (bn) {
+        case 16: return run<T, 64, 16, 4, 1>(ph, h, store, bufs, Qp, s);
+        case 32: return run<T, 64, 32, 4, 1>(ph, h, store, bufs, Qp, s);
+        case 64: return run<T, 64, 64, 2, 2>(ph, h, store, bufs, Qp, s);
+        case 128: return run<T, 64, 128, 1, 4>(ph, h, store, bufs, Qp, s);
+        default: return run<T, 64, 256, 1, 4>(ph, h, store, bufs, Qp, s);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_phase(const hm_matrix_s *h, const Phase &ph, int elem_bytes, int64_t Qp,
+                        void *const bufs[BUF_COUNT], hipStream_t s) {
+    if (ph.task_count == 0) return hipSuccess;
+    return elem_bytes == 8 ? dispatch<double>(h, ph, Qp, bufs, s) : dispatch<float>(h, ph, Qp, bufs, s);
+}
+
+hipError_t launch_permute_in(const void *W, int64_t ldw, void *Wt, int64_t Qp, const int64_t *perm,
+                             int64_t N, int64_t Q, int elem_bytes, hipStream_t s) {
+    const int g = grid_for(N * Qp, 256);
+    if (elem_bytes == 8)
+        hipLaunchKernelGGL(k_permute_in<double>, dim3(g), dim3(256), 0, s, (const double *)W, ldw,
+                           (double *)Wt, Qp, perm, N, Q);
+    else
+        hipLaunchKernelGGL(k_permute_in<float>, dim3(g), dim3(256), 0, s, (const float *)W, ldw,
+                           (float *)Wt, Qp, perm, N, Q);
+    return hipGetLastError();
+}
+
+hipError_t launch_permute_out(const void *Yt, int64_t Qp, void *Y, int64_t ldy, const int64_t *perm,
+                              int64_t N, int64_t Q, int elem_bytes, hipStream_t s) {
+    const int g = grid_for(N * Q, 256);
+    if (elem_bytes == 8)
+        hipLaunchKernelGGL(k_permute_out<double>, dim3(g), dim3(256), 0, s, (const double *)Yt, Qp,
+                           (double *)Y, ldy, perm, N, Q);
+    else
+        hipLaunchKernelGGL(k_permute_out<float>, dim3(g), dim3(256), 0, s, (const float *)Yt, Qp,
+                           (float *)Y, ldy, perm, N, Q);
+    return hipGetLastError();
+}
+
+hipError_t launch_repack(const double *stage, const RepackJob *jobs, int njobs, double *store,
+                         hipStream_t s) {
+    if (njobs == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_repack, dim3((unsigned)njobs), dim3(256), 0, s, stage, jobs, store);
+    return hipGetLastError();
+}
+
+hipError_t launch_convert_f64_to_f32(const double *src, float *dst, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_f64_to_f32, dim3(grid_for(n, 256)), dim3(256), 0, s, src, dst, n);
+    return hipGetLastError();
+}
+
+}  // namespace hm

@@ -1,0 +1,218 @@
+"""Python binding of libhm (include/hm.h): argument marshalling only.
+
+Every step of the evaluation runs in the HIP kernels of libhm.so; PyTorch is
+used only to hold device memory and to name the stream.  If libhm.so is
+missing the import fails: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhm.so")
+
+HM_OK, HM_ERR_INVALID, HM_ERR_FORMAT, HM_ERR_NOMEM = 0, -1, -2, -3
+HM_ERR_DEVICE, HM_ERR_BUSY, HM_ERR_PENDING, HM_ERR_INTERNAL = -4, -5, -6, -7
+HM_F64, HM_F32 = 0, 1
+HM_PREC_FP64, HM_PREC_FP32 = 0, 1
+HM_TREE_ORDER, HM_PROFILE = 1, 2
+STATUS_NAMES = {0: "HM_OK", -1: "HM_ERR_INVALID", -2: "HM_ERR_FORMAT", -3: "HM_ERR_NOMEM",
+                -4: "HM_ERR_DEVICE", -5: "HM_ERR_BUSY", -6: "HM_ERR_PENDING", -7: "HM_ERR_INTERNAL"}
+
+
+def precbit(p: int) -> int:
+    return 1 << p
+
+
+class HMError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_P = ctypes.c_void_p
+
+
+class hm_host_repr(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int64), ("d", ctypes.c_int64), ("n_nodes", ctypes.c_int32),
+                ("depth", ctypes.c_int32), ("flags", ctypes.c_uint32), ("kernel", ctypes.c_int32),
+                ("h", ctypes.c_double), ("tol", ctypes.c_double), ("tau", ctypes.c_double),
+                ("rmax", ctypes.c_int32), ("m", ctypes.c_int32), ("n_far", ctypes.c_int64),
+                ("n_near", ctypes.c_int64), ("basis_len", ctypes.c_int64), ("B_len", ctypes.c_int64),
+                ("D_len", ctypes.c_int64), ("skel_len", ctypes.c_int64),
+                ("perm", _P), ("start", _P), ("size", _P), ("parent", _P), ("left", _P),
+                ("right", _P), ("level", _P), ("rank", _P), ("basis_off", _P), ("basis", _P),
+                ("far_ptr", _P), ("far_col", _P), ("far_off", _P), ("B", _P), ("near_ptr", _P),
+                ("near_col", _P), ("near_off", _P), ("D", _P), ("skel_ptr", _P), ("skel", _P)]
+
+
+class hm_info_t(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int64), ("n_nodes", ctypes.c_int32), ("depth", ctypes.c_int32),
+                ("max_rank", ctypes.c_int32), ("device", ctypes.c_int32), ("n_far", ctypes.c_int64),
+                ("n_near", ctypes.c_int64), ("E_V", ctypes.c_int64), ("E_T", ctypes.c_int64),
+                ("E_B", ctypes.c_int64), ("E_D", ctypes.c_int64), ("flops_per_col", ctypes.c_double),
+                ("bytes_fp64", ctypes.c_double), ("bytes_fp32", ctypes.c_double),
+                ("n_phases", ctypes.c_int32)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libhm.so is not built ({LIB_PATH}); run paper_1812_07152_amd/build.py")
+    L = ctypes.CDLL(LIB_PATH)
+    st = ctypes.c_int
+    L.hm_last_error.restype = ctypes.c_char_p
+    L.hm_last_error.argtypes = []
+    L.hm_load_compressed.restype = st
+    L.hm_load_compressed.argtypes = [ctypes.c_char_p, ctypes.c_int, ctypes.c_uint, ctypes.POINTER(_P)]
+    L.hm_load_compressed_mem.restype = st
+    L.hm_load_compressed_mem.argtypes = [ctypes.POINTER(hm_host_repr), ctypes.c_int, ctypes.c_uint,
+                                         ctypes.POINTER(_P)]
+    L.hm_info.restype = st
+    L.hm_info.argtypes = [_P, ctypes.POINTER(hm_info_t)]
+    L.hm_free.restype = st
+    L.hm_free.argtypes = [_P]
+    L.hm_eval.restype = st
+    L.hm_eval.argtypes = [_P, _P, ctypes.c_int64, _P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int,
+                          ctypes.c_int, ctypes.c_uint, _P]
+    L.hm_profile_read.restype = st
+    L.hm_profile_read.argtypes = [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+    L.hm_profile_reset.restype = st
+    L.hm_profile_reset.argtypes = [_P]
+    return L
+
+
+lib = _load()
+
+
+def hm_last_error() -> str:
+    return lib.hm_last_error().decode(errors="replace")
+
+
+def _check(status: int) -> None:
+    if status != HM_OK:
+        raise HMError(status, hm_last_error())
+
+
+class Matrix:
+    """Owning wrapper of an hm_matrix handle."""
+
+    def __init__(self, handle: int):
+        self.handle = handle
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            lib.hm_free(self.handle)
+            self.handle = None
+
+    @property
+    def _as_parameter_(self):
+        return self.handle
+
+
+def hm_load_compressed(path: str, device: int = 0,
+                       prec_mask: int = precbit(HM_PREC_FP64)) -> Matrix:
+    out = _P()
+    _check(lib.hm_load_compressed(os.fsencode(path), device, prec_mask, ctypes.byref(out)))
+    return Matrix(out.value)
+
+
+_I64 = ("perm", "start", "size", "basis_off", "far_ptr", "far_off", "near_ptr", "near_off")
+_I32 = ("parent", "left", "right", "level", "rank", "far_col", "near_col")
+_F64 = ("basis", "B", "D")
+
+
+def host_repr(src) -> tuple[hm_host_repr, list]:
+    """Build an hm_host_repr view of an object carrying the representation's
+    arrays as attributes (numpy).  Returns the struct and the arrays it points
+    to (keep them alive until the call returns)."""
+    keep = []
+    r = hm_host_repr()
+
+    def arr(name, dt):
+        a = np.ascontiguousarray(getattr(src, name), dtype=dt)
+        keep.append(a)
+        return a.ctypes.data if a.size else None
+
+    for nme in _I64:
+        setattr(r, nme, arr(nme, np.int64))
+    for nme in _I32:
+        setattr(r, nme, arr(nme, np.int32))
+    for nme in _F64:
+        setattr(r, nme, arr(nme, np.float64))
+    r.N = int(src.N)
+    r.d = int(getattr(src, "d", 0))
+    r.n_nodes = int(src.n_nodes)
+    r.depth = int(np.max(src.level))
+    r.n_far, r.n_near = len(src.far_col), len(src.near_col)
+    r.basis_len, r.B_len, r.D_len = len(src.basis), len(src.B), len(src.D)
+    r.skel_len = 0
+    r.skel_ptr = r.skel = None
+    return r, keep
+
+
+def hm_load_compressed_mem(src, device: int = 0, prec_mask: int = precbit(HM_PREC_FP64)) -> Matrix:
+    r, keep = host_repr(src)
+    out = _P()
+    _check(lib.hm_load_compressed_mem(ctypes.byref(r), device, prec_mask, ctypes.byref(out)))
+    del keep
+    return Matrix(out.value)
+
+
+def hm_info(h: Matrix) -> dict:
+    info = hm_info_t()
+    _check(lib.hm_info(h, ctypes.byref(info)))
+    return {name: getattr(info, name) for name, _ in hm_info_t._fields_}
+
+
+def hm_free(h: Matrix) -> None:
+    if h.handle:
+        _check(lib.hm_free(h.handle))
+        h.handle = None
+
+
+def _stream_ptr(stream) -> int | None:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return getattr(stream, "cuda_stream", stream)
+
+
+def hm_eval(h: Matrix, W, Y, Q: int | None = None, prec: int | None = None, flags: int = 0,
+            stream=None) -> None:
+    """Y = K~ W on the device.  W and Y are CUDA (HIP) tensors, row-major with
+    unit column stride, N x Q (leading dimensions from their row strides)."""
+    import torch
+    if not (W.is_cuda and Y.is_cuda):
+        raise ValueError("hm_eval: W and Y must be device tensors")
+    if W.dtype != Y.dtype or W.dtype not in (torch.float64, torch.float32):
+        raise ValueError("hm_eval: W and Y must both be float64 or both float32")
+    if W.dim() != 2 or Y.dim() != 2 or W.stride(1) != 1 or Y.stride(1) != 1:
+        raise ValueError("hm_eval: W and Y must be 2-D with unit column stride")
+    info = hm_info(h)
+    if W.shape[0] < info["N"] or Y.shape[0] < info["N"]:
+        raise ValueError(f"hm_eval: W and Y need N={info['N']} rows")
+    if W.device.index != info["device"] or Y.device.index != info["device"]:
+        raise ValueError("hm_eval: tensors are not on the matrix's device")
+    dtype = HM_F64 if W.dtype == torch.float64 else HM_F32
+    if prec is None:
+        prec = HM_PREC_FP64 if dtype == HM_F64 else HM_PREC_FP32
+    if Q is None:
+        Q = W.shape[1]
+    if W.shape[1] < Q or Y.shape[1] < Q:
+        raise ValueError("hm_eval: tensors narrower than Q")
+    _check(lib.hm_eval(h, W.data_ptr(), W.stride(0), Y.data_ptr(), Y.stride(0), Q, dtype, prec,
+                       flags, _stream_ptr(stream)))
+
+
+def hm_profile_read(h: Matrix):
+    ms = (ctypes.c_double * 5)()
+    n = (ctypes.c_int64 * 5)()
+    _check(lib.hm_profile_read(h, ms, n))
+    return list(ms), list(n)
+
+
+def hm_profile_reset(h: Matrix) -> None:
+    _check(lib.hm_profile_reset(h))

@@ -1,0 +1,164 @@
+"""GPU parity: libhm's Y = K~ W (through the C ABI) against the CPU FP64
+oracle's tree walk on the same compressed representation and the same seeded
+W.  Bar: relative Frobenius error <= 1e-10 for the FP64 path (the stated
+target), elementwise within 1e-12 of max|Y| (summation order is the only
+difference); FP32 path within 5e-6 relative (single-precision rounding of
+K~ and W accumulated over the block sums, bounded in the design notes)."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle.oracle import OracleH2
+from tests.helpers import rel
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def hmx():
+    assert torch.cuda.is_available(), "GPU test run without a GPU"
+    import paper_1812_07152_amd as hmx
+    return hmx
+
+
+CASES = {
+    "c1": wl.C1,
+    "ragged": wl.small("ragged", N=777, d=2, m=20, Q=3),
+    "mix8": wl.small("mix8", N=3000, d=8, points="mixture", m=50, h=1.0, Q=37),
+    "hss_lap": wl.small("hss_lap", N=2500, d=3, m=70, adm=wl.ADM_HSS, kernel=wl.KERNEL_LAPLACE,
+                        h=2.0, rmax=70, Q=20),
+    "single_node": wl.small("single_node", N=100, d=3, m=128, Q=5),
+    "deep_small_leaves": wl.small("deep", N=2048, d=3, m=8, Q=4, rmax=8),
+}
+_built = {}
+
+
+def built(name):
+    if name not in _built:
+        w = CASES[name]
+        X = wl.gen_points(w)
+        _built[name] = (w, OracleH2.from_workload(w, X))
+    return _built[name]
+
+
+def gpu_eval(hmx, M, W, prec_f64=True, flags=0, Q=None):
+    dt = torch.float64 if prec_f64 else torch.float32
+    Wd = torch.from_numpy(W).to("cuda", dt)
+    Yd = torch.full_like(Wd, float("nan"))
+    hmx.hm_eval(M, Wd, Yd, Q=Q, flags=flags)
+    torch.cuda.synchronize()
+    return Yd.double().cpu().numpy()
+
+
+def check_f64(Y, Yref):
+    assert rel(Y, Yref) <= 1e-10
+    np.testing.assert_allclose(Y, Yref, rtol=0, atol=1e-12 * max(1.0, np.abs(Yref).max()))
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_fp64_parity_file_loader(hmx, tmp_path, name):
+    w, H = built(name)
+    _say(f"[parity] case={name} N={w.N} Q={w.Q} loader=file")
+    path = str(tmp_path / f"{name}.hmc")
+    H.write(path)
+    M = hmx.hm_load_compressed(path, 0, hmx.precbit(hmx.HM_PREC_FP64) | hmx.precbit(hmx.HM_PREC_FP32))
+    info = hmx.hm_info(M)
+    st = H.stats()
+    assert (info["E_V"], info["E_B"], info["E_D"]) == (st["E_V"], st["E_B"], st["E_D"])
+    W = wl.gen_w(w)
+    check_f64(gpu_eval(hmx, M, W), H.eval(W))
+
+
+@pytest.mark.parametrize("name", ["c1", "mix8"])
+def test_fp64_parity_memory_loader_and_q_shapes(hmx, name):
+    w, H = built(name)
+    M = hmx.hm_load_compressed_mem(H, 0)
+    for Q in (1, 2, 15, 16, 17, 33, 100, 256, 300):
+        _say(f"[parity] case={name} Q={Q} loader=mem")
+        W = wl.gen_w(w, Q=Q, seed=100 + Q)
+        check_f64(gpu_eval(hmx, M, W), H.eval(W))
+
+
+def test_fp32_path(hmx):
+    w, H = built("c1")
+    M = hmx.hm_load_compressed_mem(H, 0, hmx.precbit(hmx.HM_PREC_FP32))
+    W = wl.gen_w(w)
+    Y32 = gpu_eval(hmx, M, W, prec_f64=False)
+    Yref = H.eval(W.astype(np.float32).astype(np.float64))
+    assert rel(Y32, Yref) <= 5e-6
+    with pytest.raises(hmx.HMError):  # FP64 was not loaded
+        gpu_eval(hmx, M, W, prec_f64=True)
+
+
+def test_tree_order_flag_and_strided_views(hmx):
+    w, H = built("mix8")
+    M = hmx.hm_load_compressed_mem(H, 0)
+    W = wl.gen_w(w)
+    Yref = H.eval(W)
+    # tree order: W rows permuted by perm, Y returned in tree order
+    Wt = torch.from_numpy(W[H.perm]).cuda()
+    Yt = torch.empty_like(Wt)
+    hmx.hm_eval(M, Wt, Yt, flags=hmx.HM_TREE_ORDER)
+    torch.cuda.synchronize()
+    check_f64(Yt.cpu().numpy(), Yref[H.perm])
+    # strided: W and Y are column slices of wider buffers (ld > Q)
+    big_w = torch.zeros(w.N, w.Q + 11, dtype=torch.float64, device="cuda")
+    big_y = torch.full((w.N, w.Q + 5), 7.0, dtype=torch.float64, device="cuda")
+    big_w[:, 3:3 + w.Q] = torch.from_numpy(W).cuda()
+    hmx.hm_eval(M, big_w[:, 3:], big_y, Q=w.Q)
+    torch.cuda.synchronize()
+    out = big_y.cpu().numpy()
+    check_f64(out[:, :w.Q], Yref)
+    assert np.all(out[:, w.Q:] == 7.0), "columns beyond Q must be untouched"
+
+
+def test_deterministic_and_column_independent(hmx):
+    w, H = built("c1")
+    M = hmx.hm_load_compressed_mem(H, 0)
+    W = wl.gen_w(w)
+    Y1, Y2 = gpu_eval(hmx, M, W), gpu_eval(hmx, M, W)
+    assert np.array_equal(Y1, Y2)
+    Yc = gpu_eval(hmx, M, np.ascontiguousarray(W[:, 5:6]))
+    np.testing.assert_allclose(Yc[:, 0], Y1[:, 5], rtol=0, atol=1e-14 * np.abs(Y1).max())
+
+
+def test_q_zero_and_bad_arguments(hmx):
+    w, H = built("ragged")
+    M = hmx.hm_load_compressed_mem(H, 0)
+    W = torch.zeros(w.N, 4, dtype=torch.float64, device="cuda")
+    Y = torch.zeros_like(W)
+    hmx.hm_eval(M, W, Y, Q=0)      # valid no-op
+    from paper_1812_07152_amd import hm
+    st = hm.lib.hm_eval(M.handle, W.data_ptr(), 4, Y.data_ptr(), 2, 4, hm.HM_F64, hm.HM_PREC_FP64, 0, None)
+    assert st == hm.HM_ERR_INVALID          # ldy < Q
+    st = hm.lib.hm_eval(M.handle, W.data_ptr(), 4, Y.data_ptr(), 4, 4, hm.HM_F32, hm.HM_PREC_FP64, 0, None)
+    assert st == hm.HM_ERR_INVALID          # dtype / precision mismatch
+    st = hm.lib.hm_eval(M.handle, W.data_ptr(), 4, Y.data_ptr(), 4, 4, hm.HM_F64, hm.HM_PREC_FP64, 8, None)
+    assert st == hm.HM_ERR_INVALID          # unknown flag
+
+
+def test_c2_full_size_sampled_columns(hmx):
+    """The headline workload at full size (N=65536, d=8, Q=256) in the launch
+    configuration the benchmark times; the oracle evaluates 6 sampled columns
+    (column j of Y depends only on column j of W)."""
+    w = wl.C2
+    _say("[parity] c2 full size: oracle compression")
+    H = OracleH2.from_workload(w, wl.gen_points(w))
+    M = hmx.hm_load_compressed_mem(H, 0)
+    W = wl.gen_w(w)
+    _say("[parity] c2 full size: gpu eval Q=256")
+    Y = gpu_eval(hmx, M, W)
+    cols = np.random.default_rng(42).choice(w.Q, 6, replace=False)
+    _say("[parity] c2 full size: oracle eval of sampled columns")
+    Yref = H.eval(np.ascontiguousarray(W[:, cols]))
+    check_f64(Y[:, cols], Yref)
