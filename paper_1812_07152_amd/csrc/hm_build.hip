@@ -25,6 +25,10 @@ namespace {
 
 int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
+Seg seg(int64_t a_off, int64_t b_row, int32_t lda, int32_t K, int32_t buf) {
+    return Seg{a_off, b_row, lda, K, buf, (int32_t)round_up(K, 16)};
+}
+
 struct Block {            // one output block of a phase before tiling
     int32_t out_buf;
     int64_t out_row;
@@ -44,10 +48,11 @@ struct Planner {
     std::vector<Seg> segs;
     std::vector<Phase> phases;
 
-    // Reserve a K-major block of `krows` stored rows of `ld` elements.
+    // Reserve a K-major block of `krows` contraction rows (padded with zero
+    // rows to a multiple of 16) of `ld` elements each.
     int64_t alloc(int64_t krows, int64_t ld) {
         int64_t off = store_off;
-        store_off += round_up(krows * ld, 32);  // keep every block 256-byte aligned
+        store_off += round_up(round_up(krows, 16) * ld, 32);  // 256-byte aligned blocks
         return off;
     }
 
@@ -58,7 +63,13 @@ struct Planner {
         ph.level = level;
         int32_t maxM = 0;
         for (const Block &b : blocks) maxM = std::max(maxM, b.M);
-        ph.bm = maxM <= 64 ? 64 : 128;
+        // tile height: the one with less padded work (ties go to 128)
+        double w64 = 0, w128 = 0;
+        for (const Block &b : blocks) {
+            w64 += (double)((b.M + 63) / 64) * 64 * b.work();
+            w128 += (double)((b.M + 127) / 128) * 128 * b.work();
+        }
+        ph.bm = (maxM <= 64 || w64 < w128) ? 64 : 128;
         // longest contraction first: the hardware dispatcher then fills the
         // machine greedily (longest-processing-time order)
         std::stable_sort(blocks.begin(), blocks.end(),
@@ -163,15 +174,23 @@ hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_mat
             if (leaf(a)) {
                 const int32_t m = (int32_t)r.size[a];
                 int64_t off = P.alloc(m, kp);
-                P.jobs[0].push_back({r.basis_off[a], off, k, m, 0, 0, 0, kp});
-                b.segs.push_back({off, r.start[a], kp, m, BUF_WT, 0});
+                P.jobs[0].push_back({r.basis_off[a], off, k, m, 0, 0, m, kp});
+                b.segs.push_back(seg(off, r.start[a], kp, m, BUF_WT));
                 E_V += (int64_t)k * m;
             } else {
+                // T_a's column halves (left / right child skeletons) are stored
+                // as two blocks so that each is zero-padded on its own
                 const int32_t kl = r.rank[r.left[a]], kr = r.rank[r.right[a]];
-                int64_t off = P.alloc(kl + kr, kp);
-                P.jobs[0].push_back({r.basis_off[a], off, k, kl + kr, 0, 0, 0, kp});
-                if (kl > 0) b.segs.push_back({off, wrow[r.left[a]], kp, kl, BUF_WHAT, 0});
-                if (kr > 0) b.segs.push_back({off + (int64_t)kl * kp, wrow[r.right[a]], kp, kr, BUF_WHAT, 0});
+                if (kl > 0) {
+                    int64_t off = P.alloc(kl, kp);
+                    P.jobs[0].push_back({r.basis_off[a], off, k, kl + kr, 0, 0, kl, kp});
+                    b.segs.push_back(seg(off, wrow[r.left[a]], kp, kl, BUF_WHAT));
+                }
+                if (kr > 0) {
+                    int64_t off = P.alloc(kr, kp);
+                    P.jobs[0].push_back({r.basis_off[a], off, k, kl + kr, 0, kl, kr, kp});
+                    b.segs.push_back(seg(off, wrow[r.right[a]], kp, kr, BUF_WHAT));
+                }
                 E_T += (int64_t)k * (kl + kr);
             }
             blocks.push_back(std::move(b));
@@ -191,8 +210,8 @@ hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_mat
                 const int32_t bn = r.far_col[e], kb = r.rank[bn];
                 if (kb == 0) continue;
                 int64_t off = P.alloc(kb, kap);
-                P.jobs[1].push_back({r.far_off[e], off, ka, kb, 0, 0, 0, kap});
-                b.segs.push_back({off, wrow[bn], kap, kb, BUF_WHAT, 0});
+                P.jobs[1].push_back({r.far_off[e], off, ka, kb, 0, 0, kb, kap});
+                b.segs.push_back(seg(off, wrow[bn], kap, kb, BUF_WHAT));
                 E_B += (int64_t)ka * kb;
             }
             const int32_t p = r.parent[a];
@@ -201,7 +220,7 @@ hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_mat
                 const int32_t c0 = (a == r.left[p]) ? 0 : kl;
                 int64_t off = P.alloc(kpar, kap);
                 P.jobs[0].push_back({r.basis_off[p], off, kpar, kl + kr, 1, c0, ka, kap});
-                b.segs.push_back({off, wrow[p], kap, kpar, BUF_YHAT, 0});
+                b.segs.push_back(seg(off, wrow[p], kap, kpar, BUF_YHAT));
             }
             blocks.push_back(std::move(b));
         }
@@ -219,15 +238,15 @@ hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_mat
                 const int32_t bn = r.near_col[e];
                 const int32_t mb = (int32_t)r.size[bn];
                 int64_t off = P.alloc(mb, map);
-                P.jobs[2].push_back({r.near_off[e], off, ma, mb, 0, 0, 0, map});
-                b.segs.push_back({off, r.start[bn], map, mb, BUF_WT, 0});
+                P.jobs[2].push_back({r.near_off[e], off, ma, mb, 0, 0, mb, map});
+                b.segs.push_back(seg(off, r.start[bn], map, mb, BUF_WT));
                 E_D += (int64_t)ma * mb;
             }
             const int32_t k = r.rank[a];
             if (k > 0 && r.level[a] >= 1) {
                 int64_t off = P.alloc(k, map);
                 P.jobs[0].push_back({r.basis_off[a], off, k, ma, 1, 0, ma, map});
-                b.segs.push_back({off, wrow[a], map, k, BUF_YHAT, 0});
+                b.segs.push_back(seg(off, wrow[a], map, k, BUF_YHAT));
             }
             blocks.push_back(std::move(b));
         }
@@ -264,7 +283,8 @@ hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_mat
     h->E_B = E_B;
     h->E_D = E_D;
     h->skel_rows = wrow[n];
-    h->store_elems = std::max<int64_t>(P.store_off, 32);
+    // slack after the last block: a tile taller than its block reads past it
+    h->store_elems = P.store_off + 512;
     h->phases = P.phases;
 
     hipStream_t s = nullptr;

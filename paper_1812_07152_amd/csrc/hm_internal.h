@@ -12,7 +12,8 @@
 namespace hm {
 
 // Workspace buffers the block products read from and write to.  Each is
-// row-major with leading dimension Qp (Q rounded up to a multiple of 16).
+// row-major with leading dimension ldq (Q rounded up to a multiple of the
+// column tile of the evaluation).
 enum Buf : int32_t {
     BUF_WT = 0,    // N x Qp   W in tree order
     BUF_YT = 1,    // N x Qp   Y in tree order
@@ -22,15 +23,16 @@ enum Buf : int32_t {
 };
 
 // One operand pair of a block product: the A block (stored K-major: element
-// (row i, contraction t) at a_off + t*lda + i, zero-padded to lda >= M rows)
-// times K rows of workspace buffer b_buf starting at row b_row.
+// (row i, contraction t) at a_off + t*lda + i, zero-padded to lda >= M rows
+// and to Kpad = round_up(K, 16) contraction rows) times K rows of workspace
+// buffer b_buf starting at row b_row.
 struct Seg {
     int64_t a_off;  // element offset into the block store
     int64_t b_row;
     int32_t lda;    // padded row count of the A block (multiple of 16)
     int32_t K;      // contraction length (> 0)
     int32_t b_buf;
-    int32_t pad_;
+    int32_t Kpad;   // stored contraction rows (multiple of 16)
 };
 
 // One output block: rows [out_row, out_row + M) of buffer out_buf (M <= tile
@@ -135,7 +137,9 @@ hm_status validate(const HostRepr &r);
 hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_matrix *out);
 
 // Kernel launchers (hm_kernels.hip).
-hipError_t launch_phase(const hm_matrix_s *h, const Phase &ph, int elem_bytes, int64_t Qp,
+// Column tile for Q columns (16..256), honouring HM_BN if set.
+int pick_bn(int64_t Q);
+hipError_t launch_phase(const hm_matrix_s *h, const Phase &ph, int elem_bytes, int bn, int64_t ldq,
                         void *const bufs[BUF_COUNT], hipStream_t s);
 hipError_t launch_permute_in(const void *W, int64_t ldw, void *Wt, int64_t Qp, const int64_t *perm,
                              int64_t N, int64_t Q, int elem_bytes, hipStream_t s);

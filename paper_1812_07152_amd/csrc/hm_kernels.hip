@@ -19,6 +19,8 @@
 // chunk).  Lane mapping of the 16x16x4 MFMAs (checked on the device): lane l
 // supplies A[l%16][l/16] and B[l/16][l%16]; accumulator register r of lane l
 // holds D[4r + l/16][l%16] for FP64 and D[4(l/16) + r][l%16] for FP32.
+#include <cstdlib>
+
 #include "hm_internal.h"
 
 namespace hm {
@@ -27,6 +29,9 @@ namespace {
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
+// 16-byte staging vectors as native clang vectors (the HIP double2/float4
+// wrapper structs keep register arrays of them in scratch memory)
+typedef double d2_t __attribute__((ext_vector_type(2)));
 
 template <typename T>
 struct Mfma;
@@ -34,7 +39,7 @@ struct Mfma;
 template <>
 struct Mfma<double> {
     typedef d4_t acc_t;
-    typedef double2 vec_t;  // 16 bytes
+    typedef d2_t vec_t;  // 16 bytes
     static constexpr int kVec = 2;
     static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -45,7 +50,7 @@ struct Mfma<double> {
 template <>
 struct Mfma<float> {
     typedef f4_t acc_t;
-    typedef float4 vec_t;
+    typedef f4_t vec_t;
     static constexpr int kVec = 4;
     static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
@@ -54,11 +59,22 @@ struct Mfma<float> {
 };
 
 constexpr int kBK = 16;
+// LDS rows are padded by 128 bytes so that the four 16-lane groups of a
+// fragment read land on alternating bank halves.
+template <typename T>
+constexpr int lds_pad() { return 128 / (int)sizeof(T); }
 
+// Invariants the host guarantees (so that no load needs a bounds check and
+// the compiler never has to wait for a load before the MFMAs of the current
+// chunk):
+//   - every stored A block has Kpad = round_up(K, 16) rows (zero beyond K) and
+//     the store has slack after its last block for the row over-read of a
+//     tile taller than the block;
+//   - workspaces have leading dimension ldq, a multiple of BN.
 template <typename T, int BM, int BN, int WAVES_M, int WAVES_N>
 __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void k_block_products(
     const Task *__restrict__ tasks, const Seg *__restrict__ segs, int task_begin,
-    const T *__restrict__ store, T *buf0, T *buf1, T *buf2, T *buf3, int64_t Qp) {
+    const T *__restrict__ store, T *buf0, T *buf1, T *buf2, T *buf3, int64_t ldq) {
     using M_ = Mfma<T>;
     using acc_t = typename M_::acc_t;
     using vec_t = typename M_::vec_t;
@@ -69,17 +85,17 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void k_block_products(
     constexpr int A_ROWV = BM / VEC, B_ROWV = BN / VEC;        // vectors per chunk row
     constexpr int A_VECS = kBK * A_ROWV, B_VECS = kBK * B_ROWV;
     constexpr int A_PER = (A_VECS + NT - 1) / NT, B_PER = (B_VECS + NT - 1) / NT;
+    constexpr int LA = BM + lds_pad<T>(), LB = BN + lds_pad<T>();
     static_assert(FM >= 1 && FN >= 1 && WM % 16 == 0 && WN % 16 == 0, "bad tile");
 
-    __shared__ __attribute__((aligned(16))) T As[2][kBK][BM];
-    __shared__ __attribute__((aligned(16))) T Bs[2][kBK][BN];
+    __shared__ __attribute__((aligned(16))) T As[2][kBK][LA];
+    __shared__ __attribute__((aligned(16))) T Bs[2][kBK][LB];
 
     const Task task = tasks[task_begin + blockIdx.x];
     const int64_t n0 = (int64_t)blockIdx.y * BN;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave / WAVES_N, wn = wave % WAVES_N;
-    // buffer select without a dynamically indexed private array (which the
-    // compiler would otherwise place in LDS)
+    // buffer select without a dynamically indexed private array
     auto bufp = [&](int b) { return b == 0 ? buf0 : b == 1 ? buf1 : b == 2 ? buf2 : buf3; };
 
     acc_t acc[FM][FN];
@@ -89,39 +105,37 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void k_block_products(
         for (int j = 0; j < FN; j++) acc[i][j] = acc_t{0, 0, 0, 0};
 
     vec_t ra[A_PER], rb[B_PER];
-    const vec_t zero = {};
 
-    // Global -> registers for the chunk starting at contraction row kk of segment s.
-    auto load = [&](int s, int kk) {
-        const Seg sg = segs[s];
-        const T *A = store + sg.a_off + task.m0;
-        const T *Bp = bufp(sg.b_buf) + sg.b_row * Qp + n0;
+    // Global -> registers for the chunk at contraction row kk of segment sg.
+    // Unconditional loads: thread slots beyond the chunk re-load its last
+    // vector, B rows beyond K re-load row K-1 (multiplied by zero rows of A).
+    auto load = [&](const Seg &sg, int kk) {
+        const T *A = store + sg.a_off + task.m0 + (int64_t)kk * sg.lda;
+        const T *Bp = bufp(sg.b_buf) + (sg.b_row) * ldq + n0;
 #pragma unroll
         for (int u = 0; u < A_PER; u++) {
-            const int idx = tid + u * NT;
+            const int idx = min(tid + u * NT, A_VECS - 1);
             const int kr = idx / A_ROWV, c = (idx % A_ROWV) * VEC;
-            const bool ok = idx < A_VECS && kk + kr < sg.K && task.m0 + c < sg.lda;
-            ra[u] = ok ? *reinterpret_cast<const vec_t *>(A + (int64_t)(kk + kr) * sg.lda + c) : zero;
+            ra[u] = *reinterpret_cast<const vec_t *>(A + (int64_t)kr * sg.lda + c);
         }
 #pragma unroll
         for (int u = 0; u < B_PER; u++) {
-            const int idx = tid + u * NT;
-            const int kr = idx / B_ROWV, c = (idx % B_ROWV) * VEC;
-            const bool ok = idx < B_VECS && kk + kr < sg.K && n0 + c < Qp;
-            rb[u] = ok ? *reinterpret_cast<const vec_t *>(Bp + (int64_t)(kk + kr) * Qp + c) : zero;
+            const int idx = min(tid + u * NT, B_VECS - 1);
+            const int kr = min(kk + idx / B_ROWV, sg.K - 1), c = (idx % B_ROWV) * VEC;
+            rb[u] = *reinterpret_cast<const vec_t *>(Bp + (int64_t)kr * ldq + c);
         }
     };
     auto stash = [&](int b) {
 #pragma unroll
         for (int u = 0; u < A_PER; u++) {
             const int idx = tid + u * NT;
-            if (idx < A_VECS)
+            if (A_VECS % NT == 0 || idx < A_VECS)
                 *reinterpret_cast<vec_t *>(&As[b][idx / A_ROWV][(idx % A_ROWV) * VEC]) = ra[u];
         }
 #pragma unroll
         for (int u = 0; u < B_PER; u++) {
             const int idx = tid + u * NT;
-            if (idx < B_VECS)
+            if (B_VECS % NT == 0 || idx < B_VECS)
                 *reinterpret_cast<vec_t *>(&Bs[b][idx / B_ROWV][(idx % B_ROWV) * VEC]) = rb[u];
         }
     };
@@ -143,28 +157,32 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void k_block_products(
 
     if (task.seg_begin < task.seg_end) {
         int s = task.seg_begin, kk = 0, b = 0;
-        load(s, kk);
+        Seg sg = segs[s];
+        load(sg, 0);
         stash(0);
         __syncthreads();
         while (true) {
-            int ns = s, nkk = kk + kBK;
-            if (nkk >= segs[s].K) {
+            int nkk = kk + kBK, ns = s;
+            Seg nsg = sg;
+            if (nkk >= sg.Kpad) {
                 ns = s + 1;
                 nkk = 0;
+                if (ns < task.seg_end) nsg = segs[ns];
             }
             const bool more = ns < task.seg_end;
-            if (more) load(ns, nkk);
+            load(nsg, more ? nkk : kk);  // on the last chunk: a harmless re-load
             compute(b);
-            if (more) stash(b ^ 1);
+            stash(b ^ 1);
             __syncthreads();
             if (!more) break;
             s = ns;
             kk = nkk;
+            sg = nsg;
             b ^= 1;
         }
     }
 
-    T *out = bufp(task.out_buf) + task.out_row * Qp + n0;
+    T *out = bufp(task.out_buf) + task.out_row * ldq + n0;
 #pragma unroll
     for (int i = 0; i < FM; i++)
 #pragma unroll
@@ -173,7 +191,7 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void k_block_products(
             for (int r = 0; r < 4; r++) {
                 const int row = wm * WM + i * 16 + M_::row(lane, r);
                 const int col = wn * WN + j * 16 + (lane & 15);
-                if (row < task.M && n0 + col < Qp) out[(int64_t)row * Qp + col] = acc[i][j][r];
+                if (row < task.M) out[(int64_t)row * ldq + col] = acc[i][j][r];
             }
 }
 
@@ -205,11 +223,12 @@ __global__ void k_permute_out(const T *__restrict__ Yt, int64_t Qp, T *__restric
 }
 
 // Repack one source block per workgroup into the K-major padded store.
-//   mode 0 (transpose): src is rows x cols row-major; dst row t (t < cols)
-//     holds src[:, t] in its first `rows` entries.
+//   mode 0 (transpose): src is rows x cols row-major; dst row t (t < ncols)
+//     holds src[:, c0 + t] in its first `rows` entries.
 //   mode 1 (slice):     src is rows x cols row-major; dst row t (t < rows)
 //     holds src[t, c0 : c0 + ncols].
-// Entries [valid, ld) of every dst row are zero.
+// Entries [valid, ld) of every dst row are zero; rows beyond the ones written
+// keep the zeros the store was cleared with.
 __global__ void k_repack(const double *__restrict__ stage, const RepackJob *__restrict__ jobs,
                          double *__restrict__ store) {
     __shared__ double tile[32][33];
@@ -219,15 +238,15 @@ __global__ void k_repack(const double *__restrict__ stage, const RepackJob *__re
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
     if (j.mode == 0) {
         for (int i0 = 0; i0 < j.ld; i0 += 32)
-            for (int t0 = 0; t0 < j.cols; t0 += 32) {
+            for (int t0 = 0; t0 < j.ncols; t0 += 32) {
                 for (int y = ty; y < 32; y += 8) {
                     const int i = i0 + y, t = t0 + tx;
-                    tile[y][tx] = (i < j.rows && t < j.cols) ? src[(int64_t)i * j.cols + t] : 0.0;
+                    tile[y][tx] = (i < j.rows && t < j.ncols) ? src[(int64_t)i * j.cols + j.c0 + t] : 0.0;
                 }
                 __syncthreads();
                 for (int y = ty; y < 32; y += 8) {
                     const int t = t0 + y, i = i0 + tx;
-                    if (t < j.cols && i < j.ld) dst[(int64_t)t * j.ld + i] = tile[tx][y];
+                    if (t < j.ncols && i < j.ld) dst[(int64_t)t * j.ld + i] = tile[tx][y];
                 }
                 __syncthreads();
             }
@@ -251,52 +270,55 @@ int grid_for(int64_t work, int block) {
 
 template <typename T, int BM, int BN, int WM_, int WN_>
 hipError_t run(const Phase &ph, const hm_matrix_s *h, const T *store, void *const bufs[4],
-               int64_t Qp, hipStream_t s) {
-    dim3 grid((unsigned)ph.task_count, (unsigned)((Qp + BN - 1) / BN));
+               int64_t ldq, hipStream_t s) {
+    dim3 grid((unsigned)ph.task_count, (unsigned)(ldq / BN));
     hipLaunchKernelGGL((k_block_products<T, BM, BN, WM_, WN_>), grid, dim3(64 * WM_ * WN_), 0, s,
                        h->d_tasks, h->d_segs, ph.task_begin, store, (T *)bufs[0], (T *)bufs[1],
-                       (T *)bufs[2], (T *)bufs[3], Qp);
+                       (T *)bufs[2], (T *)bufs[3], ldq);
     return hipGetLastError();
 }
 
-// Column tile from the padded width: the smallest tile that covers Qp, at most 256.
-int pick_bn(int64_t Qp) {
-    if (Qp <= 16) return 16;
-    if (Qp <= 32) return 32;
-    if (Qp <= 64) return 64;
-    if (Qp <= 128) return 128;
-    return 256;
-}
-
 template <typename T>
-hipError_t dispatch(const hm_matrix_s *h, const Phase &ph, int64_t Qp, void *const bufs[4],
-                    hipStream_t s) {
+hipError_t dispatch(const hm_matrix_s *h, const Phase &ph, int bn, int64_t ldq,
+                    void *const bufs[4], hipStream_t s) {
     const T *store = (const T *)h->prec[sizeof(T) == 8 ? HM_PREC_FP64 : HM_PREC_FP32].blocks;
-    const int bn = pick_bn(Qp);
     if (ph.bm == 128) {
         switch (bn) {
-            case 16: return run<T, 128, 16, 4, 1>(ph, h, store, bufs, Qp, s);
-            case 32: return run<T, 128, 32, 4, 1>(ph, h, store, bufs, Qp, s);
-            case 64: return run<T, 128, 64, 2, 2>(ph, h, store, bufs, Qp, s);
-            case 128: return run<T, 128, 128, 2, 2>(ph, h, store, bufs, Qp, s);
-            default: return run<T, 128, 256, 2, 4>(ph, h, store, bufs, Qp, s);
+            case 16: return run<T, 128, 16, 4, 1>(ph, h, store, bufs, ldq, s);
+            case 32: return run<T, 128, 32, 4, 1>(ph, h, store, bufs, ldq, s);
+            case 64: return run<T, 128, 64, 2, 2>(ph, h, store, bufs, ldq, s);
+            case 128: return run<T, 128, 128, 2, 2>(ph, h, store, bufs, ldq, s);
+            default: return run<T, 128, 256, 2, 4>(ph, h, store, bufs, ldq, s);
         }
     }
     switch (bn) {
-        case 16: return run<T, 64, 16, 4, 1>(ph, h, store, bufs, Qp, s);
-        case 32: return run<T, 64, 32, 4, 1>(ph, h, store, bufs, Qp, s);
-        case 64: return run<T, 64, 64, 2, 2>(ph, h, store, bufs, Qp, s);
-        case 128: return run<T, 64, 128, 1, 4>(ph, h, store, bufs, Qp, s);
-        default: return run<T, 64, 256, 1, 4>(ph, h, store, bufs, Qp, s);
+        case 16: return run<T, 64, 16, 4, 1>(ph, h, store, bufs, ldq, s);
+        case 32: return run<T, 64, 32, 4, 1>(ph, h, store, bufs, ldq, s);
+        case 64: return run<T, 64, 64, 2, 2>(ph, h, store, bufs, ldq, s);
+        case 128: return run<T, 64, 128, 1, 4>(ph, h, store, bufs, ldq, s);
+        default: return run<T, 64, 256, 1, 4>(ph, h, store, bufs, ldq, s);
     }
 }
 
 }  // namespace
 
-hipError_t launch_phase(const hm_matrix_s *h, const Phase &ph, int elem_bytes, int64_t Qp,
+int pick_bn(int64_t Q) {
+    if (const char *e = std::getenv("HM_BN")) {
+        int v = std::atoi(e);
+        if (v == 16 || v == 32 || v == 64 || v == 128 || v == 256) return v;
+    }
+    if (Q <= 16) return 16;
+    if (Q <= 32) return 32;
+    if (Q <= 64) return 64;
+    if (Q <= 128) return 128;
+    return 256;
+}
+
+hipError_t launch_phase(const hm_matrix_s *h, const Phase &ph, int elem_bytes, int bn, int64_t ldq,
                         void *const bufs[BUF_COUNT], hipStream_t s) {
     if (ph.task_count == 0) return hipSuccess;
-    return elem_bytes == 8 ? dispatch<double>(h, ph, Qp, bufs, s) : dispatch<float>(h, ph, Qp, bufs, s);
+    return elem_bytes == 8 ? dispatch<double>(h, ph, bn, ldq, bufs, s)
+                           : dispatch<float>(h, ph, bn, ldq, bufs, s);
 }
 
 hipError_t launch_permute_in(const void *W, int64_t ldw, void *Wt, int64_t Qp, const int64_t *perm,
