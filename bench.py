@@ -1,0 +1,178 @@
+"""Benchmark: Y = K~ W on one MI355X for the headline workload (N = 65536
+points in d = 8 from a 16-component Gaussian mixture, Gaussian kernel h = 1,
+leaf 128, tol 1e-5, rank <= 128, distance admissibility tau = 2, W: N x 256).
+
+One step = one full evaluation (permute-in, up pass, far reduction + down
+pass, near field + leaf far part, permute-out) on inputs resident in HBM.
+Prints one JSON line.  Throughput counts algorithmic flops only:
+2 Q (2 E_V + 2 E_T + E_B + E_D), never the dense 2 N^2 Q.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 (vector = matrix)
+PEAK_FP32_TFLOPS = 157.3    # MI355X dense FP32
+PEAK_HBM_GBPS = 8000.0
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("hm_kernels.hip", "hm_build.hip"):
+        h.update(open(os.path.join(ROOT, "paper_1812_07152_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(name: str, launches_bytes_fallback=None):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary, if it was taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", f"{name}.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def time_variant(hmx, torch, M, w, dtype, steps, warmup):
+    W = torch.from_numpy(__import__("workloads").gen_w(w)).to("cuda", dtype)
+    Y = torch.empty_like(W)
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        hmx.hm_eval(M, W, Y, stream=stream)
+    torch.cuda.synchronize()
+    hmx.hm_profile_reset(M)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        hmx.hm_eval(M, W, Y, flags=hmx.HM_PROFILE, stream=stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms, n = hmx.hm_profile_read(M)
+    return (t1 - t0) * 1e3 / steps, ms, n
+
+
+def cpu_baseline(w, budget_s: float = 15.0):
+    """The oracle (plain C, FP64, OpenMP over nodes) on a bounded column sample
+    of the same workload: its own compression (untimed), then the timed tree
+    walk on Qs of the Q columns, Qs chosen for roughly budget_s seconds."""
+    import numpy as np
+
+    import workloads as wl
+    from oracle import oracle as orc
+    H = orc.OracleH2.from_workload(w, wl.gen_points(w))
+    st = H.stats()
+    probe_q = 4
+    t = time.perf_counter()
+    H.eval(np.ascontiguousarray(wl.gen_w(w, Q=probe_q)))
+    per_col = (time.perf_counter() - t) / probe_q
+    qs = int(max(probe_q, min(w.Q, budget_s / max(per_col, 1e-9))))
+    Ws = np.ascontiguousarray(wl.gen_w(w, Q=qs))
+    t = time.perf_counter()
+    H.eval(Ws)
+    dt = time.perf_counter() - t
+    return {"value": st["flops_per_col"] * qs / dt / 1e9, "unit": "GFLOP/s",
+            "cores": orc.max_threads(), "kind": "oracle",
+            "sample": f"same compressed workload, {qs} of the {w.Q} columns of W "
+                      f"({dt:.1f} s timed tree walk)",
+            "seconds": dt}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="after timing, run one device copy of this many MiB (a kernel of "
+                         "known traffic for calibrating HBM counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
+              "(the path shards by columns of W with no exchange, see the design notes)",
+              file=sys.stderr)
+        return 2
+
+    import torch
+
+    import paper_1812_07152_amd as hmx
+    import workloads as wl
+
+    w = wl.C2
+    X = wl.gen_points(w)
+    t = time.perf_counter()
+    R = hmx.hm_compress(X, kernel=w.kernel, h=w.h, leaf_size=w.m, tol=w.tol, max_rank=w.rmax,
+                        admissibility=w.adm, tau=w.tau, sample_rows=w.sample_rows, seed=w.sample_seed)
+    t_compress = time.perf_counter() - t
+    precs = hmx.precbit(hmx.HM_PREC_FP64) | (0 if args.no_fp32 else hmx.precbit(hmx.HM_PREC_FP32))
+    t = time.perf_counter()
+    M = hmx.hm_load_compressed_mem(R, 0, precs)
+    t_load = time.perf_counter() - t
+    info = hmx.hm_info(M)
+    del R
+    flops = info["flops_per_col"] * w.Q
+    leaf_flops = 2.0 * w.Q * (info["E_D"] + info["E_V"])
+
+    ms64, ph64, n64 = time_variant(hmx, torch, M, w, torch.float64, args.steps, args.warmup)
+    leaf_ms = ph64[3] / max(n64[3], 1)
+    achieved = leaf_flops / (leaf_ms * 1e-3) / 1e12
+    traffic = measured_traffic("leaf_pass_c2_fp64")
+
+    out = {
+        "metric": "K~W GFLOP/s (algorithmic) and % of FP64 roofline",
+        "value": flops / (ms64 * 1e-3) / 1e9,
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms64,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded Gaussian-mixture points and normal W; no dataset)",
+        "config": {"workload": w.name, "N": w.N, "d": w.d, "Q": w.Q, "kernel": "gaussian",
+                   "h": w.h, "leaf": w.m, "tol": w.tol, "max_rank": w.rmax,
+                   "admissibility": f"distance tau={w.tau}", "n_near_pairs": info["n_near"],
+                   "n_far_pairs": info["n_far"], "gflop_per_step": flops / 1e9},
+        "roofline": {"bound": "mfma", "kernel": "k_block_products (leaf pass: near field + leaf far part)",
+                     "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
+                     "launch_ms": leaf_ms, "algorithmic_gflop_per_launch": leaf_flops / 1e9},
+        "whole_step_frac_of_fp64_peak": flops / (ms64 * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
+        "phase_ms": {k: ph64[i] / max(n64[i], 1) for i, k in
+                     enumerate(("permute_in", "up", "down", "leaf", "permute_out"))},
+        "setup_s": {"compress": t_compress, "load": t_load},
+    }
+    if not args.no_fp32:
+        ms32, ph32, n32 = time_variant(hmx, torch, M, w, torch.float32, args.steps, args.warmup)
+        out["fp32"] = {"ms_per_step": ms32, "value": flops / (ms32 * 1e-3) / 1e9, "unit": "GFLOP/s",
+                       "frac_of_fp32_peak": flops / (ms32 * 1e-3) / 1e12 / PEAK_FP32_TFLOPS}
+    del M
+    if args.calib_copy_mib:
+        src = torch.ones(args.calib_copy_mib << 17, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calib_copy_bytes"] = {"read": src.numel() * 8, "write": dst.numel() * 8}
+        del src, dst
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

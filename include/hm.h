@@ -152,6 +152,44 @@ hm_status hm_eval(hm_matrix h, const void *W, int64_t ldw, void *Y, int64_t ldy,
 hm_status hm_profile_read(hm_matrix h, double ms[5], int64_t launches[5]);
 hm_status hm_profile_reset(hm_matrix h);
 
+/* ---------------------------------------------------------------------------
+ * Inspector: host-side compression of a point set into the representation
+ * above (the compression phase of the paper, Section 3.1: tree construction,
+ * interaction computation, sampling, ID low-rank approximation).  Runs on the
+ * host CPU threads; its output feeds hm_load_compressed_mem.  Readings of the
+ * steps the paper leaves open: a perfect binary tree cut at the median of the
+ * widest coordinate; far iff tau * centroid distance > diam(a) + diam(b)
+ * (diam = twice the largest distance to the centroid), or every off-diagonal
+ * pair for HSS; ID rows = the whole far field when it has at most sample_rows
+ * points, otherwise half from the nearest far clusters and half by a seeded
+ * SplitMix64 key; pivoted-QR ID with rank = first j with |R_jj| <= tol |R_11|,
+ * capped at max_rank. */
+typedef struct {
+    int32_t kernel;         /* 0: exp(-|x-y|^2 / (2 h^2)), 1: exp(-|x-y| / h) */
+    double h;               /* bandwidth (> 0) */
+    int32_t leaf_size;      /* m >= 2: leaves hold at most m points */
+    double tol;             /* ID tolerance relative to |R_11| (>= 0) */
+    int32_t max_rank;       /* rank cap */
+    int32_t admissibility;  /* 0 distance (uses tau), 1 HSS */
+    double tau;
+    int64_t sample_rows;    /* row-sample cap S of each ID */
+    uint64_t seed;          /* sample seed */
+    int32_t threads;        /* host threads (0 = all hardware threads) */
+} hm_compress_opts;
+
+typedef struct hm_repr_s *hm_repr;  /* library-owned host representation */
+
+/* Compress X (N x d, row-major FP64, host memory, read only during the call).
+ * HM_ERR_INVALID for bad options or non-finite coordinates. */
+hm_status hm_compress(const double *X, int64_t N, int64_t d, const hm_compress_opts *opts,
+                      hm_repr *out);
+/* Fill *view with pointers into r (valid until hm_repr_free(r)). */
+hm_status hm_repr_view(hm_repr r, hm_host_repr *view);
+/* Write r as an HMC1 file (the format hm_load_compressed reads). */
+hm_status hm_repr_write(hm_repr r, const char *path);
+/* Release r (NULL accepted). */
+hm_status hm_repr_free(hm_repr r);
+
 /* Message for the last non-OK status returned on this thread. */
 const char *hm_last_error(void);
 

@@ -160,8 +160,9 @@ hm_status hm_eval(hm_matrix h, const void *W, int64_t ldw, void *Y, int64_t ldy,
     if (ds.err != hipSuccess) return fail(HM_ERR_DEVICE, "hm_eval: cannot select the device");
     hipStream_t s = (hipStream_t)stream;
     const int es = dtype == HM_F64 ? 8 : 4, slot = dtype == HM_F64 ? 0 : 1;
-    const int bn = pick_bn(Q);
-    const int64_t Qp = (Q + bn - 1) / bn * bn;  // workspace leading dimension
+    int bn_kind[4] = {0, pick_bn(Q, 1), pick_bn(Q, 2), pick_bn(Q, 3)};
+    const int bn_max = std::max({bn_kind[1], bn_kind[2], bn_kind[3]});
+    const int64_t Qp = (Q + bn_max - 1) / bn_max * bn_max;  // workspace leading dimension
     const size_t rows[BUF_COUNT] = {(size_t)h->N, (size_t)h->N, (size_t)h->skel_rows,
                                     (size_t)h->skel_rows};
     for (int b = 0; b < BUF_COUNT; b++) {
@@ -196,7 +197,7 @@ hm_status hm_eval(hm_matrix h, const void *W, int64_t ldw, void *Y, int64_t ldy,
             if ((st = mark(g, true)) != HM_OK) return st;
             open_group = g;
         }
-        HM_HIP(launch_phase(h, ph, es, bn, Qp, bufs, s));
+        HM_HIP(launch_phase(h, ph, es, bn_kind[ph.kind], Qp, bufs, s));
     }
     if (open_group >= 0 && (st = mark(open_group, false)) != HM_OK) return st;
     if ((st = mark(4, true)) != HM_OK) return st;

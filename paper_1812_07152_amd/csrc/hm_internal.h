@@ -137,8 +137,10 @@ hm_status validate(const HostRepr &r);
 hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_matrix *out);
 
 // Kernel launchers (hm_kernels.hip).
-// Column tile for Q columns (16..256), honouring HM_BN if set.
-int pick_bn(int64_t Q);
+// Column tile for Q columns (16..256) in a phase of the given kind (1 up,
+// 2 down, 3 leaf), honouring the HM_BN_UP / HM_BN_DOWN / HM_BN_LEAF / HM_BN
+// environment overrides.
+int pick_bn(int64_t Q, int kind);
 hipError_t launch_phase(const hm_matrix_s *h, const Phase &ph, int elem_bytes, int bn, int64_t ldq,
                         void *const bufs[BUF_COUNT], hipStream_t s);
 hipError_t launch_permute_in(const void *W, int64_t ldw, void *Wt, int64_t Qp, const int64_t *perm,

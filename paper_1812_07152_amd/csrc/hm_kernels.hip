@@ -302,11 +302,13 @@ hipError_t dispatch(const hm_matrix_s *h, const Phase &ph, int bn, int64_t ldq,
 
 }  // namespace
 
-int pick_bn(int64_t Q) {
-    if (const char *e = std::getenv("HM_BN")) {
-        int v = std::atoi(e);
-        if (v == 16 || v == 32 || v == 64 || v == 128 || v == 256) return v;
-    }
+int pick_bn(int64_t Q, int kind) {
+    static const char *names[4] = {"HM_BN", "HM_BN_UP", "HM_BN_DOWN", "HM_BN_LEAF"};
+    for (const char *nm : {names[kind >= 1 && kind <= 3 ? kind : 0], names[0]})
+        if (const char *e = std::getenv(nm)) {
+            int v = std::atoi(e);
+            if (v == 16 || v == 32 || v == 64 || v == 128 || v == 256) return v;
+        }
     if (Q <= 16) return 16;
     if (Q <= 32) return 32;
     if (Q <= 64) return 64;

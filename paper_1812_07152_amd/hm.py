@@ -49,6 +49,14 @@ class hm_host_repr(ctypes.Structure):
                 ("near_col", _P), ("near_off", _P), ("D", _P), ("skel_ptr", _P), ("skel", _P)]
 
 
+class hm_compress_opts(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_int32), ("h", ctypes.c_double), ("leaf_size", ctypes.c_int32),
+                ("tol", ctypes.c_double), ("max_rank", ctypes.c_int32),
+                ("admissibility", ctypes.c_int32), ("tau", ctypes.c_double),
+                ("sample_rows", ctypes.c_int64), ("seed", ctypes.c_uint64),
+                ("threads", ctypes.c_int32)]
+
+
 class hm_info_t(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int64), ("n_nodes", ctypes.c_int32), ("depth", ctypes.c_int32),
                 ("max_rank", ctypes.c_int32), ("device", ctypes.c_int32), ("n_far", ctypes.c_int64),
@@ -81,6 +89,15 @@ def _load():
     L.hm_profile_read.argtypes = [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     L.hm_profile_reset.restype = st
     L.hm_profile_reset.argtypes = [_P]
+    L.hm_compress.restype = st
+    L.hm_compress.argtypes = [_P, ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(hm_compress_opts),
+                              ctypes.POINTER(_P)]
+    L.hm_repr_view.restype = st
+    L.hm_repr_view.argtypes = [_P, ctypes.POINTER(hm_host_repr)]
+    L.hm_repr_write.restype = st
+    L.hm_repr_write.argtypes = [_P, ctypes.c_char_p]
+    L.hm_repr_free.restype = st
+    L.hm_repr_free.argtypes = [_P]
     return L
 
 
@@ -153,7 +170,67 @@ def host_repr(src) -> tuple[hm_host_repr, list]:
     return r, keep
 
 
+class Repr:
+    """Host representation owned by libhm (output of hm_compress).  Its arrays
+    are exposed as zero-copy numpy views, valid while the object lives."""
+
+    def __init__(self, handle: int):
+        self.handle = handle
+        v = hm_host_repr()
+        _check(lib.hm_repr_view(handle, ctypes.byref(v)))
+        self._view = v
+        for k in ("N", "d", "n_nodes", "depth", "n_far", "n_near"):
+            setattr(self, k, getattr(v, k))
+        n = v.n_nodes
+
+        def arr(ptr, ctype, count):
+            if count == 0 or not ptr:
+                return np.zeros(0, np.ctypeslib.as_ctypes_type(ctype))
+            return np.ctypeslib.as_array((np.ctypeslib.as_ctypes_type(ctype) * count).from_address(ptr))
+
+        sizes = dict(perm=v.N, start=n, size=n, basis_off=n, far_ptr=n + 1, far_off=v.n_far,
+                     near_ptr=n + 1, near_off=v.n_near, parent=n, left=n, right=n, level=n, rank=n,
+                     far_col=v.n_far, near_col=v.n_near, basis=v.basis_len, B=v.B_len, D=v.D_len,
+                     skel_ptr=n + 1, skel=v.skel_len)
+        for k, cnt in sizes.items():
+            dt = np.int64 if k in _I64 or k in ("skel_ptr", "skel") else np.int32 if k in _I32 else np.float64
+            setattr(self, k, arr(getattr(v, k), dt, cnt))
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            lib.hm_repr_free(self.handle)
+            self.handle = None
+
+    def write(self, path: str) -> None:
+        _check(lib.hm_repr_write(self.handle, os.fsencode(path)))
+
+
+def hm_compress(X: np.ndarray, *, kernel: int, h: float, leaf_size: int, tol: float, max_rank: int,
+                admissibility: int, tau: float, sample_rows: int = 4096, seed: int = 7,
+                threads: int = 0) -> Repr:
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    o = hm_compress_opts(kernel, h, leaf_size, tol, max_rank, admissibility, tau, sample_rows, seed,
+                         threads)
+    out = _P()
+    _check(lib.hm_compress(X.ctypes.data, X.shape[0], X.shape[1], ctypes.byref(o), ctypes.byref(out)))
+    return Repr(out.value)
+
+
+def hm_repr_write(r: Repr, path: str) -> None:
+    r.write(path)
+
+
+def hm_repr_free(r: Repr) -> None:
+    if r.handle:
+        _check(lib.hm_repr_free(r.handle))
+        r.handle = None
+
+
 def hm_load_compressed_mem(src, device: int = 0, prec_mask: int = precbit(HM_PREC_FP64)) -> Matrix:
+    if isinstance(src, Repr):
+        out = _P()
+        _check(lib.hm_load_compressed_mem(ctypes.byref(src._view), device, prec_mask, ctypes.byref(out)))
+        return Matrix(out.value)
     r, keep = host_repr(src)
     out = _P()
     _check(lib.hm_load_compressed_mem(ctypes.byref(r), device, prec_mask, ctypes.byref(out)))
