@@ -144,6 +144,12 @@ hm_status hm_free(hm_matrix h);
 hm_status hm_eval(hm_matrix h, const void *W, int64_t ldw, void *Y, int64_t ldy, int64_t Q,
                   hm_dtype dtype, hm_prec prec, unsigned flags, void *stream);
 
+/* Synchronize the device and report whether any evaluation on h since the
+ * last check hit the bounded dependency wait of the persistent launch
+ * (HM_ERR_INTERNAL: those results are invalid; the launch itself always
+ * terminates).  HM_OK otherwise. */
+hm_status hm_check(hm_matrix h);
+
 /* Per-phase timings of evaluations run with HM_PROFILE since the last reset:
  * for phase i (0 permute-in, 1 up pass, 2 down pass (far reduction and
  * transfers), 3 leaf pass (near field and leaf basis), 4 permute-out) writes the

@@ -5,6 +5,6 @@ The compute path is libhm.so (HIP kernels for gfx950) behind the C ABI of
 include/hm.h; this package is its Python binding.
 """
 from .hm import (HM_F32, HM_F64, HM_PREC_FP32, HM_PREC_FP64, HM_PROFILE, HM_TREE_ORDER,  # noqa: F401
-                 HMError, Matrix, Repr, hm_compress, hm_eval, hm_free, hm_info, hm_last_error,
+                 HMError, Matrix, Repr, hm_check, hm_compress, hm_eval, hm_free, hm_info, hm_last_error,
                  hm_load_compressed, hm_load_compressed_mem, hm_profile_read, hm_profile_reset,
                  hm_repr_free, hm_repr_write, precbit)

@@ -1,6 +1,8 @@
 // hm_api.hip -- the extern "C" entry points declared in include/hm.h.
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
+#include <cstring>
 #include <new>
 #include <string>
 
@@ -133,6 +135,10 @@ hm_status hm_free(hm_matrix h) {
         for (int b = 0; b < BUF_COUNT; b++)
             if (h->ws[s][b]) (void)hipFree(h->ws[s][b]);
     if (h->d_perm) (void)hipFree(h->d_perm);
+    free_plan(h->plan[0]);
+    free_plan(h->plan[1]);
+    if (h->d_mat) (void)hipFree(h->d_mat);
+    if (h->d_head) (void)hipFree(h->d_head);
     if (h->d_tasks) (void)hipFree(h->d_tasks);
     if (h->d_segs) (void)hipFree(h->d_segs);
     for (int g = 0; g < 5; g++)
@@ -160,7 +166,10 @@ hm_status hm_eval(hm_matrix h, const void *W, int64_t ldw, void *Y, int64_t ldy,
     if (ds.err != hipSuccess) return fail(HM_ERR_DEVICE, "hm_eval: cannot select the device");
     hipStream_t s = (hipStream_t)stream;
     const int es = dtype == HM_F64 ? 8 : 4, slot = dtype == HM_F64 ? 0 : 1;
+    const char *sched = std::getenv("HM_SCHED");
+    const bool level_sched = sched && std::string(sched) == "level";
     int bn_kind[4] = {0, pick_bn(Q, 1), pick_bn(Q, 2), pick_bn(Q, 3)};
+    if (!level_sched) bn_kind[1] = bn_kind[2] = bn_kind[3];  // one tile for the whole graph
     const int bn_max = std::max({bn_kind[1], bn_kind[2], bn_kind[3]});
     const int64_t Qp = (Q + bn_max - 1) / bn_max * bn_max;  // workspace leading dimension
     const size_t rows[BUF_COUNT] = {(size_t)h->N, (size_t)h->N, (size_t)h->skel_rows,
@@ -173,6 +182,27 @@ hm_status hm_eval(hm_matrix h, const void *W, int64_t ldw, void *Y, int64_t ldy,
     for (int b = 0; b < BUF_COUNT; b++) bufs[b] = h->ws[slot][b];
     const bool prof = (flags & HM_PROFILE) != 0;
     const int64_t *perm = (flags & HM_TREE_ORDER) ? nullptr : h->d_perm;
+
+    int grid = 0;
+    if (!level_sched) {
+        const int occ = persistent_occupancy(es, bn_kind[3]);
+        const int workers = std::max(1, occ * h->n_cu);
+        GraphPlan &plan = h->plan[slot];
+        if (plan.bn != bn_kind[3] || plan.Q != Qp) {
+            HM_HIP(hipStreamSynchronize(s));
+            hm_status st = make_plan(h, slot, bn_kind[3], Qp, Qp, workers);
+            if (st != HM_OK) return st;
+        }
+        MatDesc md{h->prec[prec].blocks, {bufs[0], bufs[1], bufs[2], bufs[3]}, Qp};
+        MatDesc &cache = h->mat_cache[slot];
+        if (std::memcmp(&md, &cache, sizeof(MatDesc)) != 0 || h->mat_slot != slot) {
+            HM_HIP(hipStreamSynchronize(s));
+            HM_HIP(hipMemcpy(h->d_mat, &md, sizeof(MatDesc), hipMemcpyHostToDevice));
+            cache = md;
+            h->mat_slot = slot;
+        }
+        grid = std::min(plan.n_tasks, workers);
+    }
 
     auto mark = [&](int group, bool begin) -> hm_status {
         if (!prof) return HM_OK;
@@ -189,20 +219,43 @@ hm_status hm_eval(hm_matrix h, const void *W, int64_t ldw, void *Y, int64_t ldy,
     if ((st = mark(0, true)) != HM_OK) return st;
     HM_HIP(launch_permute_in(W, ldw, bufs[BUF_WT], Qp, perm, h->N, Q, es, s));
     if ((st = mark(0, false)) != HM_OK) return st;
-    int open_group = -1;
-    for (const Phase &ph : h->phases) {
-        int g = group_of(ph.kind);
-        if (g != open_group) {
-            if (open_group >= 0 && (st = mark(open_group, false)) != HM_OK) return st;
-            if ((st = mark(g, true)) != HM_OK) return st;
-            open_group = g;
+    if (!level_sched) {
+        // the whole graph (up, down, near, leaf far part) in one launch,
+        // reported as the leaf-pass group
+        if ((st = mark(3, true)) != HM_OK) return st;
+        HM_HIP(launch_persistent(h->plan[slot], es, h->d_segs, h->d_mat, h->d_head, grid, s));
+        if ((st = mark(3, false)) != HM_OK) return st;
+    } else {
+        int open_group = -1;
+        for (const Phase &ph : h->phases) {
+            int g = group_of(ph.kind);
+            if (g != open_group) {
+                if (open_group >= 0 && (st = mark(open_group, false)) != HM_OK) return st;
+                if ((st = mark(g, true)) != HM_OK) return st;
+                open_group = g;
+            }
+            HM_HIP(launch_phase(h, ph, es, bn_kind[ph.kind], Qp, bufs, s));
         }
-        HM_HIP(launch_phase(h, ph, es, bn_kind[ph.kind], Qp, bufs, s));
+        if (open_group >= 0 && (st = mark(open_group, false)) != HM_OK) return st;
     }
-    if (open_group >= 0 && (st = mark(open_group, false)) != HM_OK) return st;
     if ((st = mark(4, true)) != HM_OK) return st;
     HM_HIP(launch_permute_out(bufs[BUF_YT], Qp, Y, ldy, perm, h->N, Q, es, s));
     if ((st = mark(4, false)) != HM_OK) return st;
+    return HM_OK;
+}
+
+hm_status hm_check(hm_matrix h) {
+    if (!h) return fail(HM_ERR_INVALID, "hm_check: NULL argument");
+    DeviceScope ds(h->device);
+    HM_HIP(hipDeviceSynchronize());
+    int32_t err = 0;
+    HM_HIP(hipMemcpy(&err, h->d_head + 1, sizeof(int32_t), hipMemcpyDeviceToHost));
+    if (err) {
+        const int32_t zero = 0;
+        HM_HIP(hipMemcpy(h->d_head + 1, &zero, sizeof(int32_t), hipMemcpyHostToDevice));
+        return fail(HM_ERR_INTERNAL, "a dependency wait of the persistent launch timed out; "
+                                     "the results of the affected evaluations are invalid");
+    }
     return HM_OK;
 }
 

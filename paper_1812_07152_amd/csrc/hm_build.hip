@@ -34,6 +34,7 @@ struct Block {            // one output block of a phase before tiling
     int64_t out_row;
     int32_t M;
     std::vector<Seg> segs;
+    int32_t node = -1;
     int64_t work() const {
         int64_t k = 0;
         for (const Seg &s : segs) k += s.K;
@@ -47,6 +48,11 @@ struct Planner {
     std::vector<Task> tasks;
     std::vector<Seg> segs;
     std::vector<Phase> phases;
+    struct Placed {
+        int32_t kind, node, out_buf, M, seg_begin, seg_end;
+        int64_t out_row, kpad;
+    };
+    std::vector<Placed> placed;  // every block with its segment range
 
     // Reserve a K-major block of `krows` contraction rows (padded with zero
     // rows to a multiple of 16) of `ld` elements each.
@@ -83,6 +89,9 @@ struct Planner {
                 flops += 2.0 * b.M * s.K;
             }
             int32_t se = (int32_t)segs.size();
+            int64_t kp = 0;
+            for (const Seg &sg : b.segs) kp += sg.Kpad;
+            placed.push_back({kind, b.node, b.out_buf, b.M, sb, se, b.out_row, kp});
             for (int32_t m0 = 0; m0 < std::max(b.M, 1); m0 += ph.bm) {
                 Task t{};
                 t.out_row = b.out_row + m0;
@@ -170,7 +179,7 @@ hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_mat
             const int32_t k = r.rank[a];
             if (k == 0) continue;
             const int32_t kp = (int32_t)round_up(k, 16);
-            Block b{BUF_WHAT, wrow[a], k, {}};
+            Block b{BUF_WHAT, wrow[a], k, {}, a};
             if (leaf(a)) {
                 const int32_t m = (int32_t)r.size[a];
                 int64_t off = P.alloc(m, kp);
@@ -205,7 +214,7 @@ hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_mat
             const int32_t ka = r.rank[a];
             if (ka == 0) continue;
             const int32_t kap = (int32_t)round_up(ka, 16);
-            Block b{BUF_YHAT, wrow[a], ka, {}};
+            Block b{BUF_YHAT, wrow[a], ka, {}, a};
             for (int64_t e = r.far_ptr[a]; e < r.far_ptr[a + 1]; e++) {
                 const int32_t bn = r.far_col[e], kb = r.rank[bn];
                 if (kb == 0) continue;
@@ -233,7 +242,7 @@ hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_mat
         for (int a = 0; a < n; a++) {
             if (!leaf(a)) continue;
             const int32_t ma = (int32_t)r.size[a], map = (int32_t)round_up(ma, 16);
-            Block b{BUF_YT, r.start[a], ma, {}};
+            Block b{BUF_YT, r.start[a], ma, {}, a};
             for (int64_t e = r.near_ptr[a]; e < r.near_ptr[a + 1]; e++) {
                 const int32_t bn = r.near_col[e];
                 const int32_t mb = (int32_t)r.size[bn];
@@ -251,6 +260,63 @@ hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_mat
             blocks.push_back(std::move(b));
         }
         P.add_phase(3, r.depth, blocks);
+    }
+
+    // ---- dependency graph for the persistent launch
+    std::vector<GJob> jobs;
+    {
+        std::vector<int32_t> up_job(n, -1), down_job(n, -1), near_job(n, -1);
+        for (const Planner::Placed &pl : P.placed) {
+            GJob j{};
+            j.kind = pl.kind;
+            j.node = pl.node;
+            j.out_buf = pl.out_buf;
+            j.out_row = pl.out_row;
+            j.M = pl.M;
+            j.seg_begin = pl.seg_begin;
+            j.seg_end = pl.seg_end;
+            j.accumulate = 0;
+            j.kpad = pl.kpad;
+            const int a = pl.node;
+            if (pl.kind == 1) {
+                if (!leaf(a)) {
+                    if (r.rank[r.left[a]] > 0) j.preds.push_back(up_job[r.left[a]]);
+                    if (r.rank[r.right[a]] > 0) j.preds.push_back(up_job[r.right[a]]);
+                }
+                up_job[a] = (int32_t)jobs.size();
+                jobs.push_back(j);
+            } else if (pl.kind == 2) {
+                for (int64_t e = r.far_ptr[a]; e < r.far_ptr[a + 1]; e++)
+                    if (r.rank[r.far_col[e]] > 0) j.preds.push_back(up_job[r.far_col[e]]);
+                const int32_t p = r.parent[a];
+                if (p >= 0 && r.level[p] >= 1 && r.rank[p] > 0) j.preds.push_back(down_job[p]);
+                down_job[a] = (int32_t)jobs.size();
+                jobs.push_back(j);
+            } else {
+                // the leaf block's segments are its near blocks followed by
+                // the leaf far part (present when the leaf has a basis)
+                const bool far_part = r.rank[a] > 0 && r.level[a] >= 1;
+                GJob nj = j;
+                nj.kind = 3;
+                nj.seg_end = far_part ? pl.seg_end - 1 : pl.seg_end;
+                nj.kpad = 0;
+                for (int32_t q = nj.seg_begin; q < nj.seg_end; q++) nj.kpad += P.segs[q].Kpad;
+                near_job[a] = (int32_t)jobs.size();
+                jobs.push_back(nj);
+                if (far_part) {
+                    GJob fj = j;
+                    fj.kind = 4;
+                    fj.seg_begin = pl.seg_end - 1;
+                    fj.accumulate = 1;
+                    fj.kpad = P.segs[fj.seg_begin].Kpad;
+                    fj.preds = {near_job[a], down_job[a]};
+                    jobs.push_back(fj);
+                }
+            }
+        }
+        for (const GJob &j : jobs)
+            for (int32_t q : j.preds)
+                if (q < 0) return fail(HM_ERR_INTERNAL, "dependency graph: missing predecessor job");
     }
 
     // ---- device side
@@ -286,6 +352,7 @@ hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_mat
     // slack after the last block: a tile taller than its block reads past it
     h->store_elems = P.store_off + 512;
     h->phases = P.phases;
+    h->gjobs = std::move(jobs);
 
     hipStream_t s = nullptr;
     HM_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
@@ -335,6 +402,14 @@ hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_mat
     if (!P.segs.empty())
         HM_HIP(hipMemcpyAsync(h->d_segs, P.segs.data(), sizeof(Seg) * P.segs.size(),
                               hipMemcpyHostToDevice, s));
+    HM_HIP(hipMalloc(&h->d_mat, sizeof(MatDesc)));
+    HM_HIP(hipMalloc(&h->d_head, 2 * sizeof(int32_t)));
+    HM_HIP(hipMemsetAsync(h->d_head, 0, 2 * sizeof(int32_t), s));
+    {
+        hipDeviceProp_t prop;
+        HM_HIP(hipGetDeviceProperties(&prop, device));
+        h->n_cu = prop.multiProcessorCount;
+    }
     HM_HIP(hipStreamSynchronize(s));
     if (!(prec_mask & HM_PRECBIT(HM_PREC_FP64))) {
         HM_HIP(hipFree(store64));

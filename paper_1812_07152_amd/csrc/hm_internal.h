@@ -89,6 +89,51 @@ struct RepackJob {
     int32_t ld;       // padded length of a stored row
 };
 
+// One entry of the persistent task-graph launch (see k_persistent): a row
+// tile of one output block for one column tile, with its dependencies.
+struct PTask {
+    int64_t out_row;
+    int32_t out_buf, M, m0, seg_begin, seg_end;
+    int32_t bm;          // tile height: 64 or 128
+    int32_t accumulate;  // 1: out += product (a leaf's far part after its near part)
+    int32_t qtile;       // column tile: columns [qtile * BN, (qtile + 1) * BN)
+    int32_t mat;         // index into the MatDesc table
+    int32_t ndeps;       // entries that must finish first
+    int32_t succ_begin, succ_end;  // successor entries (queue positions) in the succ array
+    int32_t pad_;
+};
+
+// Device addresses of one matrix for the persistent launch.
+struct MatDesc {
+    const void *store;
+    void *buf[4];
+    int64_t ldq;
+};
+
+// A node-level job of the evaluation's dependency graph (host side).
+struct GJob {
+    int32_t kind;        // 1 up, 2 down, 3 near, 4 leaf far part
+    int32_t node;
+    int32_t out_buf;
+    int64_t out_row;
+    int32_t M;
+    int32_t seg_begin, seg_end;  // into the matrix's segment table
+    int32_t accumulate;
+    int64_t kpad;        // sum of Kpad over its segments (work model)
+    std::vector<int32_t> preds;  // job indices
+};
+
+// Expanded, ordered graph of one matrix for one (column tile, Q) choice.
+struct GraphPlan {
+    int bn = 0;
+    int64_t Q = -1;
+    int n_tasks = 0;
+    PTask *d_tasks = nullptr;
+    int32_t *d_succ = nullptr;
+    int32_t *d_counters = nullptr;
+    double est_ms = 0;   // list-scheduling estimate (diagnostic)
+};
+
 struct PrecStore {
     void *blocks = nullptr;   // device block store (FP64 or FP32 elements)
     size_t bytes = 0;
@@ -115,6 +160,13 @@ struct hm_matrix_s {
     hm::Task *d_tasks = nullptr;
     hm::Seg *d_segs = nullptr;
     std::vector<hm::Phase> phases;
+    std::vector<hm::GJob> gjobs;           // dependency graph of one evaluation
+    hm::GraphPlan plan[2];                 // per element size, for the last (Q, BN)
+    hm::MatDesc *d_mat = nullptr;          // one descriptor (persistent launch)
+    hm::MatDesc mat_cache[2] = {};         // last uploaded descriptor per element size
+    int mat_slot = -1;                     // element-size slot of the uploaded descriptor
+    int32_t *d_head = nullptr;             // queue head + error flag (2 ints)
+    int n_cu = 0;                          // compute units of the device
     // workspaces (per element size), grown on demand
     void *ws[2][hm::BUF_COUNT] = {{nullptr}};
     size_t ws_bytes[2][hm::BUF_COUNT] = {{0}};
@@ -150,5 +202,15 @@ hipError_t launch_permute_out(const void *Yt, int64_t Qp, void *Y, int64_t ldy, 
 hipError_t launch_convert_f64_to_f32(const double *src, float *dst, int64_t n, hipStream_t s);
 hipError_t launch_repack(const double *stage, const RepackJob *jobs, int njobs, double *store,
                          hipStream_t s);
+// Persistent launch of a plan (init + graph kernel) on stream s.
+hipError_t launch_persistent(const GraphPlan &plan, int elem_bytes, const Seg *segs,
+                             const MatDesc *d_mat, int32_t *d_head, int grid, hipStream_t s);
+// Resident workgroups per CU of the persistent kernel for (elem_bytes, bn).
+int persistent_occupancy(int elem_bytes, int bn);
+
+// Expand the job graph for Q columns with column tile bn, order it by list
+// scheduling on `workers` simulated workgroups, and upload it (hm_sched.hip).
+hm_status make_plan(hm_matrix h, int slot, int bn, int64_t Q, int64_t ldq, int workers);
+void free_plan(GraphPlan &p);
 
 }  // namespace hm

@@ -19,6 +19,7 @@
 // chunk).  Lane mapping of the 16x16x4 MFMAs (checked on the device): lane l
 // supplies A[l%16][l/16] and B[l/16][l%16]; accumulator register r of lane l
 // holds D[4r + l/16][l%16] for FP64 and D[4(l/16) + r][l%16] for FP32.
+#include <algorithm>
 #include <cstdlib>
 
 #include "hm_internal.h"
@@ -71,14 +72,26 @@ constexpr int lds_pad() { return 128 / (int)sizeof(T); }
 //     the store has slack after its last block for the row over-read of a
 //     tile taller than the block;
 //   - workspaces have leading dimension ldq, a multiple of BN.
-template <typename T, int BM, int BN, int WAVES_M, int WAVES_N>
-__global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void k_block_products(
-    const Task *__restrict__ tasks, const Seg *__restrict__ segs, int task_begin,
-    const T *__restrict__ store, T *buf0, T *buf1, T *buf2, T *buf3, int64_t ldq) {
+
+// One output block of a task as the tile code sees it.
+struct TileJob {
+    int64_t out_row;
+    int32_t out_buf, M, m0, seg_begin, seg_end, accumulate;
+};
+
+// Computes rows [0, M) x columns [n0, n0 + BN) of one output block:
+//   out (=|+=) sum over segments of A_s (K-major in the store) * B_s rows.
+// NT threads take part in loads and barriers; the first WAVES_M * WAVES_N
+// waves own FM x FN MFMA fragments each.  As/Bs are LDS buffers of
+// 2 x kBK x (BM + pad) and 2 x kBK x (BN + pad) elements.
+template <typename T, int BM, int BN, int WAVES_M, int WAVES_N, int NT>
+__device__ __forceinline__ void block_product(const TileJob &task, const Seg *__restrict__ segs,
+                                              const T *__restrict__ store, T *buf0, T *buf1,
+                                              T *buf2, T *buf3, int64_t ldq, int64_t n0, T *As_,
+                                              T *Bs_) {
     using M_ = Mfma<T>;
     using acc_t = typename M_::acc_t;
     using vec_t = typename M_::vec_t;
-    constexpr int NT = 64 * WAVES_M * WAVES_N;
     constexpr int WM = BM / WAVES_M, WN = BN / WAVES_N;
     constexpr int FM = WM / 16, FN = WN / 16;
     constexpr int VEC = M_::kVec;
@@ -87,13 +100,12 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void k_block_products(
     constexpr int A_PER = (A_VECS + NT - 1) / NT, B_PER = (B_VECS + NT - 1) / NT;
     constexpr int LA = BM + lds_pad<T>(), LB = BN + lds_pad<T>();
     static_assert(FM >= 1 && FN >= 1 && WM % 16 == 0 && WN % 16 == 0, "bad tile");
+    static_assert(64 * WAVES_M * WAVES_N <= NT, "too few threads");
+    T(*As)[kBK][LA] = reinterpret_cast<T(*)[kBK][LA]>(As_);
+    T(*Bs)[kBK][LB] = reinterpret_cast<T(*)[kBK][LB]>(Bs_);
 
-    __shared__ __attribute__((aligned(16))) T As[2][kBK][LA];
-    __shared__ __attribute__((aligned(16))) T Bs[2][kBK][LB];
-
-    const Task task = tasks[task_begin + blockIdx.x];
-    const int64_t n0 = (int64_t)blockIdx.y * BN;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const bool computes = wave < WAVES_M * WAVES_N;
     const int wm = wave / WAVES_N, wn = wave % WAVES_N;
     // buffer select without a dynamically indexed private array
     auto bufp = [&](int b) { return b == 0 ? buf0 : b == 1 ? buf1 : b == 2 ? buf2 : buf3; };
@@ -171,7 +183,7 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void k_block_products(
             }
             const bool more = ns < task.seg_end;
             load(nsg, more ? nkk : kk);  // on the last chunk: a harmless re-load
-            compute(b);
+            if (computes) compute(b);
             stash(b ^ 1);
             __syncthreads();
             if (!more) break;
@@ -182,6 +194,7 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void k_block_products(
         }
     }
 
+    if (!computes) return;
     T *out = bufp(task.out_buf) + task.out_row * ldq + n0;
 #pragma unroll
     for (int i = 0; i < FM; i++)
@@ -191,8 +204,99 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void k_block_products(
             for (int r = 0; r < 4; r++) {
                 const int row = wm * WM + i * 16 + M_::row(lane, r);
                 const int col = wn * WN + j * 16 + (lane & 15);
-                if (row < task.M) out[(int64_t)row * ldq + col] = acc[i][j][r];
+                if (row < task.M) {
+                    T *o = out + (int64_t)row * ldq + col;
+                    *o = task.accumulate ? *o + acc[i][j][r] : acc[i][j][r];
+                }
             }
+}
+
+// One launch = one phase: workgroup (x, y) computes task x, column tile y.
+template <typename T, int BM, int BN, int WAVES_M, int WAVES_N>
+__global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void k_block_products(
+    const Task *__restrict__ tasks, const Seg *__restrict__ segs, int task_begin,
+    const T *__restrict__ store, T *buf0, T *buf1, T *buf2, T *buf3, int64_t ldq) {
+    constexpr int NT = 64 * WAVES_M * WAVES_N;
+    __shared__ __attribute__((aligned(16))) T As[2 * kBK * (BM + lds_pad<T>())];
+    __shared__ __attribute__((aligned(16))) T Bs[2 * kBK * (BN + lds_pad<T>())];
+    const Task t = tasks[task_begin + blockIdx.x];
+    const TileJob job{t.out_row, t.out_buf, t.M, t.m0, t.seg_begin, t.seg_end, 0};
+    block_product<T, BM, BN, WAVES_M, WAVES_N, NT>(job, segs, store, buf0, buf1, buf2, buf3, ldq,
+                                                   (int64_t)blockIdx.y * BN, As, Bs);
+}
+
+// Wave layouts of the persistent kernel (8 waves) per tile: {WAVES_M, WAVES_N}.
+template <int BM, int BN>
+struct PLayout {
+    static constexpr int WN = BN >= 256 ? (BM == 128 ? 4 : 8) : BN == 128 ? (BM == 128 ? 2 : 4)
+                            : BN == 64 ? (BM == 128 ? 1 : 2) : BN == 32 ? (BM == 128 ? 1 : 2) : 1;
+    static constexpr int WMv = (BM / 16 < 8 / WN) ? BM / 16 : 8 / WN;
+};
+
+constexpr int kPersistThreads = 512;
+constexpr int kWaitLimit = 1 << 20;  // polls (each followed by a sleep) before giving up
+
+// Persistent task-graph launch: workgroups take queue entries in order with
+// an atomic head; an entry starts once its dependency counter is zero (a
+// bounded wait, see kWaitLimit), then decrements its successors' counters
+// after its output is written back (agent-scope release / acquire, which
+// also makes results visible across the XCDs' separate L2 caches).  The
+// queue order is topological, so every awaited entry was taken earlier by a
+// running workgroup: the launch cannot deadlock and every workgroup exits
+// when the queue is drained.
+template <typename T, int BN>
+__global__ __launch_bounds__(kPersistThreads) void k_persistent(
+    const PTask *__restrict__ tasks, int n_tasks, const int32_t *__restrict__ succ,
+    int32_t *counters, int32_t *head, int32_t *err, const Seg *__restrict__ segs,
+    const MatDesc *__restrict__ mats) {
+    __shared__ __attribute__((aligned(16))) T As[2 * kBK * (128 + lds_pad<T>())];
+    __shared__ __attribute__((aligned(16))) T Bs[2 * kBK * (BN + lds_pad<T>())];
+    __shared__ int s_t;
+    while (true) {
+        if (threadIdx.x == 0) s_t = __hip_atomic_fetch_add(head, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        const int t = s_t;
+        __syncthreads();
+        if (t >= n_tasks) break;
+        const PTask pt = tasks[t];
+        if (threadIdx.x == 0 && pt.ndeps > 0) {
+            int polls = 0;
+            while (__hip_atomic_load(&counters[t], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) > 0) {
+                if (++polls > kWaitLimit) {
+                    __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(8);
+            }
+        }
+        __syncthreads();
+        const MatDesc md = mats[pt.mat];
+        const TileJob job{pt.out_row, pt.out_buf, pt.M, pt.m0, pt.seg_begin, pt.seg_end, pt.accumulate};
+        const int64_t n0 = (int64_t)pt.qtile * BN;
+        const T *store = (const T *)md.store;
+        if (pt.bm == 128)
+            block_product<T, 128, BN, PLayout<128, BN>::WMv, PLayout<128, BN>::WN, kPersistThreads>(
+                job, segs, store, (T *)md.buf[0], (T *)md.buf[1], (T *)md.buf[2], (T *)md.buf[3],
+                md.ldq, n0, As, Bs);
+        else
+            block_product<T, 64, BN, PLayout<64, BN>::WMv, PLayout<64, BN>::WN, kPersistThreads>(
+                job, segs, store, (T *)md.buf[0], (T *)md.buf[1], (T *)md.buf[2], (T *)md.buf[3],
+                md.ldq, n0, As, Bs);
+        __syncthreads();  // every wave's stores of this task are done
+        if (threadIdx.x == 0 && pt.succ_end > pt.succ_begin) {
+            __threadfence();  // release this task's output to every XCD
+            for (int e = pt.succ_begin; e < pt.succ_end; e++)
+                __hip_atomic_fetch_add(&counters[succ[e]], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+// counters[i] = tasks[i].ndeps; head = 0 (run before each persistent launch).
+__global__ void k_persistent_init(const PTask *__restrict__ tasks, int n_tasks, int32_t *counters,
+                                  int32_t *head) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n_tasks) counters[i] = tasks[i].ndeps;
+    if (i == 0) *head = 0;
 }
 
 // Row gather W (original order, leading dimension ldw) -> Wt (tree order, Qp),
@@ -321,6 +425,58 @@ hipError_t launch_phase(const hm_matrix_s *h, const Phase &ph, int elem_bytes, i
     if (ph.task_count == 0) return hipSuccess;
     return elem_bytes == 8 ? dispatch<double>(h, ph, bn, ldq, bufs, s)
                            : dispatch<float>(h, ph, bn, ldq, bufs, s);
+}
+
+namespace {
+
+template <typename T, int BN>
+hipError_t run_persistent(const GraphPlan &plan, const Seg *segs, const MatDesc *mats,
+                          int32_t *head, int grid, hipStream_t s) {
+    const int nt = plan.n_tasks;
+    hipLaunchKernelGGL(k_persistent_init, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s,
+                       plan.d_tasks, nt, plan.d_counters, head);
+    hipLaunchKernelGGL((k_persistent<T, BN>), dim3((unsigned)grid), dim3(kPersistThreads), 0, s,
+                       plan.d_tasks, nt, plan.d_succ, plan.d_counters, head, head + 1, segs, mats);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t persistent_bn(const GraphPlan &plan, const Seg *segs, const MatDesc *mats, int32_t *head,
+                         int grid, hipStream_t s) {
+    switch (plan.bn) {
+        case 16: return run_persistent<T, 16>(plan, segs, mats, head, grid, s);
+        case 32: return run_persistent<T, 32>(plan, segs, mats, head, grid, s);
+        case 64: return run_persistent<T, 64>(plan, segs, mats, head, grid, s);
+        case 128: return run_persistent<T, 128>(plan, segs, mats, head, grid, s);
+        default: return run_persistent<T, 256>(plan, segs, mats, head, grid, s);
+    }
+}
+
+template <typename T>
+int occupancy_bn(int bn) {
+    int n = 0;
+    hipError_t e = hipSuccess;
+    switch (bn) {
+        case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_persistent<T, 16>, kPersistThreads, 0); break;
+        case 32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_persistent<T, 32>, kPersistThreads, 0); break;
+        case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_persistent<T, 64>, kPersistThreads, 0); break;
+        case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_persistent<T, 128>, kPersistThreads, 0); break;
+        default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_persistent<T, 256>, kPersistThreads, 0); break;
+    }
+    return e == hipSuccess ? std::max(n, 1) : 1;
+}
+
+}  // namespace
+
+hipError_t launch_persistent(const GraphPlan &plan, int elem_bytes, const Seg *segs,
+                             const MatDesc *d_mat, int32_t *d_head, int grid, hipStream_t s) {
+    if (plan.n_tasks == 0) return hipSuccess;
+    return elem_bytes == 8 ? persistent_bn<double>(plan, segs, d_mat, d_head, grid, s)
+                           : persistent_bn<float>(plan, segs, d_mat, d_head, grid, s);
+}
+
+int persistent_occupancy(int elem_bytes, int bn) {
+    return elem_bytes == 8 ? occupancy_bn<double>(bn) : occupancy_bn<float>(bn);
 }
 
 hipError_t launch_permute_in(const void *W, int64_t ldw, void *Wt, int64_t Qp, const int64_t *perm,

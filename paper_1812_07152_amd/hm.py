@@ -89,6 +89,8 @@ def _load():
     L.hm_profile_read.argtypes = [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     L.hm_profile_reset.restype = st
     L.hm_profile_reset.argtypes = [_P]
+    L.hm_check.restype = st
+    L.hm_check.argtypes = [_P]
     L.hm_compress.restype = st
     L.hm_compress.argtypes = [_P, ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(hm_compress_opts),
                               ctypes.POINTER(_P)]
@@ -282,6 +284,11 @@ def hm_eval(h: Matrix, W, Y, Q: int | None = None, prec: int | None = None, flag
         raise ValueError("hm_eval: tensors narrower than Q")
     _check(lib.hm_eval(h, W.data_ptr(), W.stride(0), Y.data_ptr(), Y.stride(0), Q, dtype, prec,
                        flags, _stream_ptr(stream)))
+
+
+def hm_check(h: Matrix) -> None:
+    """Synchronize and raise if a persistent launch's bounded wait expired."""
+    _check(lib.hm_check(h))
 
 
 def hm_profile_read(h: Matrix):

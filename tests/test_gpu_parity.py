@@ -24,6 +24,14 @@ def _say(msg):
     sys.stdout.flush()
 
 
+@pytest.fixture(params=["graph", "level"], autouse=True)
+def sched(request, monkeypatch):
+    """Run each test under both launch styles: the persistent task-graph
+    launch (default) and one launch per tree level."""
+    monkeypatch.setenv("HM_SCHED", request.param)
+    return request.param
+
+
 @pytest.fixture(scope="module")
 def hmx():
     assert torch.cuda.is_available(), "GPU test run without a GPU"
@@ -56,7 +64,7 @@ def gpu_eval(hmx, M, W, prec_f64=True, flags=0, Q=None):
     Wd = torch.from_numpy(W).to("cuda", dt)
     Yd = torch.full_like(Wd, float("nan"))
     hmx.hm_eval(M, Wd, Yd, Q=Q, flags=flags)
-    torch.cuda.synchronize()
+    hmx.hm_check(M)  # synchronizes; raises if a bounded wait expired
     return Yd.double().cpu().numpy()
 
 
