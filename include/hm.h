@@ -159,6 +159,46 @@ hm_status hm_profile_read(hm_matrix h, double ms[5], int64_t launches[5]);
 hm_status hm_profile_reset(hm_matrix h);
 
 /* ---------------------------------------------------------------------------
+ * Batched evaluation: many matrices of uneven size, rank and width evaluated
+ * by one persistent task-graph launch.  Their dependency graphs are merged
+ * into one queue, ordered together by list scheduling, so that the small
+ * matrices' tree passes and the large ones' near fields share the machine.
+ * A batch fixes its matrices, their widths Q[i], dtype and precision; it owns
+ * its workspaces (so it never disturbs hm_eval on the same matrices), runs on
+ * a private stream joined to the caller's stream by events, and replays one
+ * captured HIP graph (batched permute-in, graph launch, batched permute-out)
+ * per evaluation.  With HM_BATCH_AUTOTUNE the column tile is chosen by timing
+ * every candidate (32, 64, 128, 256) on the batch itself at creation. */
+typedef struct hm_batch_s *hm_batch;
+#define HM_BATCH_AUTOTUNE 1u   /* time the candidate column tiles and keep the fastest */
+#define HM_BATCH_NO_GRAPH 2u   /* enqueue the launches directly instead of a captured graph */
+
+typedef struct {
+    int32_t n, column_tile, n_tasks, workgroups;
+    double flops;             /* algorithmic flops of one batched evaluation */
+    double tuned_ms[5];       /* autotuner timing per tile 16, 32, 64, 128, 256 (0 = not tried) */
+    double workspace_bytes;
+} hm_batch_info_t;
+
+/* Create a batch of n matrices (same device, precision loaded) with widths Q
+ * (1 <= Q[i] <= 2^24).  Synchronizes the device while it builds the plan. */
+hm_status hm_batch_create(int n, const hm_matrix *hs, const int64_t *Q, hm_dtype dtype,
+                          hm_prec prec, unsigned flags, hm_batch *out);
+/* Y[i] = K~_i W[i] for every matrix of the batch (device pointers, row-major,
+ * leading dimensions ldw[i], ldy[i] >= Q[i]); asynchronous on `stream`.
+ * Evaluations of one batch are serialized on its private stream. */
+hm_status hm_batch_eval(hm_batch b, const void *const *W, const int64_t *ldw, void *const *Y,
+                        const int64_t *ldy, void *stream);
+hm_status hm_batch_info(hm_batch b, hm_batch_info_t *out);
+/* Wait for the batch's stream; HM_ERR_INTERNAL if a bounded wait expired. */
+hm_status hm_batch_check(hm_batch b);
+hm_status hm_batch_free(hm_batch b);
+/* One-shot form: create, evaluate, wait, free. */
+hm_status hm_eval_batched(int n, const hm_matrix *hs, const void *const *W, const int64_t *ldw,
+                          void *const *Y, const int64_t *ldy, const int64_t *Q, hm_dtype dtype,
+                          hm_prec prec, void *stream);
+
+/* ---------------------------------------------------------------------------
  * Inspector: host-side compression of a point set into the representation
  * above (the compression phase of the paper, Section 3.1: tree construction,
  * interaction computation, sampling, ID low-rank approximation).  Runs on the

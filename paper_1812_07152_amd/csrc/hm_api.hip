@@ -193,7 +193,7 @@ hm_status hm_eval(hm_matrix h, const void *W, int64_t ldw, void *Y, int64_t ldy,
             hm_status st = make_plan(h, slot, bn_kind[3], Qp, Qp, workers);
             if (st != HM_OK) return st;
         }
-        MatDesc md{h->prec[prec].blocks, {bufs[0], bufs[1], bufs[2], bufs[3]}, Qp};
+        MatDesc md{h->prec[prec].blocks, {bufs[0], bufs[1], bufs[2], bufs[3]}, Qp, h->d_segs};
         MatDesc &cache = h->mat_cache[slot];
         if (std::memcmp(&md, &cache, sizeof(MatDesc)) != 0 || h->mat_slot != slot) {
             HM_HIP(hipStreamSynchronize(s));
@@ -223,7 +223,7 @@ hm_status hm_eval(hm_matrix h, const void *W, int64_t ldw, void *Y, int64_t ldy,
         // the whole graph (up, down, near, leaf far part) in one launch,
         // reported as the leaf-pass group
         if ((st = mark(3, true)) != HM_OK) return st;
-        HM_HIP(launch_persistent(h->plan[slot], es, h->d_segs, h->d_mat, h->d_head, grid, s));
+        HM_HIP(launch_persistent(h->plan[slot], es, h->d_mat, h->d_head, grid, s));
         if ((st = mark(3, false)) != HM_OK) return st;
     } else {
         int open_group = -1;

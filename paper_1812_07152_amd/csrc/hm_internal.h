@@ -108,6 +108,20 @@ struct MatDesc {
     const void *store;
     void *buf[4];
     int64_t ldq;
+    const Seg *segs;
+};
+
+// One matrix's permutes in a batched launch.
+struct PermDesc {
+    const void *W;
+    int64_t ldw;
+    void *Y;
+    int64_t ldy;
+    void *Wt;
+    const void *Yt;
+    int64_t ldq;
+    const int64_t *perm;
+    int64_t N, Q;
 };
 
 // A node-level job of the evaluation's dependency graph (host side).
@@ -202,15 +216,26 @@ hipError_t launch_permute_out(const void *Yt, int64_t Qp, void *Y, int64_t ldy, 
 hipError_t launch_convert_f64_to_f32(const double *src, float *dst, int64_t n, hipStream_t s);
 hipError_t launch_repack(const double *stage, const RepackJob *jobs, int njobs, double *store,
                          hipStream_t s);
+// Batched row gather (in = true: W -> Wt) or scatter (Yt -> Y) for n matrices;
+// max_elems bounds N * ldq over the batch.
+hipError_t launch_permute_batched(const PermDesc *d, int n, int64_t max_elems, int elem_bytes,
+                                  bool in, hipStream_t s);
 // Persistent launch of a plan (init + graph kernel) on stream s.
-hipError_t launch_persistent(const GraphPlan &plan, int elem_bytes, const Seg *segs,
-                             const MatDesc *d_mat, int32_t *d_head, int grid, hipStream_t s);
+hipError_t launch_persistent(const GraphPlan &plan, int elem_bytes, const MatDesc *d_mat,
+                             int32_t *d_head, int grid, hipStream_t s);
 // Resident workgroups per CU of the persistent kernel for (elem_bytes, bn).
 int persistent_occupancy(int elem_bytes, int bn);
 
 // Expand the job graph for Q columns with column tile bn, order it by list
 // scheduling on `workers` simulated workgroups, and upload it (hm_sched.hip).
 hm_status make_plan(hm_matrix h, int slot, int bn, int64_t Q, int64_t ldq, int workers);
+// One matrix's share of a (possibly multi-matrix) plan.
+struct PlanPart {
+    hm_matrix h;
+    int mat;  // index in the MatDesc table
+    int nq;   // column tiles
+};
+hm_status build_plan(const std::vector<PlanPart> &parts, int bn, int workers, GraphPlan &plan);
 void free_plan(GraphPlan &p);
 
 }  // namespace hm

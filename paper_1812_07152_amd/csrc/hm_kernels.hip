@@ -247,8 +247,7 @@ constexpr int kWaitLimit = 1 << 20;  // polls (each followed by a sleep) before 
 template <typename T, int BN>
 __global__ __launch_bounds__(kPersistThreads) void k_persistent(
     const PTask *__restrict__ tasks, int n_tasks, const int32_t *__restrict__ succ,
-    int32_t *counters, int32_t *head, int32_t *err, const Seg *__restrict__ segs,
-    const MatDesc *__restrict__ mats) {
+    int32_t *counters, int32_t *head, int32_t *err, const MatDesc *__restrict__ mats) {
     __shared__ __attribute__((aligned(16))) T As[2 * kBK * (128 + lds_pad<T>())];
     __shared__ __attribute__((aligned(16))) T Bs[2 * kBK * (BN + lds_pad<T>())];
     __shared__ int s_t;
@@ -274,6 +273,7 @@ __global__ __launch_bounds__(kPersistThreads) void k_persistent(
         const TileJob job{pt.out_row, pt.out_buf, pt.M, pt.m0, pt.seg_begin, pt.seg_end, pt.accumulate};
         const int64_t n0 = (int64_t)pt.qtile * BN;
         const T *store = (const T *)md.store;
+        const Seg *segs = md.segs;
         if (pt.bm == 128)
             block_product<T, 128, BN, PLayout<128, BN>::WMv, PLayout<128, BN>::WN, kPersistThreads>(
                 job, segs, store, (T *)md.buf[0], (T *)md.buf[1], (T *)md.buf[2], (T *)md.buf[3],
@@ -361,6 +361,35 @@ __global__ void k_repack(const double *__restrict__ stage, const RepackJob *__re
     }
 }
 
+// Batched permutes: blockIdx.y selects the matrix.
+template <typename T>
+__global__ void k_permute_in_batched(const PermDesc *__restrict__ d) {
+    const PermDesc pd = d[blockIdx.y];
+    const int64_t total = pd.N * pd.ldq;
+    const T *W = (const T *)pd.W;
+    T *Wt = (T *)pd.Wt;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t t = e / pd.ldq, c = e % pd.ldq;
+        const int64_t src = pd.perm ? pd.perm[t] : t;
+        Wt[e] = c < pd.Q ? W[src * pd.ldw + c] : T(0);
+    }
+}
+
+template <typename T>
+__global__ void k_permute_out_batched(const PermDesc *__restrict__ d) {
+    const PermDesc pd = d[blockIdx.y];
+    const int64_t total = pd.N * pd.Q;
+    const T *Yt = (const T *)pd.Yt;
+    T *Y = (T *)pd.Y;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t t = e / pd.Q, c = e % pd.Q;
+        const int64_t dst = pd.perm ? pd.perm[t] : t;
+        Y[dst * pd.ldy + c] = Yt[t * pd.ldq + c];
+    }
+}
+
 __global__ void k_f64_to_f32(const double *__restrict__ s, float *__restrict__ d, int64_t n) {
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
          e += (int64_t)gridDim.x * blockDim.x)
@@ -430,25 +459,25 @@ hipError_t launch_phase(const hm_matrix_s *h, const Phase &ph, int elem_bytes, i
 namespace {
 
 template <typename T, int BN>
-hipError_t run_persistent(const GraphPlan &plan, const Seg *segs, const MatDesc *mats,
-                          int32_t *head, int grid, hipStream_t s) {
+hipError_t run_persistent(const GraphPlan &plan, const MatDesc *mats, int32_t *head, int grid,
+                          hipStream_t s) {
     const int nt = plan.n_tasks;
     hipLaunchKernelGGL(k_persistent_init, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s,
                        plan.d_tasks, nt, plan.d_counters, head);
     hipLaunchKernelGGL((k_persistent<T, BN>), dim3((unsigned)grid), dim3(kPersistThreads), 0, s,
-                       plan.d_tasks, nt, plan.d_succ, plan.d_counters, head, head + 1, segs, mats);
+                       plan.d_tasks, nt, plan.d_succ, plan.d_counters, head, head + 1, mats);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t persistent_bn(const GraphPlan &plan, const Seg *segs, const MatDesc *mats, int32_t *head,
-                         int grid, hipStream_t s) {
+hipError_t persistent_bn(const GraphPlan &plan, const MatDesc *mats, int32_t *head, int grid,
+                         hipStream_t s) {
     switch (plan.bn) {
-        case 16: return run_persistent<T, 16>(plan, segs, mats, head, grid, s);
-        case 32: return run_persistent<T, 32>(plan, segs, mats, head, grid, s);
-        case 64: return run_persistent<T, 64>(plan, segs, mats, head, grid, s);
-        case 128: return run_persistent<T, 128>(plan, segs, mats, head, grid, s);
-        default: return run_persistent<T, 256>(plan, segs, mats, head, grid, s);
+        case 16: return run_persistent<T, 16>(plan, mats, head, grid, s);
+        case 32: return run_persistent<T, 32>(plan, mats, head, grid, s);
+        case 64: return run_persistent<T, 64>(plan, mats, head, grid, s);
+        case 128: return run_persistent<T, 128>(plan, mats, head, grid, s);
+        default: return run_persistent<T, 256>(plan, mats, head, grid, s);
     }
 }
 
@@ -468,11 +497,11 @@ int occupancy_bn(int bn) {
 
 }  // namespace
 
-hipError_t launch_persistent(const GraphPlan &plan, int elem_bytes, const Seg *segs,
-                             const MatDesc *d_mat, int32_t *d_head, int grid, hipStream_t s) {
+hipError_t launch_persistent(const GraphPlan &plan, int elem_bytes, const MatDesc *d_mat,
+                             int32_t *d_head, int grid, hipStream_t s) {
     if (plan.n_tasks == 0) return hipSuccess;
-    return elem_bytes == 8 ? persistent_bn<double>(plan, segs, d_mat, d_head, grid, s)
-                           : persistent_bn<float>(plan, segs, d_mat, d_head, grid, s);
+    return elem_bytes == 8 ? persistent_bn<double>(plan, d_mat, d_head, grid, s)
+                           : persistent_bn<float>(plan, d_mat, d_head, grid, s);
 }
 
 int persistent_occupancy(int elem_bytes, int bn) {
@@ -500,6 +529,24 @@ hipError_t launch_permute_out(const void *Yt, int64_t Qp, void *Y, int64_t ldy, 
     else
         hipLaunchKernelGGL(k_permute_out<float>, dim3(g), dim3(256), 0, s, (const float *)Yt, Qp,
                            (float *)Y, ldy, perm, N, Q);
+    return hipGetLastError();
+}
+
+hipError_t launch_permute_batched(const PermDesc *d, int n, int64_t max_elems, int elem_bytes,
+                                  bool in, hipStream_t s) {
+    const dim3 grid((unsigned)std::min<int64_t>(std::max<int64_t>((max_elems + 255) / 256, 1), 2048),
+                    (unsigned)n);
+    if (in) {
+        if (elem_bytes == 8)
+            hipLaunchKernelGGL(k_permute_in_batched<double>, grid, dim3(256), 0, s, d);
+        else
+            hipLaunchKernelGGL(k_permute_in_batched<float>, grid, dim3(256), 0, s, d);
+    } else {
+        if (elem_bytes == 8)
+            hipLaunchKernelGGL(k_permute_out_batched<double>, grid, dim3(256), 0, s, d);
+        else
+            hipLaunchKernelGGL(k_permute_out_batched<float>, grid, dim3(256), 0, s, d);
+    }
     return hipGetLastError();
 }
 

@@ -23,55 +23,80 @@ void free_plan(GraphPlan &p) {
     p = GraphPlan{};
 }
 
-hm_status make_plan(hm_matrix h, int slot, int bn, int64_t Q, int64_t ldq, int workers) {
-    GraphPlan &plan = h->plan[slot];
-    const std::vector<GJob> &jobs = h->gjobs;
-    const int nj = (int)jobs.size();
-    const int nq = (int)(ldq / bn);
-    // row tiles per job
-    std::vector<int32_t> rows(nj), bm(nj), first(nj + 1, 0);
-    for (int j = 0; j < nj; j++) {
-        bm[j] = jobs[j].M <= 64 ? 64 : 128;
-        rows[j] = std::max(1, (jobs[j].M + bm[j] - 1) / bm[j]);
-        first[j + 1] = first[j] + rows[j];
+hm_status build_plan(const std::vector<PlanPart> &parts, int bn, int workers, GraphPlan &plan) {
+    // per part: row tiles per job, entry offsets
+    struct P {
+        const std::vector<GJob> *jobs;
+        int mat, nq, per_q;
+        int64_t base;
+        std::vector<int32_t> rows, bm, first;
+        std::vector<std::vector<int32_t>> succ_jobs;
+        std::vector<double> cost, blevel;  // per local entry (one column tile)
+    };
+    std::vector<P> ps(parts.size());
+    int64_t total64 = 0;
+    const double overhead = 2.0 * 128 * 64 * 256;  // fixed per-entry cost, in flops
+    for (size_t i = 0; i < parts.size(); i++) {
+        P &p = ps[i];
+        p.jobs = &parts[i].h->gjobs;
+        p.mat = parts[i].mat;
+        p.nq = parts[i].nq;
+        const std::vector<GJob> &jobs = *p.jobs;
+        const int nj = (int)jobs.size();
+        p.rows.resize(nj);
+        p.bm.resize(nj);
+        p.first.assign(nj + 1, 0);
+        for (int j = 0; j < nj; j++) {
+            p.bm[j] = jobs[j].M <= 64 ? 64 : 128;
+            p.rows[j] = std::max(1, (jobs[j].M + p.bm[j] - 1) / p.bm[j]);
+            p.first[j + 1] = p.first[j] + p.rows[j];
+        }
+        p.per_q = p.first[nj];
+        p.base = total64;
+        total64 += (int64_t)p.per_q * p.nq;
+        p.succ_jobs.assign(nj, {});
+        for (int j = 0; j < nj; j++)
+            for (int32_t q : jobs[j].preds) p.succ_jobs[q].push_back(j);
+        p.cost.resize(p.per_q);
+        p.blevel.resize(p.per_q);
+        for (int j = 0; j < nj; j++)
+            for (int r = 0; r < p.rows[j]; r++)
+                p.cost[p.first[j] + r] = 2.0 * p.bm[j] * jobs[j].kpad * bn + overhead;
+        // critical path to the end of the graph (jobs are topologically ordered)
+        std::vector<double> jbl(nj, 0.0);
+        for (int j = nj - 1; j >= 0; j--) {
+            double m = 0.0;
+            for (int32_t s2 : p.succ_jobs[j]) m = std::max(m, jbl[s2]);
+            jbl[j] = p.cost[p.first[j]] + m;
+            for (int r = 0; r < p.rows[j]; r++) p.blevel[p.first[j] + r] = jbl[j];
+        }
     }
-    const int per_q = first[nj];
-    const int64_t total64 = (int64_t)per_q * nq;
-    if (total64 > (int64_t)1 << 30) return fail(HM_ERR_INVALID, "hm_eval: task graph too large");
+    if (total64 > (int64_t)1 << 30) return fail(HM_ERR_INVALID, "task graph too large");
     const int total = (int)total64;
-    std::vector<std::vector<int32_t>> succ_jobs(nj);
-    for (int j = 0; j < nj; j++)
-        for (int32_t p : jobs[j].preds) succ_jobs[p].push_back(j);
-
-    // work model: padded flops plus a fixed per-entry overhead (in flops)
-    const double overhead = 2.0 * 128 * 64 * 256;
-    std::vector<double> cost(per_q), blevel(per_q);
-    for (int j = 0; j < nj; j++)
-        for (int r = 0; r < rows[j]; r++) cost[first[j] + r] = 2.0 * bm[j] * jobs[j].kpad * bn + overhead;
-    // critical path to the end of the graph (jobs are topologically ordered)
-    std::vector<double> job_bl(nj, 0.0);
-    for (int j = nj - 1; j >= 0; j--) {
-        double m = 0.0;
-        for (int32_t s : succ_jobs[j]) m = std::max(m, job_bl[s]);
-        job_bl[j] = cost[first[j]] + m;
-        for (int r = 0; r < rows[j]; r++) blevel[first[j] + r] = job_bl[j];
-    }
-
-    // entry e = q * per_q + first[j] + r; dependencies per entry
-    auto job_of = [&](int local) {
-        return (int)(std::upper_bound(first.begin(), first.end(), local) - first.begin()) - 1;
+    // global entry -> (part, column tile, job, row)
+    auto locate = [&](int e, int &pi, int &q, int &j, int &r) {
+        pi = 0;
+        while (pi + 1 < (int)ps.size() && ps[pi + 1].base <= e) pi++;
+        const P &p = ps[pi];
+        const int loc = (int)(e - p.base);
+        q = loc / p.per_q;
+        const int l = loc % p.per_q;
+        j = (int)(std::upper_bound(p.first.begin(), p.first.end(), l) - p.first.begin()) - 1;
+        r = l - p.first[j];
     };
     std::vector<int32_t> remaining(total);
-    for (int q = 0; q < nq; q++)
-        for (int j = 0; j < nj; j++) {
-            int nd = 0;
-            for (int32_t p : jobs[j].preds) nd += rows[p];
-            for (int r = 0; r < rows[j]; r++) remaining[q * per_q + first[j] + r] = nd;
-        }
-    std::vector<int32_t> ndeps = remaining;
+    for (const P &p : ps)
+        for (int q = 0; q < p.nq; q++)
+            for (size_t j = 0; j < p.jobs->size(); j++) {
+                int nd = 0;
+                for (int32_t pr : (*p.jobs)[j].preds) nd += p.rows[pr];
+                for (int r = 0; r < p.rows[j]; r++)
+                    remaining[p.base + (int64_t)q * p.per_q + p.first[j] + r] = nd;
+            }
+    const std::vector<int32_t> ndeps = remaining;
 
-    // list scheduling: earliest-free simulated workgroup takes the released
-    // entry of largest critical path
+    // list scheduling: the earliest-free simulated workgroup takes the
+    // released entry with the longest critical path
     struct Avail {
         double bl;
         int e;
@@ -82,19 +107,31 @@ hm_status make_plan(hm_matrix h, int slot, int bn, int64_t Q, int64_t ldq, int w
     std::priority_queue<Ev, std::vector<Ev>, std::greater<Ev>> finishes;
     std::priority_queue<double, std::vector<double>, std::greater<double>> free_at;
     for (int w = 0; w < std::max(workers, 1); w++) free_at.push(0.0);
+    auto blevel_of = [&](int e) {
+        int pi, q, j, r;
+        locate(e, pi, q, j, r);
+        return ps[pi].blevel[ps[pi].first[j] + r];
+    };
+    auto cost_of = [&](int e) {
+        int pi, q, j, r;
+        locate(e, pi, q, j, r);
+        return ps[pi].cost[ps[pi].first[j] + r];
+    };
     for (int e = 0; e < total; e++)
-        if (remaining[e] == 0) avail.push({blevel[e % per_q], e});
+        if (remaining[e] == 0) avail.push({blevel_of(e), e});
+    auto release = [&](int e) {
+        int pi, q, j, r;
+        locate(e, pi, q, j, r);
+        const P &p = ps[pi];
+        for (int32_t s2 : p.succ_jobs[j])
+            for (int rr = 0; rr < p.rows[s2]; rr++) {
+                const int f = (int)(p.base + (int64_t)q * p.per_q + p.first[s2] + rr);
+                if (--remaining[f] == 0) avail.push({p.blevel[p.first[s2] + rr], f});
+            }
+    };
     std::vector<int32_t> order;
     order.reserve(total);
     double makespan = 0.0;
-    auto release = [&](int e) {
-        const int q = e / per_q, j = job_of(e % per_q);
-        for (int32_t s : succ_jobs[j])
-            for (int r = 0; r < rows[s]; r++) {
-                const int f = q * per_q + first[s] + r;
-                if (--remaining[f] == 0) avail.push({blevel[first[s] + r], f});
-            }
-    };
     while ((int)order.size() < total) {
         double t = free_at.top();
         while (!finishes.empty() && finishes.top().first <= t) {
@@ -115,7 +152,7 @@ hm_status make_plan(hm_matrix h, int slot, int bn, int64_t Q, int64_t ldq, int w
         const Avail a = avail.top();
         avail.pop();
         free_at.pop();
-        const double fin = t + cost[a.e % per_q];
+        const double fin = t + cost_of(a.e);
         free_at.push(fin);
         finishes.push({fin, a.e});
         makespan = std::max(makespan, fin);
@@ -128,23 +165,27 @@ hm_status make_plan(hm_matrix h, int slot, int bn, int64_t Q, int64_t ldq, int w
     std::vector<PTask> tasks(total);
     std::vector<int32_t> succ;
     for (int i = 0; i < total; i++) {
-        const int e = order[i], q = e / per_q, loc = e % per_q, j = job_of(loc), r = loc - first[j];
-        const GJob &g = jobs[j];
+        const int e = order[i];
+        int pi, q, j, r;
+        locate(e, pi, q, j, r);
+        const P &p = ps[pi];
+        const GJob &g = (*p.jobs)[j];
         PTask t{};
-        t.out_row = g.out_row + (int64_t)r * bm[j];
+        t.out_row = g.out_row + (int64_t)r * p.bm[j];
         t.out_buf = g.out_buf;
-        t.M = std::min(bm[j], g.M - r * bm[j]);
-        t.m0 = r * bm[j];
+        t.M = std::min(p.bm[j], g.M - r * p.bm[j]);
+        t.m0 = r * p.bm[j];
         t.seg_begin = g.seg_begin;
         t.seg_end = g.seg_end;
-        t.bm = bm[j];
+        t.bm = p.bm[j];
         t.accumulate = g.accumulate;
         t.qtile = q;
-        t.mat = 0;
+        t.mat = p.mat;
         t.ndeps = ndeps[e];
         t.succ_begin = (int32_t)succ.size();
-        for (int32_t s : succ_jobs[j])
-            for (int rr = 0; rr < rows[s]; rr++) succ.push_back(pos[q * per_q + first[s] + rr]);
+        for (int32_t s2 : p.succ_jobs[j])
+            for (int rr = 0; rr < p.rows[s2]; rr++)
+                succ.push_back(pos[p.base + (int64_t)q * p.per_q + p.first[s2] + rr]);
         t.succ_end = (int32_t)succ.size();
         tasks[i] = t;
     }
@@ -160,13 +201,19 @@ hm_status make_plan(hm_matrix h, int slot, int bn, int64_t Q, int64_t ldq, int w
     if (err != hipSuccess) {
         free_plan(plan);
         return fail(err == hipErrorOutOfMemory ? HM_ERR_NOMEM : HM_ERR_DEVICE,
-                    std::string("hm_eval: uploading the task graph: ") + hipGetErrorString(err));
+                    std::string("uploading the task graph: ") + hipGetErrorString(err));
     }
     plan.bn = bn;
-    plan.Q = Q;
     plan.n_tasks = total;
     plan.est_ms = makespan;
     return HM_OK;
+}
+
+hm_status make_plan(hm_matrix h, int slot, int bn, int64_t Q, int64_t ldq, int workers) {
+    std::vector<PlanPart> parts{{h, 0, (int)(ldq / bn)}};
+    hm_status st = build_plan(parts, bn, workers, h->plan[slot]);
+    if (st == HM_OK) h->plan[slot].Q = Q;
+    return st;
 }
 
 }  // namespace hm

@@ -19,6 +19,7 @@ HM_ERR_DEVICE, HM_ERR_BUSY, HM_ERR_PENDING, HM_ERR_INTERNAL = -4, -5, -6, -7
 HM_F64, HM_F32 = 0, 1
 HM_PREC_FP64, HM_PREC_FP32 = 0, 1
 HM_TREE_ORDER, HM_PROFILE = 1, 2
+HM_BATCH_AUTOTUNE, HM_BATCH_NO_GRAPH = 1, 2
 STATUS_NAMES = {0: "HM_OK", -1: "HM_ERR_INVALID", -2: "HM_ERR_FORMAT", -3: "HM_ERR_NOMEM",
                 -4: "HM_ERR_DEVICE", -5: "HM_ERR_BUSY", -6: "HM_ERR_PENDING", -7: "HM_ERR_INTERNAL"}
 
@@ -57,6 +58,12 @@ class hm_compress_opts(ctypes.Structure):
                 ("threads", ctypes.c_int32)]
 
 
+class hm_batch_info_t(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("column_tile", ctypes.c_int32), ("n_tasks", ctypes.c_int32),
+                ("workgroups", ctypes.c_int32), ("flops", ctypes.c_double),
+                ("tuned_ms", ctypes.c_double * 5), ("workspace_bytes", ctypes.c_double)]
+
+
 class hm_info_t(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int64), ("n_nodes", ctypes.c_int32), ("depth", ctypes.c_int32),
                 ("max_rank", ctypes.c_int32), ("device", ctypes.c_int32), ("n_far", ctypes.c_int64),
@@ -91,6 +98,22 @@ def _load():
     L.hm_profile_reset.argtypes = [_P]
     L.hm_check.restype = st
     L.hm_check.argtypes = [_P]
+    _PP = ctypes.POINTER(_P)
+    _I64P = ctypes.POINTER(ctypes.c_int64)
+    L.hm_batch_create.restype = st
+    L.hm_batch_create.argtypes = [ctypes.c_int, _PP, _I64P, ctypes.c_int, ctypes.c_int, ctypes.c_uint,
+                                  ctypes.POINTER(_P)]
+    L.hm_batch_eval.restype = st
+    L.hm_batch_eval.argtypes = [_P, _PP, _I64P, _PP, _I64P, _P]
+    L.hm_batch_info.restype = st
+    L.hm_batch_info.argtypes = [_P, ctypes.POINTER(hm_batch_info_t)]
+    L.hm_batch_check.restype = st
+    L.hm_batch_check.argtypes = [_P]
+    L.hm_batch_free.restype = st
+    L.hm_batch_free.argtypes = [_P]
+    L.hm_eval_batched.restype = st
+    L.hm_eval_batched.argtypes = [ctypes.c_int, _PP, _PP, _I64P, _PP, _I64P, _I64P, ctypes.c_int,
+                                  ctypes.c_int, _P]
     L.hm_compress.restype = st
     L.hm_compress.argtypes = [_P, ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(hm_compress_opts),
                               ctypes.POINTER(_P)]
@@ -289,6 +312,86 @@ def hm_eval(h: Matrix, W, Y, Q: int | None = None, prec: int | None = None, flag
 def hm_check(h: Matrix) -> None:
     """Synchronize and raise if a persistent launch's bounded wait expired."""
     _check(lib.hm_check(h))
+
+
+class Batch:
+    """Owning wrapper of an hm_batch handle (keeps its matrices alive)."""
+
+    def __init__(self, handle: int, mats, Q):
+        self.handle, self.mats, self.Q = handle, list(mats), list(Q)
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            lib.hm_batch_free(self.handle)
+            self.handle = None
+
+
+def _ptrs(xs):
+    return (_P * len(xs))(*xs)
+
+
+def _i64s(xs):
+    return (ctypes.c_int64 * len(xs))(*[int(x) for x in xs])
+
+
+def hm_batch_create(mats, Q, dtype: int = HM_F64, prec: int | None = None, flags: int = 0) -> Batch:
+    if prec is None:
+        prec = HM_PREC_FP64 if dtype == HM_F64 else HM_PREC_FP32
+    out = _P()
+    _check(lib.hm_batch_create(len(mats), _ptrs([m.handle for m in mats]), _i64s(Q), dtype, prec, flags,
+                               ctypes.byref(out)))
+    return Batch(out.value, mats, Q)
+
+
+def _check_tensors(mats, Ws, Ys, Qs):
+    import torch
+    if not (len(mats) == len(Ws) == len(Ys) == len(Qs)):
+        raise ValueError("one W, Y and Q per matrix")
+    for m, W, Y, q in zip(mats, Ws, Ys, Qs):
+        info = hm_info(m)
+        if not (W.is_cuda and Y.is_cuda) or W.dtype != Y.dtype or W.dtype not in (torch.float64, torch.float32):
+            raise ValueError("W and Y must be device tensors of one float dtype")
+        if W.dim() != 2 or Y.dim() != 2 or W.stride(1) != 1 or Y.stride(1) != 1:
+            raise ValueError("W and Y must be 2-D with unit column stride")
+        if W.shape[0] < info["N"] or Y.shape[0] < info["N"] or W.shape[1] < q or Y.shape[1] < q:
+            raise ValueError("W and Y too small for the matrix and width")
+
+
+def hm_batch_eval(b: Batch, Ws, Ys, stream=None) -> None:
+    _check_tensors(b.mats, Ws, Ys, b.Q)
+    _check(lib.hm_batch_eval(b.handle, _ptrs([w.data_ptr() for w in Ws]), _i64s([w.stride(0) for w in Ws]),
+                             _ptrs([y.data_ptr() for y in Ys]), _i64s([y.stride(0) for y in Ys]),
+                             _stream_ptr(stream)))
+
+
+def hm_batch_info(b: Batch) -> dict:
+    info = hm_batch_info_t()
+    _check(lib.hm_batch_info(b.handle, ctypes.byref(info)))
+    d = {name: getattr(info, name) for name, _ in hm_batch_info_t._fields_}
+    d["tuned_ms"] = dict(zip((16, 32, 64, 128, 256), list(info.tuned_ms)))
+    return d
+
+
+def hm_batch_check(b: Batch) -> None:
+    _check(lib.hm_batch_check(b.handle))
+
+
+def hm_batch_free(b: Batch) -> None:
+    if b.handle:
+        _check(lib.hm_batch_free(b.handle))
+        b.handle = None
+
+
+def hm_eval_batched(mats, Ws, Ys, Q=None, prec: int | None = None, stream=None) -> None:
+    import torch
+    Q = [w.shape[1] for w in Ws] if Q is None else list(Q)
+    _check_tensors(mats, Ws, Ys, Q)
+    dtype = HM_F64 if Ws[0].dtype == torch.float64 else HM_F32
+    if prec is None:
+        prec = HM_PREC_FP64 if dtype == HM_F64 else HM_PREC_FP32
+    _check(lib.hm_eval_batched(len(mats), _ptrs([m.handle for m in mats]), _ptrs([w.data_ptr() for w in Ws]),
+                               _i64s([w.stride(0) for w in Ws]), _ptrs([y.data_ptr() for y in Ys]),
+                               _i64s([y.stride(0) for y in Ys]), _i64s(Q), dtype, prec, _stream_ptr(stream)))
 
 
 def hm_profile_read(h: Matrix):
