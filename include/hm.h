@@ -199,6 +199,49 @@ hm_status hm_eval_batched(int n, const hm_matrix *hs, const void *const *W, cons
                           hm_prec prec, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * Serving: several compressed matrices resident in HBM, requests of any width
+ * Q in [1, 1024] submitted without blocking and served by continuous
+ * batching.  A server thread coalesces the pending requests of a matrix
+ * column-wise into one sweep (one evaluation of up to 1024 columns) whenever
+ * the matrix has no sweep in flight, a slot (stream) is free and the HBM
+ * budget (packed W and Y of the sweeps in flight) allows it; requests that
+ * arrive while a sweep of their matrix runs join the next one, and sweeps of
+ * different matrices run on different streams and overlap on the device.  A
+ * result is bitwise the same alone and in the mix (column j of Y depends only
+ * on column j of W).  Add every matrix before submitting work; the matrices
+ * must outlive the server, and hm_eval must not be called on them while the
+ * server runs (they share workspaces). */
+typedef struct hm_server_s *hm_server;
+typedef uint64_t hm_ticket;
+
+typedef struct {
+    int64_t completed, failed, sweeps, columns, pending;
+    int32_t inflight, peak_inflight;
+    double peak_bytes;        /* largest HBM the packed sweeps held at once */
+} hm_server_stats_t;
+
+/* max_slots: sweeps in flight at once (1..16); hbm_budget: bytes for packed
+ * W/Y of sweeps in flight; dtype/prec as for hm_eval. */
+hm_status hm_server_create(int device, size_t hbm_budget, int max_slots, hm_dtype dtype,
+                           hm_prec prec, hm_server *out);
+/* Make h resident (reserves its workspaces and launch plans for every sweep
+ * width, so that sweeps never allocate); *mat_id names it in hm_submit. */
+hm_status hm_server_add(hm_server s, hm_matrix h, int *mat_id);
+/* Queue Y = K~ W for matrix mat_id (device pointers, N x Q row-major; they
+ * must stay valid until hm_poll reports done).  Never blocks; HM_ERR_BUSY when
+ * the request can never fit the budget or too many requests are queued. */
+hm_status hm_submit(hm_server s, int mat_id, const void *W, int64_t ldw, void *Y, int64_t ldy,
+                    int64_t Q, hm_ticket *out);
+/* *done = 1 once Y is written (then *latency_us = submit-to-completion time
+ * and the ticket is retired); *done = 0 while pending.  HM_ERR_INVALID for an
+ * unknown or retired ticket. */
+hm_status hm_poll(hm_server s, hm_ticket t, int *done, double *latency_us);
+hm_status hm_server_stats(hm_server s, hm_server_stats_t *out);
+/* Stop the server thread and wait for the sweeps in flight; queued requests
+ * that never started are dropped. */
+hm_status hm_server_destroy(hm_server s);
+
+/* ---------------------------------------------------------------------------
  * Inspector: host-side compression of a point set into the representation
  * above (the compression phase of the paper, Section 3.1: tree construction,
  * interaction computation, sampling, ID low-rank approximation).  Runs on the

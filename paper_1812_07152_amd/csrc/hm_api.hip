@@ -56,6 +56,21 @@ hm_status ensure_ws(hm_matrix h, int slot, int b, size_t bytes) {
     return HM_OK;
 }
 
+}  // namespace
+
+hm_status reserve_ws(hm_matrix h, int slot, int64_t ldq) {
+    const int es = slot == 0 ? 8 : 4;
+    const size_t rows[BUF_COUNT] = {(size_t)h->N, (size_t)h->N, (size_t)h->skel_rows,
+                                    (size_t)h->skel_rows};
+    for (int b = 0; b < BUF_COUNT; b++) {
+        hm_status st = ensure_ws(h, slot, b, rows[b] * (size_t)ldq * es);
+        if (st != HM_OK) return st;
+    }
+    return HM_OK;
+}
+
+namespace {
+
 // Phase group of a Phase.kind for profiling: 1 up, 2 down, 3 leaf.
 int group_of(int kind) { return kind; }
 
@@ -135,8 +150,8 @@ hm_status hm_free(hm_matrix h) {
         for (int b = 0; b < BUF_COUNT; b++)
             if (h->ws[s][b]) (void)hipFree(h->ws[s][b]);
     if (h->d_perm) (void)hipFree(h->d_perm);
-    free_plan(h->plan[0]);
-    free_plan(h->plan[1]);
+    for (int k = 0; k < 2; k++)
+        for (GraphPlan &p : h->plans[k]) free_plan(p);
     if (h->d_mat) (void)hipFree(h->d_mat);
     if (h->d_head) (void)hipFree(h->d_head);
     if (h->d_tasks) (void)hipFree(h->d_tasks);
@@ -172,10 +187,8 @@ hm_status hm_eval(hm_matrix h, const void *W, int64_t ldw, void *Y, int64_t ldy,
     if (!level_sched) bn_kind[1] = bn_kind[2] = bn_kind[3];  // one tile for the whole graph
     const int bn_max = std::max({bn_kind[1], bn_kind[2], bn_kind[3]});
     const int64_t Qp = (Q + bn_max - 1) / bn_max * bn_max;  // workspace leading dimension
-    const size_t rows[BUF_COUNT] = {(size_t)h->N, (size_t)h->N, (size_t)h->skel_rows,
-                                    (size_t)h->skel_rows};
-    for (int b = 0; b < BUF_COUNT; b++) {
-        hm_status st = ensure_ws(h, slot, b, rows[b] * (size_t)Qp * es);
+    {
+        hm_status st = reserve_ws(h, slot, Qp);
         if (st != HM_OK) return st;
     }
     void *bufs[BUF_COUNT];
@@ -184,15 +197,12 @@ hm_status hm_eval(hm_matrix h, const void *W, int64_t ldw, void *Y, int64_t ldy,
     const int64_t *perm = (flags & HM_TREE_ORDER) ? nullptr : h->d_perm;
 
     int grid = 0;
+    GraphPlan *plan = nullptr;
     if (!level_sched) {
         const int occ = persistent_occupancy(es, bn_kind[3]);
         const int workers = std::max(1, occ * h->n_cu);
-        GraphPlan &plan = h->plan[slot];
-        if (plan.bn != bn_kind[3] || plan.Q != Qp) {
-            HM_HIP(hipStreamSynchronize(s));
-            hm_status st = make_plan(h, slot, bn_kind[3], Qp, Qp, workers);
-            if (st != HM_OK) return st;
-        }
+        hm_status pst = get_plan(h, slot, bn_kind[3], Qp, workers, &plan);
+        if (pst != HM_OK) return pst;
         MatDesc md{h->prec[prec].blocks, {bufs[0], bufs[1], bufs[2], bufs[3]}, Qp, h->d_segs};
         MatDesc &cache = h->mat_cache[slot];
         if (std::memcmp(&md, &cache, sizeof(MatDesc)) != 0 || h->mat_slot != slot) {
@@ -201,7 +211,7 @@ hm_status hm_eval(hm_matrix h, const void *W, int64_t ldw, void *Y, int64_t ldy,
             cache = md;
             h->mat_slot = slot;
         }
-        grid = std::min(plan.n_tasks, workers);
+        grid = std::min(plan->n_tasks, workers);
     }
 
     auto mark = [&](int group, bool begin) -> hm_status {
@@ -223,7 +233,7 @@ hm_status hm_eval(hm_matrix h, const void *W, int64_t ldw, void *Y, int64_t ldy,
         // the whole graph (up, down, near, leaf far part) in one launch,
         // reported as the leaf-pass group
         if ((st = mark(3, true)) != HM_OK) return st;
-        HM_HIP(launch_persistent(h->plan[slot], es, h->d_mat, h->d_head, grid, s));
+        HM_HIP(launch_persistent(*plan, es, h->d_mat, h->d_head, grid, s));
         if ((st = mark(3, false)) != HM_OK) return st;
     } else {
         int open_group = -1;

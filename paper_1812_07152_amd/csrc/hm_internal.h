@@ -175,7 +175,7 @@ struct hm_matrix_s {
     hm::Seg *d_segs = nullptr;
     std::vector<hm::Phase> phases;
     std::vector<hm::GJob> gjobs;           // dependency graph of one evaluation
-    hm::GraphPlan plan[2];                 // per element size, for the last (Q, BN)
+    std::vector<hm::GraphPlan> plans[2];   // per element size: one plan per (tile, tile count)
     hm::MatDesc *d_mat = nullptr;          // one descriptor (persistent launch)
     hm::MatDesc mat_cache[2] = {};         // last uploaded descriptor per element size
     int mat_slot = -1;                     // element-size slot of the uploaded descriptor
@@ -228,7 +228,10 @@ int persistent_occupancy(int elem_bytes, int bn);
 
 // Expand the job graph for Q columns with column tile bn, order it by list
 // scheduling on `workers` simulated workgroups, and upload it (hm_sched.hip).
-hm_status make_plan(hm_matrix h, int slot, int bn, int64_t Q, int64_t ldq, int workers);
+// The plan of h for (bn, ldq / bn column tiles), built and cached on first use.
+hm_status get_plan(hm_matrix h, int slot, int bn, int64_t ldq, int workers, GraphPlan **out);
+// Grow h's workspaces for element-size slot to a leading dimension of ldq.
+hm_status reserve_ws(hm_matrix h, int slot, int64_t ldq);
 // One matrix's share of a (possibly multi-matrix) plan.
 struct PlanPart {
     hm_matrix h;

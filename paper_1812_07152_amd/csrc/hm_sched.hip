@@ -209,11 +209,25 @@ hm_status build_plan(const std::vector<PlanPart> &parts, int bn, int workers, Gr
     return HM_OK;
 }
 
-hm_status make_plan(hm_matrix h, int slot, int bn, int64_t Q, int64_t ldq, int workers) {
-    std::vector<PlanPart> parts{{h, 0, (int)(ldq / bn)}};
-    hm_status st = build_plan(parts, bn, workers, h->plan[slot]);
-    if (st == HM_OK) h->plan[slot].Q = Q;
-    return st;
+hm_status get_plan(hm_matrix h, int slot, int bn, int64_t ldq, int workers, GraphPlan **out) {
+    const int nq = (int)(ldq / bn);
+    for (GraphPlan &p : h->plans[slot])
+        if (p.bn == bn && p.Q == nq) {
+            *out = &p;
+            return HM_OK;
+        }
+    if (h->plans[slot].size() >= 16) {  // bounded cache: drop the oldest plan
+        free_plan(h->plans[slot].front());
+        h->plans[slot].erase(h->plans[slot].begin());
+    }
+    GraphPlan p;
+    std::vector<PlanPart> parts{{h, 0, nq}};
+    hm_status st = build_plan(parts, bn, workers, p);
+    if (st != HM_OK) return st;
+    p.Q = nq;  // cache key: column tiles
+    h->plans[slot].push_back(p);
+    *out = &h->plans[slot].back();
+    return HM_OK;
 }
 
 }  // namespace hm

@@ -64,6 +64,12 @@ class hm_batch_info_t(ctypes.Structure):
                 ("tuned_ms", ctypes.c_double * 5), ("workspace_bytes", ctypes.c_double)]
 
 
+class hm_server_stats_t(ctypes.Structure):
+    _fields_ = [("completed", ctypes.c_int64), ("failed", ctypes.c_int64), ("sweeps", ctypes.c_int64),
+                ("columns", ctypes.c_int64), ("pending", ctypes.c_int64), ("inflight", ctypes.c_int32),
+                ("peak_inflight", ctypes.c_int32), ("peak_bytes", ctypes.c_double)]
+
+
 class hm_info_t(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int64), ("n_nodes", ctypes.c_int32), ("depth", ctypes.c_int32),
                 ("max_rank", ctypes.c_int32), ("device", ctypes.c_int32), ("n_far", ctypes.c_int64),
@@ -111,6 +117,20 @@ def _load():
     L.hm_batch_check.argtypes = [_P]
     L.hm_batch_free.restype = st
     L.hm_batch_free.argtypes = [_P]
+    L.hm_server_create.restype = st
+    L.hm_server_create.argtypes = [ctypes.c_int, ctypes.c_size_t, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                   ctypes.POINTER(_P)]
+    L.hm_server_add.restype = st
+    L.hm_server_add.argtypes = [_P, _P, ctypes.POINTER(ctypes.c_int)]
+    L.hm_submit.restype = st
+    L.hm_submit.argtypes = [_P, ctypes.c_int, _P, ctypes.c_int64, _P, ctypes.c_int64, ctypes.c_int64,
+                            ctypes.POINTER(ctypes.c_uint64)]
+    L.hm_poll.restype = st
+    L.hm_poll.argtypes = [_P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]
+    L.hm_server_stats.restype = st
+    L.hm_server_stats.argtypes = [_P, ctypes.POINTER(hm_server_stats_t)]
+    L.hm_server_destroy.restype = st
+    L.hm_server_destroy.argtypes = [_P]
     L.hm_eval_batched.restype = st
     L.hm_eval_batched.argtypes = [ctypes.c_int, _PP, _PP, _I64P, _PP, _I64P, _I64P, ctypes.c_int,
                                   ctypes.c_int, _P]
@@ -392,6 +412,73 @@ def hm_eval_batched(mats, Ws, Ys, Q=None, prec: int | None = None, stream=None) 
     _check(lib.hm_eval_batched(len(mats), _ptrs([m.handle for m in mats]), _ptrs([w.data_ptr() for w in Ws]),
                                _i64s([w.stride(0) for w in Ws]), _ptrs([y.data_ptr() for y in Ys]),
                                _i64s([y.stride(0) for y in Ys]), _i64s(Q), dtype, prec, _stream_ptr(stream)))
+
+
+class Server:
+    """Owning wrapper of an hm_server (keeps resident matrices alive)."""
+
+    def __init__(self, handle: int, dtype: int):
+        self.handle, self.dtype, self.mats = handle, dtype, []
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            lib.hm_server_destroy(self.handle)
+            self.handle = None
+
+
+def hm_server_create(device: int = 0, hbm_budget: int = 8 << 30, max_slots: int = 4,
+                     dtype: int = HM_F32, prec: int | None = None) -> Server:
+    if prec is None:
+        prec = HM_PREC_FP64 if dtype == HM_F64 else HM_PREC_FP32
+    out = _P()
+    _check(lib.hm_server_create(device, hbm_budget, max_slots, dtype, prec, ctypes.byref(out)))
+    return Server(out.value, dtype)
+
+
+def hm_server_add(s: Server, h: Matrix) -> int:
+    mid = ctypes.c_int()
+    _check(lib.hm_server_add(s.handle, h.handle, ctypes.byref(mid)))
+    s.mats.append(h)
+    return mid.value
+
+
+def hm_submit(s: Server, mat_id: int, W, Y, Q: int | None = None) -> int:
+    """Queue Y = K~ W (device tensors; keep them alive until hm_poll says done)."""
+    import torch
+    want = torch.float64 if s.dtype == HM_F64 else torch.float32
+    if not (W.is_cuda and Y.is_cuda) or W.dtype != want or Y.dtype != want:
+        raise ValueError("hm_submit: W and Y must be device tensors of the server's dtype")
+    if W.dim() != 2 or Y.dim() != 2 or W.stride(1) != 1 or Y.stride(1) != 1:
+        raise ValueError("hm_submit: W and Y must be 2-D with unit column stride")
+    Q = W.shape[1] if Q is None else Q
+    if 0 <= mat_id < len(s.mats):  # unknown ids are rejected by the library itself
+        N = hm_info(s.mats[mat_id])["N"]
+        if W.shape[0] < N or Y.shape[0] < N or W.shape[1] < Q or Y.shape[1] < Q:
+            raise ValueError("hm_submit: tensors too small")
+    t = ctypes.c_uint64()
+    _check(lib.hm_submit(s.handle, mat_id, W.data_ptr(), W.stride(0), Y.data_ptr(), Y.stride(0), Q,
+                         ctypes.byref(t)))
+    return t.value
+
+
+def hm_poll(s: Server, ticket: int):
+    """(done, latency_us): latency is None while pending."""
+    done = ctypes.c_int()
+    lat = ctypes.c_double()
+    _check(lib.hm_poll(s.handle, ticket, ctypes.byref(done), ctypes.byref(lat)))
+    return bool(done.value), (lat.value if done.value else None)
+
+
+def hm_server_stats(s: Server) -> dict:
+    st = hm_server_stats_t()
+    _check(lib.hm_server_stats(s.handle, ctypes.byref(st)))
+    return {name: getattr(st, name) for name, _ in hm_server_stats_t._fields_}
+
+
+def hm_server_destroy(s: Server) -> None:
+    if s.handle:
+        _check(lib.hm_server_destroy(s.handle))
+        s.handle = None
 
 
 def hm_profile_read(h: Matrix):
