@@ -151,6 +151,123 @@ def bench_batched(args) -> dict:
     }
 
 
+def bench_serving(args) -> dict:
+    """Serving form: 8 resident matrices (N 16384..524288, d in {3, 8, 28},
+    H^2 and HSS, tol 1e-5), FP32, requests with Q ~ U{1..256} on a uniformly
+    chosen matrix.  Measures the served saturation throughput (a burst of
+    requests drained by the server) against the plain path (the same requests
+    one at a time with hm_eval), then p50/p99 latency under open-loop Poisson
+    arrivals at 25 / 50 / 80 % of the served saturation rate."""
+    import threading
+
+    import numpy as np
+    import torch
+
+    import paper_1812_07152_amd as hmx
+    import workloads as wl
+    specs = wl.serving_workloads()
+    t = time.perf_counter()
+    mats = []
+    for w in specs:
+        R = hmx.hm_compress(wl.gen_points(w), kernel=w.kernel, h=w.h, leaf_size=w.m, tol=w.tol,
+                            max_rank=w.rmax, admissibility=w.adm, tau=w.tau,
+                            sample_rows=w.sample_rows, seed=w.sample_seed)
+        mats.append(hmx.hm_load_compressed_mem(R, 0, hmx.precbit(hmx.HM_PREC_FP32)))
+        del R
+        print(f"[serving] built {w.name} ({time.perf_counter() - t:.0f} s)", file=sys.stderr, flush=True)
+    t_build = time.perf_counter() - t
+    infos = [hmx.hm_info(m) for m in mats]
+    Wsrc = [torch.randn(w.N, 256, device="cuda", dtype=torch.float32,
+                        generator=torch.Generator(device="cuda").manual_seed(w.w_seed)) for w in specs]
+    rng = np.random.default_rng(args.serving_seed)
+
+    def draw(n):
+        return [(int(rng.integers(0, len(specs))), int(rng.integers(1, 257))) for _ in range(n)]
+
+    def flops(reqs):
+        return sum(infos[m]["flops_per_col"] * q for m, q in reqs)
+
+    # plain path: one request at a time
+    burst = draw(args.burst)
+    for m, q in burst[:8]:
+        hmx.hm_eval(mats[m], Wsrc[m][:, :q], torch.empty(specs[m].N, q, device="cuda"))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for m, q in burst:
+        hmx.hm_eval(mats[m], Wsrc[m][:, :q], torch.empty(specs[m].N, q, device="cuda"))
+    torch.cuda.synchronize()
+    plain_s = time.perf_counter() - t0
+
+    S = hmx.hm_server_create(0, hbm_budget=24 << 30, max_slots=4, dtype=hmx.HM_F32)
+    ids = [hmx.hm_server_add(S, mt) for mt in mats]
+
+    def run(reqs, gaps):
+        """Submit reqs (after the given inter-arrival gaps, seconds) and poll
+        until all are done; returns (latencies in ms, wall seconds)."""
+        out = {}
+        pending = {}
+        lock = threading.Lock()
+
+        def producer():
+            t_next = time.perf_counter()
+            for (m, q), gap in zip(reqs, gaps):
+                t_next += gap
+                while time.perf_counter() < t_next:
+                    time.sleep(0.0001)
+                Y = torch.empty(specs[m].N, q, device="cuda")
+                tk = hmx.hm_submit(S, ids[m], Wsrc[m][:, :q], Y)
+                with lock:
+                    pending[tk] = Y
+        start = time.perf_counter()
+        th = threading.Thread(target=producer)
+        th.start()
+        deadline = start + 300
+        while len(out) < len(reqs):
+            assert time.perf_counter() < deadline, "serving run did not drain"
+            with lock:
+                tks = list(pending)
+            for tk in tks:
+                done, lat = hmx.hm_poll(S, tk)
+                if done:
+                    out[tk] = lat / 1e3
+                    with lock:
+                        del pending[tk]
+            time.sleep(0.0002)
+        th.join()
+        return list(out.values()), time.perf_counter() - start
+
+    run(draw(16), [0.0] * 16)                      # warm-up
+    lat, wall = run(burst, [0.0] * len(burst))    # saturation: everything at once
+    sat_rps = len(burst) / wall
+    levels = []
+    for frac in (0.25, 0.5, 0.8):
+        rate = frac * sat_rps
+        n = max(16, int(rate * args.serving_seconds))
+        reqs = draw(n)
+        gaps = list(rng.exponential(1.0 / rate, n))
+        lat, wall = run(reqs, gaps)
+        levels.append({"offered_rps": rate, "fraction_of_saturation": frac, "requests": n,
+                       "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                       "achieved_rps": n / wall, "gflops": flops(reqs) / wall / 1e9})
+    st = hmx.hm_server_stats(S)
+    hmx.hm_server_destroy(S)
+    return {
+        "metric": "served K~W throughput (GFLOP/s, algorithmic) and p50/p99 latency",
+        "value": flops(burst) / (len(burst) / sat_rps) / 1e9, "unit": "GFLOP/s", "n_gpus": 1,
+        "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "c5_8_resident_n16384_524288", "matrices": [w.name for w in specs],
+                   "Q": "U{1..256}", "burst_requests": len(burst), "slots": 4, "hbm_budget_gib": 24},
+        "saturation_rps": sat_rps,
+        "plain_per_request": {"rps": len(burst) / plain_s, "gflops": flops(burst) / plain_s / 1e9},
+        "speedup_vs_plain": (len(burst) / plain_s) and sat_rps / (len(burst) / plain_s),
+        "levels": levels,
+        "server": {"sweeps": st["sweeps"], "completed": st["completed"], "failed": st["failed"],
+                   "requests_per_sweep": st["completed"] / max(st["sweeps"], 1),
+                   "peak_inflight_sweeps": st["peak_inflight"], "peak_pack_gib": st["peak_bytes"] / 2**30},
+        "setup_s": {"compress_and_load": t_build},
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -158,8 +275,12 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
-    ap.add_argument("--form", choices=("plain", "batched"), default="plain",
-                    help="plain: the headline workload; batched: 64 uneven matrices in one launch")
+    ap.add_argument("--form", choices=("plain", "batched", "serving"), default="plain",
+                    help="plain: the headline workload; batched: 64 uneven matrices in one launch; "
+                         "serving: 8 resident matrices under a request stream")
+    ap.add_argument("--burst", type=int, default=128, help="serving: requests in the saturation burst")
+    ap.add_argument("--serving-seconds", type=float, default=3.0, help="serving: seconds per load level")
+    ap.add_argument("--serving-seed", type=int, default=4)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after timing, run one device copy of this many MiB (a kernel of "
                          "known traffic for calibrating HBM counters)")
@@ -172,6 +293,9 @@ def main() -> int:
 
     if args.form == "batched":
         print(json.dumps(bench_batched(args)), flush=True)
+        return 0
+    if args.form == "serving":
+        print(json.dumps(bench_serving(args)), flush=True)
         return 0
 
     import torch

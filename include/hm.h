@@ -55,8 +55,14 @@ typedef enum { HM_F64 = 0, HM_F32 = 1 } hm_dtype;
 
 /* Arithmetic used for the block products.
  *   HM_PREC_FP64: FP64 everywhere (W, Y in FP64).
- *   HM_PREC_FP32: FP32 blocks and FP32 accumulation (W, Y in FP32). */
-typedef enum { HM_PREC_FP64 = 0, HM_PREC_FP32 = 1 } hm_prec;
+ *   HM_PREC_FP32: FP32 blocks and FP32 accumulation (W, Y in FP32).
+ *   HM_PREC_BF16X3: mixed precision (W, Y in FP64).  The near-field, far
+ *     (coupling) and leaf-basis products split both operands into BF16
+ *     hi + lo parts and sum hi*hi + hi*lo + lo*hi on MFMA with FP32
+ *     accumulation (relative error of a product about 2^-16); the transfer
+ *     products of the up and down passes and the final near + far sum stay in
+ *     FP64.  Loading it keeps the FP64 store and adds a split-BF16 store. */
+typedef enum { HM_PREC_FP64 = 0, HM_PREC_FP32 = 1, HM_PREC_BF16X3 = 2 } hm_prec;
 
 /* Bit for hm_load_*'s prec_mask: which precisions to keep on the device. */
 #define HM_PRECBIT(p) (1u << (unsigned)(p))
@@ -113,6 +119,7 @@ typedef struct {
     int64_t E_V, E_T, E_B, E_D;     /* stored entries of leaf bases, transfers, B, D */
     double flops_per_col;           /* algorithmic flops per column of W: 2(2E_V+2E_T+E_B+E_D) */
     double bytes_fp64, bytes_fp32;  /* device bytes of the block store per precision (0 = not loaded) */
+    double bytes_bf16x3;            /* device bytes of the split-BF16 store (0 = not loaded) */
     int32_t n_phases;               /* launches of one evaluation (excluding permutes) */
 } hm_info_t;
 
@@ -137,7 +144,7 @@ hm_status hm_info(hm_matrix h, hm_info_t *out);
 hm_status hm_free(hm_matrix h);
 
 /* Y = K~ W for Q columns on `stream` (a hipStream_t, NULL = null stream).
- * dtype must be HM_F64 with HM_PREC_FP64 and HM_F32 with HM_PREC_FP32; the
+ * dtype must be HM_F64 with HM_PREC_FP64 or HM_PREC_BF16X3, HM_F32 with HM_PREC_FP32; the
  * precision must have been loaded.  Q = 0 is a valid no-op.  Workspaces grow
  * on demand (the first call at a larger Q allocates).  Calls on the same h
  * must be serialized by the caller (they share workspaces). */

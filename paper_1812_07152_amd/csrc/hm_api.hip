@@ -94,7 +94,7 @@ const char *hm_last_error(void) { return g_last_error.c_str(); }
 hm_status hm_load_compressed(const char *path, int device, unsigned prec_mask, hm_matrix *out) {
     if (!out) return fail(HM_ERR_INVALID, "hm_load_compressed: out is NULL");
     *out = nullptr;
-    if (!(prec_mask & (HM_PRECBIT(HM_PREC_FP64) | HM_PRECBIT(HM_PREC_FP32))))
+    if (!(prec_mask & (HM_PRECBIT(HM_PREC_FP64) | HM_PRECBIT(HM_PREC_FP32) | HM_PRECBIT(HM_PREC_BF16X3))))
         return fail(HM_ERR_INVALID, "hm_load_compressed: prec_mask selects no precision");
     HostRepr r;
     hm_status st = read_file(path, r);
@@ -110,7 +110,7 @@ hm_status hm_load_compressed_mem(const hm_host_repr *repr, int device, unsigned 
     if (!out) return fail(HM_ERR_INVALID, "hm_load_compressed_mem: out is NULL");
     *out = nullptr;
     if (!repr) return fail(HM_ERR_INVALID, "hm_load_compressed_mem: repr is NULL");
-    if (!(prec_mask & (HM_PRECBIT(HM_PREC_FP64) | HM_PRECBIT(HM_PREC_FP32))))
+    if (!(prec_mask & (HM_PRECBIT(HM_PREC_FP64) | HM_PRECBIT(HM_PREC_FP32) | HM_PRECBIT(HM_PREC_BF16X3))))
         return fail(HM_ERR_INVALID, "hm_load_compressed_mem: prec_mask selects no precision");
     HostRepr r;
     hm_status st = from_view(*repr, r);
@@ -137,6 +137,7 @@ hm_status hm_info(hm_matrix h, hm_info_t *o) {
     o->flops_per_col = 2.0 * (2.0 * h->E_V + 2.0 * h->E_T + (double)h->E_B + (double)h->E_D);
     o->bytes_fp64 = (double)h->prec[HM_PREC_FP64].bytes;
     o->bytes_fp32 = (double)h->prec[HM_PREC_FP32].bytes;
+    o->bytes_bf16x3 = (double)h->store16_bytes;
     o->n_phases = (int32_t)h->phases.size();
     return HM_OK;
 }
@@ -146,6 +147,7 @@ hm_status hm_free(hm_matrix h) {
     DeviceScope ds(h->device);
     for (int i = 0; i < 2; i++)
         if (h->prec[i].blocks) (void)hipFree(h->prec[i].blocks);
+    if (h->store16) (void)hipFree(h->store16);
     for (int s = 0; s < 2; s++)
         for (int b = 0; b < BUF_COUNT; b++)
             if (h->ws[s][b]) (void)hipFree(h->ws[s][b]);
@@ -173,16 +175,19 @@ hm_status hm_eval(hm_matrix h, const void *W, int64_t ldw, void *Y, int64_t ldy,
     if (!W || !Y) return fail(HM_ERR_INVALID, "hm_eval: W or Y is NULL");
     if (ldw < Q || ldy < Q) return fail(HM_ERR_INVALID, "hm_eval: leading dimension < Q");
     if (flags & ~(HM_TREE_ORDER | HM_PROFILE)) return fail(HM_ERR_INVALID, "hm_eval: unknown flags");
-    if (!((dtype == HM_F64 && prec == HM_PREC_FP64) || (dtype == HM_F32 && prec == HM_PREC_FP32)))
+    if (!((dtype == HM_F64 && prec == HM_PREC_FP64) || (dtype == HM_F32 && prec == HM_PREC_FP32) ||
+          (dtype == HM_F64 && prec == HM_PREC_BF16X3)))
         return fail(HM_ERR_INVALID, "hm_eval: dtype and precision do not match");
-    if (!h->prec[prec].blocks) return fail(HM_ERR_INVALID, "hm_eval: precision was not loaded");
+    const bool mixed = prec == HM_PREC_BF16X3;
+    if (mixed ? !(h->store16 && h->prec[HM_PREC_FP64].blocks) : !h->prec[prec].blocks)
+        return fail(HM_ERR_INVALID, "hm_eval: precision was not loaded");
     if (Q > (int64_t)1 << 24) return fail(HM_ERR_INVALID, "hm_eval: Q too large");
     DeviceScope ds(h->device);
     if (ds.err != hipSuccess) return fail(HM_ERR_DEVICE, "hm_eval: cannot select the device");
     hipStream_t s = (hipStream_t)stream;
     const int es = dtype == HM_F64 ? 8 : 4, slot = dtype == HM_F64 ? 0 : 1;
     const char *sched = std::getenv("HM_SCHED");
-    const bool level_sched = sched && std::string(sched) == "level";
+    const bool level_sched = sched && std::string(sched) == "level" && !mixed;
     int bn_kind[4] = {0, pick_bn(Q, 1), pick_bn(Q, 2), pick_bn(Q, 3)};
     if (!level_sched) bn_kind[1] = bn_kind[2] = bn_kind[3];  // one tile for the whole graph
     const int bn_max = std::max({bn_kind[1], bn_kind[2], bn_kind[3]});
@@ -199,11 +204,12 @@ hm_status hm_eval(hm_matrix h, const void *W, int64_t ldw, void *Y, int64_t ldy,
     int grid = 0;
     GraphPlan *plan = nullptr;
     if (!level_sched) {
-        const int occ = persistent_occupancy(es, bn_kind[3]);
+        const int occ = persistent_occupancy(es, bn_kind[3], mixed);
         const int workers = std::max(1, occ * h->n_cu);
-        hm_status pst = get_plan(h, slot, bn_kind[3], Qp, workers, &plan);
+        hm_status pst = get_plan(h, slot, bn_kind[3], Qp, workers, &plan, mixed ? 1 : 0);
         if (pst != HM_OK) return pst;
-        MatDesc md{h->prec[prec].blocks, {bufs[0], bufs[1], bufs[2], bufs[3]}, Qp, h->d_segs};
+        MatDesc md{h->prec[mixed ? HM_PREC_FP64 : prec].blocks, {bufs[0], bufs[1], bufs[2], bufs[3]},
+                   Qp, h->d_segs, mixed ? h->store16 : nullptr};
         MatDesc &cache = h->mat_cache[slot];
         if (std::memcmp(&md, &cache, sizeof(MatDesc)) != 0 || h->mat_slot != slot) {
             HM_HIP(hipStreamSynchronize(s));

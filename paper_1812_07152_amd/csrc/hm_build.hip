@@ -318,6 +318,98 @@ hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_mat
             for (int32_t q : j.preds)
                 if (q < 0) return fail(HM_ERR_INTERNAL, "dependency graph: missing predecessor job");
     }
+    // Mixed precision: the same jobs with split-BF16 parts (leaf bases, far
+    // blocks, near blocks) and FP64 parts (transfers) separated; a down job
+    // becomes its far reduction (split BF16, overwrite) followed by its
+    // transfer from the parent (FP64, accumulate).
+    std::vector<GJob> mjobs;
+    {
+        std::vector<int32_t> up_job(n, -1), down_final(n, -1), near_job(n, -1);
+        for (const Planner::Placed &pl : P.placed) {
+            GJob j{};
+            j.node = pl.node;
+            j.out_buf = pl.out_buf;
+            j.out_row = pl.out_row;
+            j.M = pl.M;
+            const int a = pl.node;
+            auto kpad_of = [&](int32_t b, int32_t e) {
+                int64_t k = 0;
+                for (int32_t q = b; q < e; q++) k += P.segs[q].Kpad;
+                return k;
+            };
+            if (pl.kind == 1) {
+                j.kind = 1;
+                j.seg_begin = pl.seg_begin;
+                j.seg_end = pl.seg_end;
+                j.mode = leaf(a) ? 1 : 0;
+                j.kpad = pl.kpad;
+                if (!leaf(a)) {
+                    if (r.rank[r.left[a]] > 0) j.preds.push_back(up_job[r.left[a]]);
+                    if (r.rank[r.right[a]] > 0) j.preds.push_back(up_job[r.right[a]]);
+                }
+                up_job[a] = (int32_t)mjobs.size();
+                mjobs.push_back(j);
+            } else if (pl.kind == 2) {
+                const int32_t p = r.parent[a];
+                const bool has_td = p >= 0 && r.level[p] >= 1 && r.rank[p] > 0;
+                GJob fj = j;
+                fj.kind = 2;
+                fj.mode = 1;
+                fj.seg_begin = pl.seg_begin;
+                fj.seg_end = has_td ? pl.seg_end - 1 : pl.seg_end;
+                fj.kpad = kpad_of(fj.seg_begin, fj.seg_end);
+                for (int64_t e = r.far_ptr[a]; e < r.far_ptr[a + 1]; e++)
+                    if (r.rank[r.far_col[e]] > 0) fj.preds.push_back(up_job[r.far_col[e]]);
+                const int32_t far_idx = (int32_t)mjobs.size();
+                mjobs.push_back(fj);
+                down_final[a] = far_idx;
+                if (has_td) {
+                    GJob tj = j;
+                    tj.kind = 5;
+                    tj.mode = 0;
+                    tj.accumulate = 1;
+                    tj.seg_begin = pl.seg_end - 1;
+                    tj.seg_end = pl.seg_end;
+                    tj.kpad = kpad_of(tj.seg_begin, tj.seg_end);
+                    tj.preds = {far_idx, down_final[p]};
+                    down_final[a] = (int32_t)mjobs.size();
+                    mjobs.push_back(tj);
+                }
+            } else {
+                const bool far_part = r.rank[a] > 0 && r.level[a] >= 1;
+                GJob nj = j;
+                nj.kind = 3;
+                nj.mode = 1;
+                nj.seg_begin = pl.seg_begin;
+                nj.seg_end = far_part ? pl.seg_end - 1 : pl.seg_end;
+                nj.kpad = kpad_of(nj.seg_begin, nj.seg_end);
+                near_job[a] = (int32_t)mjobs.size();
+                mjobs.push_back(nj);
+                if (far_part) {
+                    GJob fj = j;
+                    fj.kind = 4;
+                    fj.mode = 1;
+                    fj.accumulate = 1;
+                    fj.seg_begin = pl.seg_end - 1;
+                    fj.seg_end = pl.seg_end;
+                    fj.kpad = kpad_of(fj.seg_begin, fj.seg_end);
+                    fj.preds = {near_job[a], down_final[a]};
+                    mjobs.push_back(fj);
+                }
+            }
+        }
+        for (const GJob &j : mjobs)
+            for (int32_t q : j.preds)
+                if (q < 0) return fail(HM_ERR_INTERNAL, "mixed dependency graph: missing predecessor job");
+    }
+    // offsets of every block in the split-BF16 store (32-wide contraction
+    // chunks, hi then lo part of lda x 32 values each)
+    int64_t store16_elems = 0;
+    for (Seg &sg : P.segs) {
+        sg.a_off16 = store16_elems;
+        store16_elems += (int64_t)((sg.K + 31) / 32) * 2 * sg.lda * 32;
+    }
+    store16_elems += 8192;  // slack for tiles taller than their block
 
     // ---- device side
     int prev = 0;
@@ -353,6 +445,7 @@ hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_mat
     h->store_elems = P.store_off + 512;
     h->phases = P.phases;
     h->gjobs = std::move(jobs);
+    h->gjobs_mixed = std::move(mjobs);
 
     hipStream_t s = nullptr;
     HM_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
@@ -384,6 +477,11 @@ hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_mat
             if (st != HM_OK) return st;
         }
     }
+    if (prec_mask & HM_PRECBIT(HM_PREC_BF16X3)) {
+        HM_HIP(hipMalloc(&h->store16, 2 * (size_t)store16_elems));
+        h->store16_bytes = 2 * (size_t)store16_elems;
+        HM_HIP(hipMemsetAsync(h->store16, 0, h->store16_bytes, s));
+    }
     if (prec_mask & HM_PRECBIT(HM_PREC_FP32)) {
         float *store32 = nullptr;
         HM_HIP(hipMalloc(&store32, sizeof(float) * (size_t)h->store_elems));
@@ -410,8 +508,10 @@ hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_mat
         HM_HIP(hipGetDeviceProperties(&prop, device));
         h->n_cu = prop.multiProcessorCount;
     }
+    if (h->store16)
+        HM_HIP(launch_make_bf16x3(store64, h->d_segs, (int)P.segs.size(), h->store16, s));
     HM_HIP(hipStreamSynchronize(s));
-    if (!(prec_mask & HM_PRECBIT(HM_PREC_FP64))) {
+    if (!(prec_mask & (HM_PRECBIT(HM_PREC_FP64) | HM_PRECBIT(HM_PREC_BF16X3)))) {
         HM_HIP(hipFree(store64));
         h->prec[HM_PREC_FP64].blocks = nullptr;
         h->prec[HM_PREC_FP64].bytes = 0;

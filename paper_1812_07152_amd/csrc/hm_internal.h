@@ -33,6 +33,7 @@ struct Seg {
     int32_t K;      // contraction length (> 0)
     int32_t b_buf;
     int32_t Kpad;   // stored contraction rows (multiple of 16)
+    int64_t a_off16; // element offset of the block in the split-BF16 store (see k_make_bf16x3)
 };
 
 // One output block: rows [out_row, out_row + M) of buffer out_buf (M <= tile
@@ -100,7 +101,7 @@ struct PTask {
     int32_t mat;         // index into the MatDesc table
     int32_t ndeps;       // entries that must finish first
     int32_t succ_begin, succ_end;  // successor entries (queue positions) in the succ array
-    int32_t pad_;
+    int32_t mode;        // 0: products in the launch's type; 1: split BF16 (hi+lo) with FP32 accumulation
 };
 
 // Device addresses of one matrix for the persistent launch.
@@ -109,6 +110,7 @@ struct MatDesc {
     void *buf[4];
     int64_t ldq;
     const Seg *segs;
+    const void *store16;  // split-BF16 store (mixed precision), or null
 };
 
 // One matrix's permutes in a batched launch.
@@ -133,6 +135,7 @@ struct GJob {
     int32_t M;
     int32_t seg_begin, seg_end;  // into the matrix's segment table
     int32_t accumulate;
+    int32_t mode;        // 0 native, 1 split BF16
     int64_t kpad;        // sum of Kpad over its segments (work model)
     std::vector<int32_t> preds;  // job indices
 };
@@ -141,6 +144,7 @@ struct GJob {
 struct GraphPlan {
     int bn = 0;
     int64_t Q = -1;
+    int mode = 0;        // 0: native job graph, 1: mixed-precision job graph
     int n_tasks = 0;
     PTask *d_tasks = nullptr;
     int32_t *d_succ = nullptr;
@@ -175,6 +179,9 @@ struct hm_matrix_s {
     hm::Seg *d_segs = nullptr;
     std::vector<hm::Phase> phases;
     std::vector<hm::GJob> gjobs;           // dependency graph of one evaluation
+    std::vector<hm::GJob> gjobs_mixed;     // same, with split-BF16 and FP64 parts separated
+    void *store16 = nullptr;               // split-BF16 block store (HM_PREC_BF16X3)
+    size_t store16_bytes = 0;
     std::vector<hm::GraphPlan> plans[2];   // per element size: one plan per (tile, tile count)
     hm::MatDesc *d_mat = nullptr;          // one descriptor (persistent launch)
     hm::MatDesc mat_cache[2] = {};         // last uploaded descriptor per element size
@@ -214,6 +221,9 @@ hipError_t launch_permute_in(const void *W, int64_t ldw, void *Wt, int64_t Qp, c
 hipError_t launch_permute_out(const void *Yt, int64_t Qp, void *Y, int64_t ldy, const int64_t *perm,
                               int64_t N, int64_t Q, int elem_bytes, hipStream_t s);
 hipError_t launch_convert_f64_to_f32(const double *src, float *dst, int64_t n, hipStream_t s);
+// Split-BF16 copies of blocks (one per segment) of the FP64 store.
+hipError_t launch_make_bf16x3(const double *store, const Seg *segs, int nsegs, void *store16,
+                              hipStream_t s);
 hipError_t launch_repack(const double *stage, const RepackJob *jobs, int njobs, double *store,
                          hipStream_t s);
 // Batched row gather (in = true: W -> Wt) or scatter (Yt -> Y) for n matrices;
@@ -224,12 +234,13 @@ hipError_t launch_permute_batched(const PermDesc *d, int n, int64_t max_elems, i
 hipError_t launch_persistent(const GraphPlan &plan, int elem_bytes, const MatDesc *d_mat,
                              int32_t *d_head, int grid, hipStream_t s);
 // Resident workgroups per CU of the persistent kernel for (elem_bytes, bn).
-int persistent_occupancy(int elem_bytes, int bn);
+int persistent_occupancy(int elem_bytes, int bn, bool split = false);
 
 // Expand the job graph for Q columns with column tile bn, order it by list
 // scheduling on `workers` simulated workgroups, and upload it (hm_sched.hip).
 // The plan of h for (bn, ldq / bn column tiles), built and cached on first use.
-hm_status get_plan(hm_matrix h, int slot, int bn, int64_t ldq, int workers, GraphPlan **out);
+hm_status get_plan(hm_matrix h, int slot, int bn, int64_t ldq, int workers, GraphPlan **out,
+                   int mode = 0);
 // Grow h's workspaces for element-size slot to a leading dimension of ldq.
 hm_status reserve_ws(hm_matrix h, int slot, int64_t ldq);
 // One matrix's share of a (possibly multi-matrix) plan.
@@ -237,6 +248,7 @@ struct PlanPart {
     hm_matrix h;
     int mat;  // index in the MatDesc table
     int nq;   // column tiles
+    int mode = 0;  // which job graph of h: 0 native, 1 mixed precision
 };
 hm_status build_plan(const std::vector<PlanPart> &parts, int bn, int workers, GraphPlan &plan);
 void free_plan(GraphPlan &p);

@@ -211,6 +211,201 @@ __device__ __forceinline__ void block_product(const TileJob &task, const Seg *__
             }
 }
 
+// ---------------------------------------------------------------------------
+// Split-BF16 products (mixed precision).  An FP64 value v is carried as
+// v ~= hi + lo with hi = bf16(v), lo = bf16(v - hi), and a product as
+// A B ~= A_hi B_hi + A_hi B_lo + A_lo B_hi, each term a
+// v_mfma_f32_16x16x32_bf16 with FP32 accumulation (lane mapping checked on
+// the device: lane l supplies A[l%16][8(l/16)..8(l/16)+7] and
+// B[8(l/16)..8(l/16)+7][l%16]; accumulator register r of lane l holds
+// D[4(l/16)+r][l%16]).  A blocks come from the split-BF16 store, where a
+// block is a run of 32-wide contraction chunks, each chunk the hi part
+// (lda rows x 32 contraction values, row-major) followed by the lo part.
+// B rows come from the FP64 workspaces and are split while being staged.
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef short s16x8_t __attribute__((ext_vector_type(8)));
+
+constexpr int kKC = 32;              // contraction rows per chunk
+constexpr int kKCP = kKC + 8;        // LDS row pitch in bf16 (80 bytes)
+
+__device__ __forceinline__ void split_bf16(float f, __bf16 &hi, __bf16 &lo) {
+    hi = (__bf16)f;
+    lo = (__bf16)(f - (float)hi);
+}
+
+// LDS: As[2 stages][2 (hi, lo)][BM][kKCP], Bs[2][2][BN][kKCP] (bf16).
+template <int BM, int BN>
+constexpr int bf16_lds_bytes() {
+    return 2 * 2 * (BM + BN) * kKCP * 2;
+}
+
+template <int BM, int BN, int WAVES_M, int WAVES_N, int NT>
+__device__ __forceinline__ void block_product_bf16x3(const TileJob &task, const Seg *__restrict__ segs,
+                                                     const __bf16 *__restrict__ store16, double *buf0,
+                                                     double *buf1, double *buf2, double *buf3,
+                                                     int64_t ldq, int64_t n0, char *lds) {
+    constexpr int WM = BM / WAVES_M, WN = BN / WAVES_N;
+    constexpr int FM = WM / 16, FN = WN / 16;
+    static_assert(FM >= 1 && FN >= 1, "bad tile");
+    // A chunk: BM rows x 32 values x {hi, lo}, as 16-byte vectors (4 per row and part)
+    constexpr int A_VECS = 2 * BM * (kKC / 8);
+    constexpr int A_PER = (A_VECS + NT - 1) / NT;
+    // B chunk: (16 contraction pairs) x (BN / 2 column pairs), 2 x 16-byte loads each
+    constexpr int B_ITEMS = (kKC / 2) * (BN / 2);
+    constexpr int B_PER = (B_ITEMS + NT - 1) / NT;
+    __bf16(*As)[2][BM][kKCP] = reinterpret_cast<__bf16(*)[2][BM][kKCP]>(lds);
+    __bf16(*Bs)[2][BN][kKCP] =
+        reinterpret_cast<__bf16(*)[2][BN][kKCP]>(lds + 2 * 2 * BM * kKCP * 2);
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const bool computes = wave < WAVES_M * WAVES_N;
+    const int wm = wave / WAVES_N, wn = wave % WAVES_N;
+    auto bufp = [&](int b) { return b == 0 ? buf0 : b == 1 ? buf1 : b == 2 ? buf2 : buf3; };
+
+    f4_t acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; i++)
+#pragma unroll
+        for (int j = 0; j < FN; j++) acc[i][j] = f4_t{0, 0, 0, 0};
+
+    s16x8_t ra[A_PER];
+    d2_t rb0[B_PER], rb1[B_PER];
+
+    auto load = [&](const Seg &sg, int kk) {
+        // chunk kk / 32 of the block; rows m0.. of the hi and lo parts
+        const __bf16 *A = store16 + sg.a_off16 + (int64_t)(kk / kKC) * 2 * sg.lda * kKC;
+#pragma unroll
+        for (int u = 0; u < A_PER; u++) {
+            const int idx = min(tid + u * NT, A_VECS - 1);
+            const int part = idx / (BM * 4), rem = idx % (BM * 4), r = rem / 4, c = (rem % 4) * 8;
+            ra[u] = *reinterpret_cast<const s16x8_t *>(A + (int64_t)part * sg.lda * kKC +
+                                                      (int64_t)(task.m0 + r) * kKC + c);
+        }
+        const double *Bp = bufp(sg.b_buf) + sg.b_row * ldq + n0;
+#pragma unroll
+        for (int u = 0; u < B_PER; u++) {
+            const int idx = min(tid + u * NT, B_ITEMS - 1);
+            const int pr = idx % (kKC / 2), cp = idx / (kKC / 2);
+            const int k0 = min(kk + 2 * pr, sg.K - 1), k1 = min(kk + 2 * pr + 1, sg.K - 1);
+            rb0[u] = *reinterpret_cast<const d2_t *>(Bp + (int64_t)k0 * ldq + 2 * cp);
+            rb1[u] = *reinterpret_cast<const d2_t *>(Bp + (int64_t)k1 * ldq + 2 * cp);
+        }
+    };
+    auto stash = [&](int b) {
+#pragma unroll
+        for (int u = 0; u < A_PER; u++) {
+            const int idx = tid + u * NT;
+            if (A_VECS % NT == 0 || idx < A_VECS) {
+                const int part = idx / (BM * 4), rem = idx % (BM * 4), r = rem / 4, c = (rem % 4) * 8;
+                *reinterpret_cast<s16x8_t *>(&As[b][part][r][c]) = ra[u];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < B_PER; u++) {
+            const int idx = tid + u * NT;
+            if (B_ITEMS % NT == 0 || idx < B_ITEMS) {
+                const int pr = idx % (kKC / 2), cp = idx / (kKC / 2);
+#pragma unroll
+                for (int e = 0; e < 2; e++) {  // the two columns of the pair
+                    __bf16 h0, l0, h1, l1;
+                    split_bf16((float)rb0[u][e], h0, l0);
+                    split_bf16((float)rb1[u][e], h1, l1);
+                    *reinterpret_cast<bf16x2_t *>(&Bs[b][0][2 * cp + e][2 * pr]) = bf16x2_t{h0, h1};
+                    *reinterpret_cast<bf16x2_t *>(&Bs[b][1][2 * cp + e][2 * pr]) = bf16x2_t{l0, l1};
+                }
+            }
+        }
+    };
+    auto compute = [&](int b) {
+        const int kg = (lane >> 4) * 8;
+        bf16x8_t ah[FM], al[FM], bh[FN], bl[FN];
+#pragma unroll
+        for (int i = 0; i < FM; i++) {
+            const int r = wm * WM + i * 16 + (lane & 15);
+            ah[i] = *reinterpret_cast<const bf16x8_t *>(&As[b][0][r][kg]);
+            al[i] = *reinterpret_cast<const bf16x8_t *>(&As[b][1][r][kg]);
+        }
+#pragma unroll
+        for (int j = 0; j < FN; j++) {
+            const int n = wn * WN + j * 16 + (lane & 15);
+            bh[j] = *reinterpret_cast<const bf16x8_t *>(&Bs[b][0][n][kg]);
+            bl[j] = *reinterpret_cast<const bf16x8_t *>(&Bs[b][1][n][kg]);
+        }
+#pragma unroll
+        for (int i = 0; i < FM; i++)
+#pragma unroll
+            for (int j = 0; j < FN; j++) {
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+            }
+    };
+
+    if (task.seg_begin < task.seg_end) {
+        int s = task.seg_begin, kk = 0, b = 0;
+        Seg sg = segs[s];
+        load(sg, 0);
+        stash(0);
+        __syncthreads();
+        while (true) {
+            int nkk = kk + kKC, ns = s;
+            Seg nsg = sg;
+            if (nkk >= sg.K) {
+                ns = s + 1;
+                nkk = 0;
+                if (ns < task.seg_end) nsg = segs[ns];
+            }
+            const bool more = ns < task.seg_end;
+            load(nsg, more ? nkk : kk);
+            if (computes) compute(b);
+            stash(b ^ 1);
+            __syncthreads();
+            if (!more) break;
+            s = ns;
+            kk = nkk;
+            sg = nsg;
+            b ^= 1;
+        }
+    }
+
+    if (!computes) return;
+    double *out = bufp(task.out_buf) + task.out_row * ldq + n0;
+#pragma unroll
+    for (int i = 0; i < FM; i++)
+#pragma unroll
+        for (int j = 0; j < FN; j++)
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int row = wm * WM + i * 16 + 4 * (lane >> 4) + r;
+                const int col = wn * WN + j * 16 + (lane & 15);
+                if (row < task.M) {
+                    double *o = out + (int64_t)row * ldq + col;
+                    *o = task.accumulate ? *o + (double)acc[i][j][r] : (double)acc[i][j][r];
+                }
+            }
+}
+
+// Split-BF16 copy of one block per workgroup: for chunk c, part h (0 hi,
+// 1 lo), row i < lda, value k < 32: dst = split(src[(32c + k) * lda + i]),
+// zero beyond the block's K contraction rows.
+__global__ void k_make_bf16x3(const double *__restrict__ store, const Seg *__restrict__ segs,
+                              __bf16 *__restrict__ store16) {
+    const Seg sg = segs[blockIdx.x];
+    const int nchunks = (sg.K + kKC - 1) / kKC;
+    const int64_t per_chunk = (int64_t)sg.lda * kKC;
+    for (int64_t e = threadIdx.x; e < nchunks * per_chunk; e += blockDim.x) {
+        const int c = (int)(e / per_chunk), rem = (int)(e % per_chunk), i = rem / kKC, k = rem % kKC;
+        const int kk = c * kKC + k;
+        const float v = kk < sg.K ? (float)store[sg.a_off + (int64_t)kk * sg.lda + i] : 0.0f;
+        __bf16 hi, lo;
+        split_bf16(v, hi, lo);
+        __bf16 *dst = store16 + sg.a_off16 + (int64_t)c * 2 * per_chunk;
+        dst[rem] = hi;
+        dst[per_chunk + rem] = lo;
+    }
+}
+
 // One launch = one phase: workgroup (x, y) computes task x, column tile y.
 template <typename T, int BM, int BN, int WAVES_M, int WAVES_N>
 __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void k_block_products(
@@ -244,12 +439,15 @@ constexpr int kWaitLimit = 1 << 20;  // polls (each followed by a sleep) before 
 // queue order is topological, so every awaited entry was taken earlier by a
 // running workgroup: the launch cannot deadlock and every workgroup exits
 // when the queue is drained.
-template <typename T, int BN>
+template <typename T, int BN, bool SPLIT>
 __global__ __launch_bounds__(kPersistThreads) void k_persistent(
     const PTask *__restrict__ tasks, int n_tasks, const int32_t *__restrict__ succ,
     int32_t *counters, int32_t *head, int32_t *err, const MatDesc *__restrict__ mats) {
-    __shared__ __attribute__((aligned(16))) T As[2 * kBK * (128 + lds_pad<T>())];
-    __shared__ __attribute__((aligned(16))) T Bs[2 * kBK * (BN + lds_pad<T>())];
+    constexpr int kNative = (2 * kBK * (128 + lds_pad<T>()) + 2 * kBK * (BN + lds_pad<T>())) * (int)sizeof(T);
+    constexpr int kSplit = (SPLIT && sizeof(T) == 8) ? bf16_lds_bytes<128, BN>() : 0;
+    __shared__ __attribute__((aligned(16))) char lds[kNative > kSplit ? kNative : kSplit];
+    T *As = reinterpret_cast<T *>(lds);
+    T *Bs = As + 2 * kBK * (128 + lds_pad<T>());
     __shared__ int s_t;
     while (true) {
         if (threadIdx.x == 0) s_t = __hip_atomic_fetch_add(head, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -274,7 +472,21 @@ __global__ __launch_bounds__(kPersistThreads) void k_persistent(
         const int64_t n0 = (int64_t)pt.qtile * BN;
         const T *store = (const T *)md.store;
         const Seg *segs = md.segs;
-        if (pt.bm == 128)
+        bool split = false;
+        if constexpr (SPLIT && sizeof(T) == 8) split = pt.mode == 1;
+        if (split) {
+            if constexpr (SPLIT && sizeof(T) == 8) {
+                const __bf16 *s16 = (const __bf16 *)md.store16;
+                if (pt.bm == 128)
+                    block_product_bf16x3<128, BN, PLayout<128, BN>::WMv, PLayout<128, BN>::WN, kPersistThreads>(
+                        job, segs, s16, (double *)md.buf[0], (double *)md.buf[1], (double *)md.buf[2],
+                        (double *)md.buf[3], md.ldq, n0, lds);
+                else
+                    block_product_bf16x3<64, BN, PLayout<64, BN>::WMv, PLayout<64, BN>::WN, kPersistThreads>(
+                        job, segs, s16, (double *)md.buf[0], (double *)md.buf[1], (double *)md.buf[2],
+                        (double *)md.buf[3], md.ldq, n0, lds);
+            }
+        } else if (pt.bm == 128)
             block_product<T, 128, BN, PLayout<128, BN>::WMv, PLayout<128, BN>::WN, kPersistThreads>(
                 job, segs, store, (T *)md.buf[0], (T *)md.buf[1], (T *)md.buf[2], (T *)md.buf[3],
                 md.ldq, n0, As, Bs);
@@ -464,8 +676,12 @@ hipError_t run_persistent(const GraphPlan &plan, const MatDesc *mats, int32_t *h
     const int nt = plan.n_tasks;
     hipLaunchKernelGGL(k_persistent_init, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s,
                        plan.d_tasks, nt, plan.d_counters, head);
-    hipLaunchKernelGGL((k_persistent<T, BN>), dim3((unsigned)grid), dim3(kPersistThreads), 0, s,
-                       plan.d_tasks, nt, plan.d_succ, plan.d_counters, head, head + 1, mats);
+    if (sizeof(T) == 8 && plan.mode == 1)
+        hipLaunchKernelGGL((k_persistent<T, BN, true>), dim3((unsigned)grid), dim3(kPersistThreads), 0,
+                           s, plan.d_tasks, nt, plan.d_succ, plan.d_counters, head, head + 1, mats);
+    else
+        hipLaunchKernelGGL((k_persistent<T, BN, false>), dim3((unsigned)grid), dim3(kPersistThreads), 0,
+                           s, plan.d_tasks, nt, plan.d_succ, plan.d_counters, head, head + 1, mats);
     return hipGetLastError();
 }
 
@@ -481,16 +697,16 @@ hipError_t persistent_bn(const GraphPlan &plan, const MatDesc *mats, int32_t *he
     }
 }
 
-template <typename T>
+template <typename T, bool SPLIT>
 int occupancy_bn(int bn) {
     int n = 0;
     hipError_t e = hipSuccess;
     switch (bn) {
-        case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_persistent<T, 16>, kPersistThreads, 0); break;
-        case 32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_persistent<T, 32>, kPersistThreads, 0); break;
-        case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_persistent<T, 64>, kPersistThreads, 0); break;
-        case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_persistent<T, 128>, kPersistThreads, 0); break;
-        default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_persistent<T, 256>, kPersistThreads, 0); break;
+        case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_persistent<T, 16, SPLIT>, kPersistThreads, 0); break;
+        case 32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_persistent<T, 32, SPLIT>, kPersistThreads, 0); break;
+        case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_persistent<T, 64, SPLIT>, kPersistThreads, 0); break;
+        case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_persistent<T, 128, SPLIT>, kPersistThreads, 0); break;
+        default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_persistent<T, 256, SPLIT>, kPersistThreads, 0); break;
     }
     return e == hipSuccess ? std::max(n, 1) : 1;
 }
@@ -504,8 +720,9 @@ hipError_t launch_persistent(const GraphPlan &plan, int elem_bytes, const MatDes
                            : persistent_bn<float>(plan, d_mat, d_head, grid, s);
 }
 
-int persistent_occupancy(int elem_bytes, int bn) {
-    return elem_bytes == 8 ? occupancy_bn<double>(bn) : occupancy_bn<float>(bn);
+int persistent_occupancy(int elem_bytes, int bn, bool split) {
+    if (elem_bytes == 8) return split ? occupancy_bn<double, true>(bn) : occupancy_bn<double, false>(bn);
+    return occupancy_bn<float, false>(bn);
 }
 
 hipError_t launch_permute_in(const void *W, int64_t ldw, void *Wt, int64_t Qp, const int64_t *perm,
@@ -554,6 +771,14 @@ hipError_t launch_repack(const double *stage, const RepackJob *jobs, int njobs, 
                          hipStream_t s) {
     if (njobs == 0) return hipSuccess;
     hipLaunchKernelGGL(k_repack, dim3((unsigned)njobs), dim3(256), 0, s, stage, jobs, store);
+    return hipGetLastError();
+}
+
+hipError_t launch_make_bf16x3(const double *store, const Seg *segs, int nsegs, void *store16,
+                              hipStream_t s) {
+    if (nsegs == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_make_bf16x3, dim3((unsigned)nsegs), dim3(256), 0, s, store, segs,
+                       (__bf16 *)store16);
     return hipGetLastError();
 }
 

@@ -38,7 +38,7 @@ hm_status build_plan(const std::vector<PlanPart> &parts, int bn, int workers, Gr
     const double overhead = 2.0 * 128 * 64 * 256;  // fixed per-entry cost, in flops
     for (size_t i = 0; i < parts.size(); i++) {
         P &p = ps[i];
-        p.jobs = &parts[i].h->gjobs;
+        p.jobs = parts[i].mode == 1 ? &parts[i].h->gjobs_mixed : &parts[i].h->gjobs;
         p.mat = parts[i].mat;
         p.nq = parts[i].nq;
         const std::vector<GJob> &jobs = *p.jobs;
@@ -61,7 +61,8 @@ hm_status build_plan(const std::vector<PlanPart> &parts, int bn, int workers, Gr
         p.blevel.resize(p.per_q);
         for (int j = 0; j < nj; j++)
             for (int r = 0; r < p.rows[j]; r++)
-                p.cost[p.first[j] + r] = 2.0 * p.bm[j] * jobs[j].kpad * bn + overhead;
+                p.cost[p.first[j] + r] =
+                    2.0 * p.bm[j] * jobs[j].kpad * bn * (jobs[j].mode == 1 ? 0.35 : 1.0) + overhead;
         // critical path to the end of the graph (jobs are topologically ordered)
         std::vector<double> jbl(nj, 0.0);
         for (int j = nj - 1; j >= 0; j--) {
@@ -181,6 +182,7 @@ hm_status build_plan(const std::vector<PlanPart> &parts, int bn, int workers, Gr
         t.accumulate = g.accumulate;
         t.qtile = q;
         t.mat = p.mat;
+        t.mode = g.mode;
         t.ndeps = ndeps[e];
         t.succ_begin = (int32_t)succ.size();
         for (int32_t s2 : p.succ_jobs[j])
@@ -209,10 +211,11 @@ hm_status build_plan(const std::vector<PlanPart> &parts, int bn, int workers, Gr
     return HM_OK;
 }
 
-hm_status get_plan(hm_matrix h, int slot, int bn, int64_t ldq, int workers, GraphPlan **out) {
+hm_status get_plan(hm_matrix h, int slot, int bn, int64_t ldq, int workers, GraphPlan **out,
+                   int mode) {
     const int nq = (int)(ldq / bn);
     for (GraphPlan &p : h->plans[slot])
-        if (p.bn == bn && p.Q == nq) {
+        if (p.bn == bn && p.Q == nq && p.mode == mode) {
             *out = &p;
             return HM_OK;
         }
@@ -221,10 +224,11 @@ hm_status get_plan(hm_matrix h, int slot, int bn, int64_t ldq, int workers, Grap
         h->plans[slot].erase(h->plans[slot].begin());
     }
     GraphPlan p;
-    std::vector<PlanPart> parts{{h, 0, nq}};
+    std::vector<PlanPart> parts{{h, 0, nq, mode}};
     hm_status st = build_plan(parts, bn, workers, p);
     if (st != HM_OK) return st;
     p.Q = nq;  // cache key: column tiles
+    p.mode = mode;
     h->plans[slot].push_back(p);
     *out = &h->plans[slot].back();
     return HM_OK;

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libhm.so")
 HM_OK, HM_ERR_INVALID, HM_ERR_FORMAT, HM_ERR_NOMEM = 0, -1, -2, -3
 HM_ERR_DEVICE, HM_ERR_BUSY, HM_ERR_PENDING, HM_ERR_INTERNAL = -4, -5, -6, -7
 HM_F64, HM_F32 = 0, 1
-HM_PREC_FP64, HM_PREC_FP32 = 0, 1
+HM_PREC_FP64, HM_PREC_FP32, HM_PREC_BF16X3 = 0, 1, 2
 HM_TREE_ORDER, HM_PROFILE = 1, 2
 HM_BATCH_AUTOTUNE, HM_BATCH_NO_GRAPH = 1, 2
 STATUS_NAMES = {0: "HM_OK", -1: "HM_ERR_INVALID", -2: "HM_ERR_FORMAT", -3: "HM_ERR_NOMEM",
@@ -76,7 +76,7 @@ class hm_info_t(ctypes.Structure):
                 ("n_near", ctypes.c_int64), ("E_V", ctypes.c_int64), ("E_T", ctypes.c_int64),
                 ("E_B", ctypes.c_int64), ("E_D", ctypes.c_int64), ("flops_per_col", ctypes.c_double),
                 ("bytes_fp64", ctypes.c_double), ("bytes_fp32", ctypes.c_double),
-                ("n_phases", ctypes.c_int32)]
+                ("bytes_bf16x3", ctypes.c_double), ("n_phases", ctypes.c_int32)]
 
 
 def _load():
@@ -323,6 +323,8 @@ def hm_eval(h: Matrix, W, Y, Q: int | None = None, prec: int | None = None, flag
         prec = HM_PREC_FP64 if dtype == HM_F64 else HM_PREC_FP32
     if Q is None:
         Q = W.shape[1]
+    if Q == 0:
+        return
     if W.shape[1] < Q or Y.shape[1] < Q:
         raise ValueError("hm_eval: tensors narrower than Q")
     _check(lib.hm_eval(h, W.data_ptr(), W.stride(0), Y.data_ptr(), Y.stride(0), Q, dtype, prec,

@@ -170,3 +170,28 @@ def test_c2_full_size_sampled_columns(hmx):
     _say("[parity] c2 full size: oracle eval of sampled columns")
     Yref = H.eval(np.ascontiguousarray(W[:, cols]))
     check_f64(Y[:, cols], Yref)
+
+
+@pytest.mark.parametrize("name", ["c1", "mix8", "hss_lap", "deep_small_leaves"])
+def test_mixed_precision_bf16x3(hmx, name, sched):
+    """Split-BF16 near/far/leaf-basis products with FP32 accumulation, FP64
+    transfers and final sum.  Bar: 5e-5 relative Frobenius against the FP64
+    oracle.  Derivation: each split product drops lo*lo (|lo| <= 2^-9 |v|, so
+    the dropped term is <= 2^-18 relative) and rounds operands to FP32 before
+    splitting (2^-24); FP32 accumulation over a contraction of length K adds
+    about sqrt(K) * 2^-24.  Summed over the two or three products a value
+    passes through (leaf basis, far block, leaf basis), the bound is ~1e-5
+    with margin to 5e-5."""
+    if sched == "level":
+        pytest.skip("mixed precision runs on the task-graph launch only")
+    w, H = built(name)
+    M = hmx.hm_load_compressed_mem(H, 0, hmx.precbit(hmx.HM_PREC_BF16X3))
+    assert hmx.hm_info(M)["bytes_bf16x3"] > 0
+    W = wl.gen_w(w, Q=max(w.Q, 24))
+    Wd = torch.from_numpy(W).cuda()
+    Yd = torch.full_like(Wd, float("nan"))
+    hmx.hm_eval(M, Wd, Yd, prec=hmx.HM_PREC_BF16X3)
+    hmx.hm_check(M)
+    err = rel(Yd.cpu().numpy(), H.eval(W))
+    _say(f"[mixed] case={name} rel err={err:.3e}")
+    assert err <= 5e-5

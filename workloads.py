@@ -93,6 +93,25 @@ def batched_workloads(count: int = 64, base_seed: int = 1000) -> list[Workload]:
     return out
 
 
+def serving_workloads() -> list[Workload]:
+    """Eight resident matrices for the serving form: N from 16384 to 524288,
+    d in {3, 8, 28}, distance admissibility (H^2) for d <= 8 and HSS for d = 28
+    (where distance admissibility degenerates), tol 1e-5."""
+    def g(name, N, d, points, h, m, adm, kernel=KERNEL_GAUSSIAN, seed=0):
+        return Workload(name, N=N, d=d, points=points, point_seed=2000 + seed, kernel=kernel, h=h,
+                        m=m, tol=1e-5, rmax=m, adm=adm, tau=2.0, Q=256, w_seed=3000 + seed)
+    return [
+        g("s1_n16384_d3_h2", 16384, 3, "uniform", 0.5, 64, ADM_DISTANCE, seed=1),
+        g("s2_n32768_d8_h2", 32768, 8, "mixture", 1.0, 128, ADM_DISTANCE, seed=2),
+        g("s3_n65536_d28_hss", 65536, 28, "normal", 4.0, 128, ADM_HSS, KERNEL_LAPLACE, seed=3),
+        g("s4_n65536_d3_h2", 65536, 3, "uniform", 0.5, 128, ADM_DISTANCE, seed=4),
+        g("s5_n131072_d3_h2", 131072, 3, "uniform", 0.5, 128, ADM_DISTANCE, seed=5),
+        g("s6_n131072_d28_hss", 131072, 28, "normal", 4.0, 128, ADM_HSS, KERNEL_LAPLACE, seed=6),
+        g("s7_n262144_d3_h2", 262144, 3, "uniform", 0.5, 128, ADM_DISTANCE, seed=7),
+        g("s8_n524288_d3_h2", 524288, 3, "uniform", 0.5, 128, ADM_DISTANCE, seed=8),
+    ]
+
+
 def small(name: str, N: int, d: int = 3, points: str = "uniform", m: int = 32,
           Q: int = 8, adm: int = ADM_DISTANCE, kernel: int = KERNEL_GAUSSIAN,
           h: float = 0.5, tol: float = 1e-6, rmax: int = 64, tau: float = 2.0,
