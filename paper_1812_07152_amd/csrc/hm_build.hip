@@ -318,13 +318,13 @@ hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_mat
             for (int32_t q : j.preds)
                 if (q < 0) return fail(HM_ERR_INTERNAL, "dependency graph: missing predecessor job");
     }
-    // Mixed precision: the same jobs with split-BF16 parts (leaf bases, far
-    // blocks, near blocks) and FP64 parts (transfers) separated; a down job
-    // becomes its far reduction (split BF16, overwrite) followed by its
-    // transfer from the parent (FP64, accumulate).
+    // Mixed precision: the same jobs with the products of the leaf bases, far
+    // blocks and near blocks in split BF16 and the transfers in FP64; a down
+    // job runs its far blocks in split BF16 and continues in FP64 with the
+    // transfer from its parent (mode 2).
     std::vector<GJob> mjobs;
     {
-        std::vector<int32_t> up_job(n, -1), down_final(n, -1), near_job(n, -1);
+        std::vector<int32_t> up_job(n, -1), down_job(n, -1), near_job(n, -1);
         for (const Planner::Placed &pl : P.placed) {
             GJob j{};
             j.node = pl.node;
@@ -343,6 +343,7 @@ hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_mat
                 j.seg_end = pl.seg_end;
                 j.mode = leaf(a) ? 1 : 0;
                 j.kpad = pl.kpad;
+                j.kpad_split = leaf(a) ? pl.kpad : 0;
                 if (!leaf(a)) {
                     if (r.rank[r.left[a]] > 0) j.preds.push_back(up_job[r.left[a]]);
                     if (r.rank[r.right[a]] > 0) j.preds.push_back(up_job[r.right[a]]);
@@ -350,31 +351,24 @@ hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_mat
                 up_job[a] = (int32_t)mjobs.size();
                 mjobs.push_back(j);
             } else if (pl.kind == 2) {
+                // segments: the far blocks, then (if the parent has a
+                // basis) the transfer from the parent
                 const int32_t p = r.parent[a];
                 const bool has_td = p >= 0 && r.level[p] >= 1 && r.rank[p] > 0;
-                GJob fj = j;
-                fj.kind = 2;
-                fj.mode = 1;
-                fj.seg_begin = pl.seg_begin;
-                fj.seg_end = has_td ? pl.seg_end - 1 : pl.seg_end;
-                fj.kpad = kpad_of(fj.seg_begin, fj.seg_end);
+                const int32_t far_end = has_td ? pl.seg_end - 1 : pl.seg_end;
+                GJob dj = j;
+                dj.kind = 2;
+                dj.seg_begin = pl.seg_begin;
+                dj.seg_end = pl.seg_end;
+                dj.kpad = kpad_of(pl.seg_begin, pl.seg_end);
+                dj.kpad_split = kpad_of(pl.seg_begin, far_end);
+                dj.mode = !has_td ? 1 : far_end > pl.seg_begin ? 2 : 0;
+                if (dj.mode == 0) dj.kpad_split = 0;
                 for (int64_t e = r.far_ptr[a]; e < r.far_ptr[a + 1]; e++)
-                    if (r.rank[r.far_col[e]] > 0) fj.preds.push_back(up_job[r.far_col[e]]);
-                const int32_t far_idx = (int32_t)mjobs.size();
-                mjobs.push_back(fj);
-                down_final[a] = far_idx;
-                if (has_td) {
-                    GJob tj = j;
-                    tj.kind = 5;
-                    tj.mode = 0;
-                    tj.accumulate = 1;
-                    tj.seg_begin = pl.seg_end - 1;
-                    tj.seg_end = pl.seg_end;
-                    tj.kpad = kpad_of(tj.seg_begin, tj.seg_end);
-                    tj.preds = {far_idx, down_final[p]};
-                    down_final[a] = (int32_t)mjobs.size();
-                    mjobs.push_back(tj);
-                }
+                    if (r.rank[r.far_col[e]] > 0) dj.preds.push_back(up_job[r.far_col[e]]);
+                if (has_td) dj.preds.push_back(down_job[p]);
+                down_job[a] = (int32_t)mjobs.size();
+                mjobs.push_back(dj);
             } else {
                 const bool far_part = r.rank[a] > 0 && r.level[a] >= 1;
                 GJob nj = j;
@@ -383,6 +377,7 @@ hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_mat
                 nj.seg_begin = pl.seg_begin;
                 nj.seg_end = far_part ? pl.seg_end - 1 : pl.seg_end;
                 nj.kpad = kpad_of(nj.seg_begin, nj.seg_end);
+                nj.kpad_split = nj.kpad;
                 near_job[a] = (int32_t)mjobs.size();
                 mjobs.push_back(nj);
                 if (far_part) {
@@ -393,7 +388,8 @@ hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_mat
                     fj.seg_begin = pl.seg_end - 1;
                     fj.seg_end = pl.seg_end;
                     fj.kpad = kpad_of(fj.seg_begin, fj.seg_end);
-                    fj.preds = {near_job[a], down_final[a]};
+                    fj.kpad_split = fj.kpad;
+                    fj.preds = {near_job[a], down_job[a]};
                     mjobs.push_back(fj);
                 }
             }

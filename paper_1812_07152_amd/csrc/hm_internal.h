@@ -101,7 +101,9 @@ struct PTask {
     int32_t mat;         // index into the MatDesc table
     int32_t ndeps;       // entries that must finish first
     int32_t succ_begin, succ_end;  // successor entries (queue positions) in the succ array
-    int32_t mode;        // 0: products in the launch's type; 1: split BF16 (hi+lo) with FP32 accumulation
+    int32_t mode;        // 0: products in the launch's type; 1: split BF16 (hi+lo) with FP32
+                         // accumulation; 2: split BF16 for all segments but the last, FP64 for
+                         // the last one, continuing from the FP32 partial sums
 };
 
 // Device addresses of one matrix for the persistent launch.
@@ -135,8 +137,9 @@ struct GJob {
     int32_t M;
     int32_t seg_begin, seg_end;  // into the matrix's segment table
     int32_t accumulate;
-    int32_t mode;        // 0 native, 1 split BF16
+    int32_t mode;        // 0 native, 1 split BF16, 2 split BF16 then FP64 (see PTask)
     int64_t kpad;        // sum of Kpad over its segments (work model)
+    int64_t kpad_split;  // the part of kpad computed in split BF16
     std::vector<int32_t> preds;  // job indices
 };
 

@@ -79,20 +79,37 @@ struct TileJob {
     int32_t out_buf, M, m0, seg_begin, seg_end, accumulate;
 };
 
-// Computes rows [0, M) x columns [n0, n0 + BN) of one output block:
-//   out (=|+=) sum over segments of A_s (K-major in the store) * B_s rows.
-// NT threads take part in loads and barriers; the first WAVES_M * WAVES_N
-// waves own FM x FN MFMA fragments each.  As/Bs are LDS buffers of
-// 2 x kBK x (BM + pad) and 2 x kBK x (BN + pad) elements.
-template <typename T, int BM, int BN, int WAVES_M, int WAVES_N, int NT>
-__device__ __forceinline__ void block_product(const TileJob &task, const Seg *__restrict__ segs,
-                                              const T *__restrict__ store, T *buf0, T *buf1,
-                                              T *buf2, T *buf3, int64_t ldq, int64_t n0, T *As_,
-                                              T *Bs_) {
+// Fragment grid of a BM x BN tile over WAVES_M x WAVES_N waves.
+template <int BM, int BN, int WAVES_M, int WAVES_N>
+struct Tile {
+    static constexpr int WM = BM / WAVES_M, WN = BN / WAVES_N;
+    static constexpr int FM = WM / 16, FN = WN / 16;
+};
+
+// Row of accumulator register r of lane l within a 16 x 16 fragment:
+// 4r + l/16 (FP64 MFMA) or 4(l/16) + r (FP32 accumulation, and FP64 with
+// permuted A rows, see product_loop).
+template <bool F32_ROWS>
+__device__ __forceinline__ int frag_row(int lane, int r) {
+    return F32_ROWS ? 4 * (lane >> 4) + r : 4 * r + (lane >> 4);
+}
+
+// Accumulates rows [m0, m0 + BM) x columns [n0, n0 + BN) of
+//   sum over segments [sb, se) of A_s (K-major in the store) * B_s rows
+// into acc.  NT threads take part in loads and barriers; the first
+// WAVES_M * WAVES_N waves own FM x FN MFMA fragments each.  As/Bs are LDS
+// buffers of 2 x kBK x (BM + pad) and 2 x kBK x (BN + pad) elements.
+// ROWPERM (FP64 only): fragment row x reads A row 4(x % 4) + x / 4, which
+// puts the FP64 accumulators in the FP32 register layout (frag_row<true>),
+// so that a product can continue from FP32 partial sums.
+template <typename T, int BM, int BN, int WAVES_M, int WAVES_N, int NT, bool ROWPERM = false>
+__device__ __forceinline__ void product_loop(
+    const Seg *__restrict__ segs, int sb, int se, int m0, const T *__restrict__ store, T *buf0, T *buf1,
+    T *buf2, T *buf3, int64_t ldq, int64_t n0, T *As_, T *Bs_,
+    typename Mfma<T>::acc_t (&acc)[Tile<BM, BN, WAVES_M, WAVES_N>::FM][Tile<BM, BN, WAVES_M, WAVES_N>::FN]) {
     using M_ = Mfma<T>;
-    using acc_t = typename M_::acc_t;
     using vec_t = typename M_::vec_t;
-    constexpr int WM = BM / WAVES_M, WN = BN / WAVES_N;
+    constexpr int WM = Tile<BM, BN, WAVES_M, WAVES_N>::WM, WN = Tile<BM, BN, WAVES_M, WAVES_N>::WN;
     constexpr int FM = WM / 16, FN = WN / 16;
     constexpr int VEC = M_::kVec;
     constexpr int A_ROWV = BM / VEC, B_ROWV = BN / VEC;        // vectors per chunk row
@@ -107,14 +124,9 @@ __device__ __forceinline__ void block_product(const TileJob &task, const Seg *__
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const bool computes = wave < WAVES_M * WAVES_N;
     const int wm = wave / WAVES_N, wn = wave % WAVES_N;
+    const int arow = ROWPERM ? 4 * (lane & 3) + ((lane >> 2) & 3) : (lane & 15);
     // buffer select without a dynamically indexed private array
     auto bufp = [&](int b) { return b == 0 ? buf0 : b == 1 ? buf1 : b == 2 ? buf2 : buf3; };
-
-    acc_t acc[FM][FN];
-#pragma unroll
-    for (int i = 0; i < FM; i++)
-#pragma unroll
-        for (int j = 0; j < FN; j++) acc[i][j] = acc_t{0, 0, 0, 0};
 
     vec_t ra[A_PER], rb[B_PER];
 
@@ -122,7 +134,7 @@ __device__ __forceinline__ void block_product(const TileJob &task, const Seg *__
     // Unconditional loads: thread slots beyond the chunk re-load its last
     // vector, B rows beyond K re-load row K-1 (multiplied by zero rows of A).
     auto load = [&](const Seg &sg, int kk) {
-        const T *A = store + sg.a_off + task.m0 + (int64_t)kk * sg.lda;
+        const T *A = store + sg.a_off + m0 + (int64_t)kk * sg.lda;
         const T *Bp = bufp(sg.b_buf) + (sg.b_row) * ldq + n0;
 #pragma unroll
         for (int u = 0; u < A_PER; u++) {
@@ -157,7 +169,7 @@ __device__ __forceinline__ void block_product(const TileJob &task, const Seg *__
             T af[FM], bf[FN];
             const int kr = ks + (lane >> 4);
 #pragma unroll
-            for (int i = 0; i < FM; i++) af[i] = As[b][kr][wm * WM + i * 16 + (lane & 15)];
+            for (int i = 0; i < FM; i++) af[i] = As[b][kr][wm * WM + i * 16 + arow];
 #pragma unroll
             for (int j = 0; j < FN; j++) bf[j] = Bs[b][kr][wn * WN + j * 16 + (lane & 15)];
 #pragma unroll
@@ -167,8 +179,8 @@ __device__ __forceinline__ void block_product(const TileJob &task, const Seg *__
         }
     };
 
-    if (task.seg_begin < task.seg_end) {
-        int s = task.seg_begin, kk = 0, b = 0;
+    if (sb < se) {
+        int s = sb, kk = 0, b = 0;
         Seg sg = segs[s];
         load(sg, 0);
         stash(0);
@@ -179,9 +191,9 @@ __device__ __forceinline__ void block_product(const TileJob &task, const Seg *__
             if (nkk >= sg.Kpad) {
                 ns = s + 1;
                 nkk = 0;
-                if (ns < task.seg_end) nsg = segs[ns];
+                if (ns < se) nsg = segs[ns];
             }
-            const bool more = ns < task.seg_end;
+            const bool more = ns < se;
             load(nsg, more ? nkk : kk);  // on the last chunk: a harmless re-load
             if (computes) compute(b);
             stash(b ^ 1);
@@ -193,22 +205,53 @@ __device__ __forceinline__ void block_product(const TileJob &task, const Seg *__
             b ^= 1;
         }
     }
+}
 
-    if (!computes) return;
-    T *out = bufp(task.out_buf) + task.out_row * ldq + n0;
+// Writes (or, with task.accumulate, adds) the tile's accumulators to rows
+// [0, task.M) x columns [n0, n0 + BN) of the task's output block.
+template <typename OUT, typename ACC, int BM, int BN, int WAVES_M, int WAVES_N, bool F32_ROWS>
+__device__ __forceinline__ void store_tile(const TileJob &task, OUT *buf0, OUT *buf1, OUT *buf2, OUT *buf3,
+                                           int64_t ldq, int64_t n0,
+                                           const ACC (&acc)[Tile<BM, BN, WAVES_M, WAVES_N>::FM]
+                                                           [Tile<BM, BN, WAVES_M, WAVES_N>::FN]) {
+    constexpr int WM = Tile<BM, BN, WAVES_M, WAVES_N>::WM, WN = Tile<BM, BN, WAVES_M, WAVES_N>::WN;
+    constexpr int FM = WM / 16, FN = WN / 16;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (wave >= WAVES_M * WAVES_N) return;
+    const int wm = wave / WAVES_N, wn = wave % WAVES_N;
+    OUT *base = task.out_buf == 0 ? buf0 : task.out_buf == 1 ? buf1 : task.out_buf == 2 ? buf2 : buf3;
+    OUT *out = base + task.out_row * ldq + n0;
 #pragma unroll
     for (int i = 0; i < FM; i++)
 #pragma unroll
         for (int j = 0; j < FN; j++)
 #pragma unroll
             for (int r = 0; r < 4; r++) {
-                const int row = wm * WM + i * 16 + M_::row(lane, r);
+                const int row = wm * WM + i * 16 + frag_row<F32_ROWS>(lane, r);
                 const int col = wn * WN + j * 16 + (lane & 15);
                 if (row < task.M) {
-                    T *o = out + (int64_t)row * ldq + col;
-                    *o = task.accumulate ? *o + acc[i][j][r] : acc[i][j][r];
+                    OUT *o = out + (int64_t)row * ldq + col;
+                    *o = task.accumulate ? *o + (OUT)acc[i][j][r] : (OUT)acc[i][j][r];
                 }
             }
+}
+
+// One output tile: out (=|+=) sum over the task's segments of A_s * B_s.
+template <typename T, int BM, int BN, int WAVES_M, int WAVES_N, int NT>
+__device__ __forceinline__ void block_product(const TileJob &task, const Seg *__restrict__ segs,
+                                              const T *__restrict__ store, T *buf0, T *buf1,
+                                              T *buf2, T *buf3, int64_t ldq, int64_t n0, T *As_,
+                                              T *Bs_) {
+    typedef Tile<BM, BN, WAVES_M, WAVES_N> TL;
+    typename Mfma<T>::acc_t acc[TL::FM][TL::FN];
+#pragma unroll
+    for (int i = 0; i < TL::FM; i++)
+#pragma unroll
+        for (int j = 0; j < TL::FN; j++) acc[i][j] = typename Mfma<T>::acc_t{0, 0, 0, 0};
+    product_loop<T, BM, BN, WAVES_M, WAVES_N, NT>(segs, task.seg_begin, task.seg_end, task.m0, store, buf0,
+                                                  buf1, buf2, buf3, ldq, n0, As_, Bs_, acc);
+    store_tile<T, typename Mfma<T>::acc_t, BM, BN, WAVES_M, WAVES_N, sizeof(T) == 4>(task, buf0, buf1, buf2,
+                                                                                     buf3, ldq, n0, acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -239,12 +282,21 @@ template <int BM, int BN>
 constexpr int bf16_lds_bytes() {
     return 2 * 2 * (BM + BN) * kKCP * 2;
 }
+// LDS of a split-then-FP64 tile: the split-BF16 buffers, or the FP32 partial
+// sums of the whole tile while they are handed over, whichever is larger.
+template <int BM, int BN>
+constexpr int split_f64_lds_bytes() {
+    return bf16_lds_bytes<BM, BN>() > BM * BN * 4 ? bf16_lds_bytes<BM, BN>() : BM * BN * 4;
+}
 
+// Accumulates rows [m0, m0 + BM) x columns [n0, n0 + BN) of the split-BF16
+// products of segments [sb, se) into FP32 accumulators (FP32 register
+// layout, frag_row<true>).
 template <int BM, int BN, int WAVES_M, int WAVES_N, int NT>
-__device__ __forceinline__ void block_product_bf16x3(const TileJob &task, const Seg *__restrict__ segs,
-                                                     const __bf16 *__restrict__ store16, double *buf0,
-                                                     double *buf1, double *buf2, double *buf3,
-                                                     int64_t ldq, int64_t n0, char *lds) {
+__device__ __forceinline__ void product_loop_bf16x3(
+    const Seg *__restrict__ segs, int sb, int se, int m0, const __bf16 *__restrict__ store16, double *buf0,
+    double *buf1, double *buf2, double *buf3, int64_t ldq, int64_t n0, char *lds,
+    f4_t (&acc)[Tile<BM, BN, WAVES_M, WAVES_N>::FM][Tile<BM, BN, WAVES_M, WAVES_N>::FN]) {
     constexpr int WM = BM / WAVES_M, WN = BN / WAVES_N;
     constexpr int FM = WM / 16, FN = WN / 16;
     static_assert(FM >= 1 && FN >= 1, "bad tile");
@@ -263,12 +315,6 @@ __device__ __forceinline__ void block_product_bf16x3(const TileJob &task, const 
     const int wm = wave / WAVES_N, wn = wave % WAVES_N;
     auto bufp = [&](int b) { return b == 0 ? buf0 : b == 1 ? buf1 : b == 2 ? buf2 : buf3; };
 
-    f4_t acc[FM][FN];
-#pragma unroll
-    for (int i = 0; i < FM; i++)
-#pragma unroll
-        for (int j = 0; j < FN; j++) acc[i][j] = f4_t{0, 0, 0, 0};
-
     s16x8_t ra[A_PER];
     d2_t rb0[B_PER], rb1[B_PER];
 
@@ -280,7 +326,7 @@ __device__ __forceinline__ void block_product_bf16x3(const TileJob &task, const 
             const int idx = min(tid + u * NT, A_VECS - 1);
             const int part = idx / (BM * 4), rem = idx % (BM * 4), r = rem / 4, c = (rem % 4) * 8;
             ra[u] = *reinterpret_cast<const s16x8_t *>(A + (int64_t)part * sg.lda * kKC +
-                                                      (int64_t)(task.m0 + r) * kKC + c);
+                                                      (int64_t)(m0 + r) * kKC + c);
         }
         const double *Bp = bufp(sg.b_buf) + sg.b_row * ldq + n0;
 #pragma unroll
@@ -342,8 +388,8 @@ __device__ __forceinline__ void block_product_bf16x3(const TileJob &task, const 
             }
     };
 
-    if (task.seg_begin < task.seg_end) {
-        int s = task.seg_begin, kk = 0, b = 0;
+    if (sb < se) {
+        int s = sb, kk = 0, b = 0;
         Seg sg = segs[s];
         load(sg, 0);
         stash(0);
@@ -354,9 +400,9 @@ __device__ __forceinline__ void block_product_bf16x3(const TileJob &task, const 
             if (nkk >= sg.K) {
                 ns = s + 1;
                 nkk = 0;
-                if (ns < task.seg_end) nsg = segs[ns];
+                if (ns < se) nsg = segs[ns];
             }
-            const bool more = ns < task.seg_end;
+            const bool more = ns < se;
             load(nsg, more ? nkk : kk);
             if (computes) compute(b);
             stash(b ^ 1);
@@ -368,22 +414,72 @@ __device__ __forceinline__ void block_product_bf16x3(const TileJob &task, const 
             b ^= 1;
         }
     }
+}
 
-    if (!computes) return;
-    double *out = bufp(task.out_buf) + task.out_row * ldq + n0;
+// One output tile in split BF16: out (=|+=) sum over the task's segments.
+template <int BM, int BN, int WAVES_M, int WAVES_N, int NT>
+__device__ __forceinline__ void block_product_bf16x3(const TileJob &task, const Seg *__restrict__ segs,
+                                                     const __bf16 *__restrict__ store16, double *buf0,
+                                                     double *buf1, double *buf2, double *buf3,
+                                                     int64_t ldq, int64_t n0, char *lds) {
+    typedef Tile<BM, BN, WAVES_M, WAVES_N> TL;
+    f4_t acc[TL::FM][TL::FN];
 #pragma unroll
-    for (int i = 0; i < FM; i++)
+    for (int i = 0; i < TL::FM; i++)
 #pragma unroll
-        for (int j = 0; j < FN; j++)
+        for (int j = 0; j < TL::FN; j++) acc[i][j] = f4_t{0, 0, 0, 0};
+    product_loop_bf16x3<BM, BN, WAVES_M, WAVES_N, NT>(segs, task.seg_begin, task.seg_end, task.m0, store16,
+                                                      buf0, buf1, buf2, buf3, ldq, n0, lds, acc);
+    store_tile<double, f4_t, BM, BN, WAVES_M, WAVES_N, true>(task, buf0, buf1, buf2, buf3, ldq, n0, acc);
+}
+
+// A down-pass tile of the mixed-precision graph: the far blocks (all
+// segments but the last) in split BF16 with FP32 accumulation, then the
+// transfer from the parent (the last segment) in FP64 continuing from those
+// partial sums (converted to FP64), written once.
+template <int BM, int BN, int WAVES_M, int WAVES_N, int NT>
+__device__ __forceinline__ void block_product_split_then_f64(const TileJob &task, const Seg *__restrict__ segs,
+                                                             const double *__restrict__ store,
+                                                             const __bf16 *__restrict__ store16, double *buf0,
+                                                             double *buf1, double *buf2, double *buf3,
+                                                             int64_t ldq, int64_t n0, char *lds) {
+    typedef Tile<BM, BN, WAVES_M, WAVES_N> TL;
+    f4_t acc32[TL::FM][TL::FN];
 #pragma unroll
-            for (int r = 0; r < 4; r++) {
-                const int row = wm * WM + i * 16 + 4 * (lane >> 4) + r;
-                const int col = wn * WN + j * 16 + (lane & 15);
-                if (row < task.M) {
-                    double *o = out + (int64_t)row * ldq + col;
-                    *o = task.accumulate ? *o + (double)acc[i][j][r] : (double)acc[i][j][r];
-                }
-            }
+    for (int i = 0; i < TL::FM; i++)
+#pragma unroll
+        for (int j = 0; j < TL::FN; j++) acc32[i][j] = f4_t{0, 0, 0, 0};
+    product_loop_bf16x3<BM, BN, WAVES_M, WAVES_N, NT>(segs, task.seg_begin, task.seg_end - 1, task.m0, store16,
+                                                      buf0, buf1, buf2, buf3, ldq, n0, lds, acc32);
+    // hand the partial sums over through LDS (free once the split loop has
+    // ended), so that the FP32 and FP64 accumulators are never live together
+    constexpr int kVals = TL::FM * TL::FN * 4;
+    float *stage = reinterpret_cast<float *>(lds);
+    const bool computes = (int)(threadIdx.x >> 6) < WAVES_M * WAVES_N;
+    if (computes) {
+#pragma unroll
+        for (int i = 0; i < TL::FM; i++)
+#pragma unroll
+            for (int j = 0; j < TL::FN; j++)
+#pragma unroll
+                for (int r = 0; r < 4; r++) stage[((i * TL::FN + j) * 4 + r) * NT + threadIdx.x] = acc32[i][j][r];
+    }
+    __syncthreads();
+    d4_t acc[TL::FM][TL::FN];
+#pragma unroll
+    for (int i = 0; i < TL::FM; i++)
+#pragma unroll
+        for (int j = 0; j < TL::FN; j++)
+#pragma unroll
+            for (int r = 0; r < 4; r++)
+                acc[i][j][r] = computes ? (double)stage[((i * TL::FN + j) * 4 + r) * NT + threadIdx.x] : 0.0;
+    static_assert(kVals * NT * 4 <= split_f64_lds_bytes<BM, BN>(), "LDS hand-over does not fit");
+    __syncthreads();
+    double *As = reinterpret_cast<double *>(lds);
+    double *Bs = As + 2 * kBK * (BM + lds_pad<double>());
+    product_loop<double, BM, BN, WAVES_M, WAVES_N, NT, true>(segs, task.seg_end - 1, task.seg_end, task.m0, store,
+                                                             buf0, buf1, buf2, buf3, ldq, n0, As, Bs, acc);
+    store_tile<double, d4_t, BM, BN, WAVES_M, WAVES_N, true>(task, buf0, buf1, buf2, buf3, ldq, n0, acc);
 }
 
 // Split-BF16 copy of one block per workgroup: for chunk c, part h (0 hi,
@@ -444,7 +540,7 @@ __global__ __launch_bounds__(kPersistThreads) void k_persistent(
     const PTask *__restrict__ tasks, int n_tasks, const int32_t *__restrict__ succ,
     int32_t *counters, int32_t *head, int32_t *err, const MatDesc *__restrict__ mats) {
     constexpr int kNative = (2 * kBK * (128 + lds_pad<T>()) + 2 * kBK * (BN + lds_pad<T>())) * (int)sizeof(T);
-    constexpr int kSplit = (SPLIT && sizeof(T) == 8) ? bf16_lds_bytes<128, BN>() : 0;
+    constexpr int kSplit = (SPLIT && sizeof(T) == 8) ? split_f64_lds_bytes<128, BN>() : 0;
     __shared__ __attribute__((aligned(16))) char lds[kNative > kSplit ? kNative : kSplit];
     T *As = reinterpret_cast<T *>(lds);
     T *Bs = As + 2 * kBK * (128 + lds_pad<T>());
@@ -472,19 +568,27 @@ __global__ __launch_bounds__(kPersistThreads) void k_persistent(
         const int64_t n0 = (int64_t)pt.qtile * BN;
         const T *store = (const T *)md.store;
         const Seg *segs = md.segs;
-        bool split = false;
-        if constexpr (SPLIT && sizeof(T) == 8) split = pt.mode == 1;
-        if (split) {
+        int mode = 0;
+        if constexpr (SPLIT && sizeof(T) == 8) mode = pt.mode;
+        if (mode != 0) {
             if constexpr (SPLIT && sizeof(T) == 8) {
                 const __bf16 *s16 = (const __bf16 *)md.store16;
-                if (pt.bm == 128)
+                double *b0 = (double *)md.buf[0], *b1 = (double *)md.buf[1], *b2 = (double *)md.buf[2],
+                       *b3 = (double *)md.buf[3];
+                if (mode == 1 && pt.bm == 128)
                     block_product_bf16x3<128, BN, PLayout<128, BN>::WMv, PLayout<128, BN>::WN, kPersistThreads>(
-                        job, segs, s16, (double *)md.buf[0], (double *)md.buf[1], (double *)md.buf[2],
-                        (double *)md.buf[3], md.ldq, n0, lds);
-                else
+                        job, segs, s16, b0, b1, b2, b3, md.ldq, n0, lds);
+                else if (mode == 1)
                     block_product_bf16x3<64, BN, PLayout<64, BN>::WMv, PLayout<64, BN>::WN, kPersistThreads>(
-                        job, segs, s16, (double *)md.buf[0], (double *)md.buf[1], (double *)md.buf[2],
-                        (double *)md.buf[3], md.ldq, n0, lds);
+                        job, segs, s16, b0, b1, b2, b3, md.ldq, n0, lds);
+                else if (pt.bm == 128)
+                    block_product_split_then_f64<128, BN, PLayout<128, BN>::WMv, PLayout<128, BN>::WN,
+                                                 kPersistThreads>(job, segs, (const double *)store, s16, b0, b1,
+                                                                  b2, b3, md.ldq, n0, lds);
+                else
+                    block_product_split_then_f64<64, BN, PLayout<64, BN>::WMv, PLayout<64, BN>::WN,
+                                                 kPersistThreads>(job, segs, (const double *)store, s16, b0, b1,
+                                                                  b2, b3, md.ldq, n0, lds);
             }
         } else if (pt.bm == 128)
             block_product<T, 128, BN, PLayout<128, BN>::WMv, PLayout<128, BN>::WN, kPersistThreads>(

@@ -62,7 +62,7 @@ hm_status build_plan(const std::vector<PlanPart> &parts, int bn, int workers, Gr
         for (int j = 0; j < nj; j++)
             for (int r = 0; r < p.rows[j]; r++)
                 p.cost[p.first[j] + r] =
-                    2.0 * p.bm[j] * jobs[j].kpad * bn * (jobs[j].mode == 1 ? 0.35 : 1.0) + overhead;
+                    2.0 * p.bm[j] * bn * (jobs[j].kpad - 0.65 * jobs[j].kpad_split) + overhead;
         // critical path to the end of the graph (jobs are topologically ordered)
         std::vector<double> jbl(nj, 0.0);
         for (int j = nj - 1; j >= 0; j--) {
@@ -96,12 +96,34 @@ hm_status build_plan(const std::vector<PlanPart> &parts, int bn, int workers, Gr
             }
     const std::vector<int32_t> ndeps = remaining;
 
+    // tie-break key among entries of equal priority: the row and column
+    // tiles of one job come one after another, so that they run at the same
+    // time and share their operands in the caches
+    std::vector<int64_t> ekey(total);
+    {
+        int64_t job_base = 0, max_nq = 1, max_rows = 1;
+        for (const P &p : ps) {
+            max_nq = std::max<int64_t>(max_nq, p.nq);
+            for (int32_t rr : p.rows) max_rows = std::max<int64_t>(max_rows, rr);
+        }
+        for (const P &p : ps) {
+            const std::vector<GJob> &jobs = *p.jobs;
+            for (int q = 0; q < p.nq; q++)
+                for (size_t j = 0; j < jobs.size(); j++)
+                    for (int r = 0; r < p.rows[j]; r++)
+                        ekey[p.base + (int64_t)q * p.per_q + p.first[j] + r] =
+                            ((job_base + (int64_t)j) * max_nq + q) * max_rows + r;
+            job_base += (int64_t)jobs.size();
+        }
+    }
+
     // list scheduling: the earliest-free simulated workgroup takes the
     // released entry with the longest critical path
     struct Avail {
         double bl;
+        int64_t key;
         int e;
-        bool operator<(const Avail &o) const { return bl < o.bl || (bl == o.bl && e > o.e); }
+        bool operator<(const Avail &o) const { return bl < o.bl || (bl == o.bl && key > o.key); }
     };
     std::priority_queue<Avail> avail;
     typedef std::pair<double, int> Ev;  // (finish time, entry)
@@ -119,7 +141,7 @@ hm_status build_plan(const std::vector<PlanPart> &parts, int bn, int workers, Gr
         return ps[pi].cost[ps[pi].first[j] + r];
     };
     for (int e = 0; e < total; e++)
-        if (remaining[e] == 0) avail.push({blevel_of(e), e});
+        if (remaining[e] == 0) avail.push({blevel_of(e), ekey[e], e});
     auto release = [&](int e) {
         int pi, q, j, r;
         locate(e, pi, q, j, r);
@@ -127,7 +149,7 @@ hm_status build_plan(const std::vector<PlanPart> &parts, int bn, int workers, Gr
         for (int32_t s2 : p.succ_jobs[j])
             for (int rr = 0; rr < p.rows[s2]; rr++) {
                 const int f = (int)(p.base + (int64_t)q * p.per_q + p.first[s2] + rr);
-                if (--remaining[f] == 0) avail.push({p.blevel[p.first[s2] + rr], f});
+                if (--remaining[f] == 0) avail.push({p.blevel[p.first[s2] + rr], ekey[f], f});
             }
     };
     std::vector<int32_t> order;
