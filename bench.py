@@ -268,30 +268,26 @@ def bench_serving(args) -> dict:
     }
 
 
-def bench_mixed(args) -> dict:
-    """Mixed-precision form: N = 262144 points in d = 28 (i.i.d. normal),
-    kernel exp(-r/4), leaf 256, tol 1e-4, rank <= 256, HSS, W: N x 1024 FP64.
-    The split-BF16 evaluation against the plain FP64 and FP32 paths on the
-    same matrix, with its error against the FP64 result."""
+def _mixed_one(args, w, adm_name: str, kernel_name: str) -> dict:
+    """Times one workload in FP64, split BF16 and FP32 on the same compressed
+    matrix; errors are relative Frobenius norms against the FP64 result."""
     import torch
 
     import paper_1812_07152_amd as hmx
     import workloads as wl
-    w = wl.C4
     t = time.perf_counter()
     R = hmx.hm_compress(wl.gen_points(w), kernel=w.kernel, h=w.h, leaf_size=w.m, tol=w.tol,
                         max_rank=w.rmax, admissibility=w.adm, tau=w.tau, sample_rows=w.sample_rows,
                         seed=w.sample_seed)
     t_compress = time.perf_counter() - t
-    print(f"[mixed] compressed in {t_compress:.0f} s", file=sys.stderr, flush=True)
+    print(f"[mixed] {w.name}: compressed in {t_compress:.0f} s", file=sys.stderr, flush=True)
     mask = hmx.precbit(hmx.HM_PREC_FP64) | hmx.precbit(hmx.HM_PREC_BF16X3) | hmx.precbit(hmx.HM_PREC_FP32)
     M = hmx.hm_load_compressed_mem(R, 0, mask)
     del R
     info = hmx.hm_info(M)
     flops = info["flops_per_col"] * w.Q
     W = torch.from_numpy(wl.gen_w(w)).cuda()
-    out = {}
-    results = {}
+    out, results = {}, {}
     for name, Wx, prec in (("fp64", W, hmx.HM_PREC_FP64), ("bf16x3", W, hmx.HM_PREC_BF16X3),
                            ("fp32", W.float(), hmx.HM_PREC_FP32)):
         Y = torch.empty_like(Wx)
@@ -306,23 +302,38 @@ def bench_mixed(args) -> dict:
         hmx.hm_check(M)
         results[name] = Y.double()
         out[name] = {"ms_per_step": ms, "gflops": flops / (ms * 1e-3) / 1e9}
-        print(f"[mixed] {name}: {ms:.2f} ms", file=sys.stderr, flush=True)
+        print(f"[mixed] {w.name} {name}: {ms:.2f} ms", file=sys.stderr, flush=True)
     ref = results["fp64"]
     for name in ("bf16x3", "fp32"):
         out[name]["rel_err_vs_fp64"] = float((results[name] - ref).norm() / ref.norm())
     return {
-        "metric": "mixed-precision K~W GFLOP/s (algorithmic) vs the plain FP64 path",
-        "value": out["bf16x3"]["gflops"], "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": out["bf16x3"]["ms_per_step"], "higher_is_better": True,
-        "dtype": "bf16x3+f64", "data": "synthetic",
-        "config": {"workload": w.name, "N": w.N, "d": w.d, "Q": w.Q, "kernel": "exp(-r/h)", "h": w.h,
-                   "leaf": w.m, "tol": w.tol, "max_rank": w.rmax, "admissibility": "HSS",
+        "config": {"workload": w.name, "N": w.N, "d": w.d, "Q": w.Q, "kernel": kernel_name, "h": w.h,
+                   "leaf": w.m, "tol": w.tol, "max_rank": w.rmax, "admissibility": adm_name,
                    "gflop_per_step": flops / 1e9, "E_V": info["E_V"], "E_T": info["E_T"],
                    "E_B": info["E_B"], "E_D": info["E_D"],
-                   "fp64_transfer_share": 4 * info["E_T"] / (info["flops_per_col"] / 1)},
+                   "fp64_transfer_share": 4 * info["E_T"] / info["flops_per_col"]},
         "paths": out,
         "speedup_vs_fp64": out["fp64"]["ms_per_step"] / out["bf16x3"]["ms_per_step"],
         "setup_s": {"compress": t_compress},
+    }
+
+
+def bench_mixed(args) -> dict:
+    """Mixed-precision form: N = 262144 points in d = 28 (i.i.d. normal),
+    kernel exp(-r/4), leaf 256, tol 1e-4, rank <= 256, HSS, W: N x 1024 FP64
+    (the reported line), and the N = 65536, d = 8, Q = 256 distance-admissible
+    workload beside it.  Split BF16 against the plain FP64 and FP32 paths on
+    the same matrix, with its error against the FP64 result."""
+    import workloads as wl
+    main_run = _mixed_one(args, wl.C4, "HSS", "exp(-r/h)")
+    also = _mixed_one(args, wl.C2, f"distance tau={wl.C2.tau}", "gaussian") if args.mixed_both else None
+    m = main_run["paths"]["bf16x3"]
+    return {
+        "metric": "mixed-precision K~W GFLOP/s (algorithmic) vs the plain FP64 path",
+        "value": m["gflops"], "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": m["ms_per_step"], "higher_is_better": True,
+        "dtype": "bf16x3+f64", "data": "synthetic", **main_run,
+        "also": also,
     }
 
 
@@ -333,6 +344,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--mixed-c4-only", dest="mixed_both", action="store_false",
+                    help="mixed form: skip the N=65536 workload reported beside the main one")
     ap.add_argument("--form", choices=("plain", "batched", "serving", "mixed"), default="plain",
                     help="plain: the headline workload; batched: 64 uneven matrices in one launch; "
                          "serving: 8 resident matrices under a request stream")
