@@ -59,6 +59,30 @@ struct Mfma<float> {
     static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 
+// Loads of the block store and the workspaces go through global (address
+// space 1) pointers.  The persistent launch reads its buffer addresses from a
+// descriptor in memory, so the compiler cannot infer their address space and
+// would emit flat loads; a flat load also counts against the LDS wait
+// counter, so the wait for the LDS reads of the current chunk would wait for
+// the global loads of the next one as well.
+template <typename V>
+__device__ __forceinline__ V load_global(const void *p) {
+    return *(const __attribute__((address_space(1))) V *)p;
+}
+
+__device__ __forceinline__ Seg load_seg(const Seg *p) {
+    const __attribute__((address_space(1))) Seg *g = (const __attribute__((address_space(1))) Seg *)p;
+    Seg s;
+    s.a_off = g->a_off;
+    s.b_row = g->b_row;
+    s.lda = g->lda;
+    s.K = g->K;
+    s.b_buf = g->b_buf;
+    s.Kpad = g->Kpad;
+    s.a_off16 = g->a_off16;
+    return s;
+}
+
 constexpr int kBK = 16;
 // LDS rows are padded by 128 bytes so that the four 16-lane groups of a
 // fragment read land on alternating bank halves.
@@ -140,13 +164,13 @@ __device__ __forceinline__ void product_loop(
         for (int u = 0; u < A_PER; u++) {
             const int idx = min(tid + u * NT, A_VECS - 1);
             const int kr = idx / A_ROWV, c = (idx % A_ROWV) * VEC;
-            ra[u] = *reinterpret_cast<const vec_t *>(A + (int64_t)kr * sg.lda + c);
+            ra[u] = load_global<vec_t>(A + (int64_t)kr * sg.lda + c);
         }
 #pragma unroll
         for (int u = 0; u < B_PER; u++) {
             const int idx = min(tid + u * NT, B_VECS - 1);
             const int kr = min(kk + idx / B_ROWV, sg.K - 1), c = (idx % B_ROWV) * VEC;
-            rb[u] = *reinterpret_cast<const vec_t *>(Bp + (int64_t)kr * ldq + c);
+            rb[u] = load_global<vec_t>(Bp + (int64_t)kr * ldq + c);
         }
     };
     auto stash = [&](int b) {
@@ -181,7 +205,7 @@ __device__ __forceinline__ void product_loop(
 
     if (sb < se) {
         int s = sb, kk = 0, b = 0;
-        Seg sg = segs[s];
+        Seg sg = load_seg(segs + s);
         load(sg, 0);
         stash(0);
         __syncthreads();
@@ -191,7 +215,7 @@ __device__ __forceinline__ void product_loop(
             if (nkk >= sg.Kpad) {
                 ns = s + 1;
                 nkk = 0;
-                if (ns < se) nsg = segs[ns];
+                if (ns < se) nsg = load_seg(segs + ns);
             }
             const bool more = ns < se;
             load(nsg, more ? nkk : kk);  // on the last chunk: a harmless re-load
@@ -230,7 +254,8 @@ __device__ __forceinline__ void store_tile(const TileJob &task, OUT *buf0, OUT *
                 const int row = wm * WM + i * 16 + frag_row<F32_ROWS>(lane, r);
                 const int col = wn * WN + j * 16 + (lane & 15);
                 if (row < task.M) {
-                    OUT *o = out + (int64_t)row * ldq + col;
+                    __attribute__((address_space(1))) OUT *o =
+                        (__attribute__((address_space(1))) OUT *)(out + (int64_t)row * ldq + col);
                     *o = task.accumulate ? *o + (OUT)acc[i][j][r] : (OUT)acc[i][j][r];
                 }
             }
@@ -325,8 +350,7 @@ __device__ __forceinline__ void product_loop_bf16x3(
         for (int u = 0; u < A_PER; u++) {
             const int idx = min(tid + u * NT, A_VECS - 1);
             const int part = idx / (BM * 4), rem = idx % (BM * 4), r = rem / 4, c = (rem % 4) * 8;
-            ra[u] = *reinterpret_cast<const s16x8_t *>(A + (int64_t)part * sg.lda * kKC +
-                                                      (int64_t)(m0 + r) * kKC + c);
+            ra[u] = load_global<s16x8_t>(A + (int64_t)part * sg.lda * kKC + (int64_t)(m0 + r) * kKC + c);
         }
         const double *Bp = bufp(sg.b_buf) + sg.b_row * ldq + n0;
 #pragma unroll
@@ -334,8 +358,8 @@ __device__ __forceinline__ void product_loop_bf16x3(
             const int idx = min(tid + u * NT, B_ITEMS - 1);
             const int pr = idx % (kKC / 2), cp = idx / (kKC / 2);
             const int k0 = min(kk + 2 * pr, sg.K - 1), k1 = min(kk + 2 * pr + 1, sg.K - 1);
-            rb0[u] = *reinterpret_cast<const d2_t *>(Bp + (int64_t)k0 * ldq + 2 * cp);
-            rb1[u] = *reinterpret_cast<const d2_t *>(Bp + (int64_t)k1 * ldq + 2 * cp);
+            rb0[u] = load_global<d2_t>(Bp + (int64_t)k0 * ldq + 2 * cp);
+            rb1[u] = load_global<d2_t>(Bp + (int64_t)k1 * ldq + 2 * cp);
         }
     };
     auto stash = [&](int b) {
@@ -390,7 +414,7 @@ __device__ __forceinline__ void product_loop_bf16x3(
 
     if (sb < se) {
         int s = sb, kk = 0, b = 0;
-        Seg sg = segs[s];
+        Seg sg = load_seg(segs + s);
         load(sg, 0);
         stash(0);
         __syncthreads();
@@ -400,7 +424,7 @@ __device__ __forceinline__ void product_loop_bf16x3(
             if (nkk >= sg.K) {
                 ns = s + 1;
                 nkk = 0;
-                if (ns < se) nsg = segs[ns];
+                if (ns < se) nsg = load_seg(segs + ns);
             }
             const bool more = ns < se;
             load(nsg, more ? nkk : kk);
