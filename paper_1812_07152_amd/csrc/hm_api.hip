@@ -189,7 +189,7 @@ hm_status hm_eval(hm_matrix h, const void *W, int64_t ldw, void *Y, int64_t ldy,
     const char *sched = std::getenv("HM_SCHED");
     const bool level_sched = sched && std::string(sched) == "level" && !mixed;
     int bn_kind[4] = {0, pick_bn(Q, 1), pick_bn(Q, 2), pick_bn(Q, 3)};
-    if (!level_sched) bn_kind[1] = bn_kind[2] = bn_kind[3];  // one tile for the whole graph
+    if (!level_sched) bn_kind[1] = bn_kind[2] = bn_kind[3] = graph_bn(Q, es, mixed, h->task_k);  // one tile for the graph
     const int bn_max = std::max({bn_kind[1], bn_kind[2], bn_kind[3]});
     const int64_t Qp = (Q + bn_max - 1) / bn_max * bn_max;  // workspace leading dimension
     {

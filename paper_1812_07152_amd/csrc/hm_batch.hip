@@ -211,7 +211,9 @@ hm_status hm_batch_create(int n, const hm_matrix *hs, const int64_t *Q, hm_dtype
     HM_HIP(hipMalloc(&b->d_perm, sizeof(PermDesc) * n));
     HM_HIP(hipMalloc(&b->d_head, 2 * sizeof(int32_t)));
     HM_HIP(hipMemset(b->d_head, 0, 2 * sizeof(int32_t)));
-    const int default_bn = pick_bn(maxq, 3);
+    double tk = 0;
+    for (int i = 0; i < n; i++) tk = std::max(tk, hs[i]->task_k);
+    const int default_bn = graph_bn(maxq, b->es, false, tk);
     if (flags & HM_BATCH_AUTOTUNE) {
         // time every candidate tile on the batch's own (zeroed) workspaces
         hipEvent_t t0, t1;

@@ -440,6 +440,7 @@ hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_mat
     // slack after the last block: a tile taller than its block reads past it
     h->store_elems = P.store_off + 512;
     h->phases = P.phases;
+    h->task_k = job_task_k(jobs);
     h->gjobs = std::move(jobs);
     h->gjobs_mixed = std::move(mjobs);
 

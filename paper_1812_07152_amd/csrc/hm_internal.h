@@ -183,6 +183,7 @@ struct hm_matrix_s {
     std::vector<hm::Phase> phases;
     std::vector<hm::GJob> gjobs;           // dependency graph of one evaluation
     std::vector<hm::GJob> gjobs_mixed;     // same, with split-BF16 and FP64 parts separated
+    double task_k = 0;                     // job_task_k(gjobs)
     void *store16 = nullptr;               // split-BF16 block store (HM_PREC_BF16X3)
     size_t store16_bytes = 0;
     std::vector<hm::GraphPlan> plans[2];   // per element size: one plan per (tile, tile count)
@@ -217,6 +218,12 @@ hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_mat
 // 2 down, 3 leaf), honouring the HM_BN_UP / HM_BN_DOWN / HM_BN_LEAF / HM_BN
 // environment overrides.
 int pick_bn(int64_t Q, int kind);
+// Column tile of the persistent task-graph launch for Q columns of elem_bytes
+// (split: the launch runs split-BF16 tiles; task_k: the flop-weighted mean
+// contraction length of the graph's jobs, see job_task_k).
+int graph_bn(int64_t Q, int elem_bytes, bool split, double task_k);
+// Flop-weighted mean contraction length of a job graph: sum M k^2 / sum M k.
+double job_task_k(const std::vector<GJob> &jobs);
 hipError_t launch_phase(const hm_matrix_s *h, const Phase &ph, int elem_bytes, int bn, int64_t ldq,
                         void *const bufs[BUF_COUNT], hipStream_t s);
 hipError_t launch_permute_in(const void *W, int64_t ldw, void *Wt, int64_t Qp, const int64_t *perm,

@@ -548,6 +548,8 @@ struct PLayout {
     static constexpr int WMv = (BM / 16 < 8 / WN) ? BM / 16 : 8 / WN;
 };
 
+// 8 waves per workgroup.  With column tiles up to 128 the kernel is held to
+// 128 VGPRs (4 waves per SIMD), so that two workgroups share a compute unit.
 constexpr int kPersistThreads = 512;
 constexpr int kWaitLimit = 1 << 20;  // polls (each followed by a sleep) before giving up
 
@@ -560,7 +562,7 @@ constexpr int kWaitLimit = 1 << 20;  // polls (each followed by a sleep) before 
 // running workgroup: the launch cannot deadlock and every workgroup exits
 // when the queue is drained.
 template <typename T, int BN, bool SPLIT>
-__global__ __launch_bounds__(kPersistThreads) void k_persistent(
+__global__ __launch_bounds__(kPersistThreads, BN <= 128 ? 4 : 1) void k_persistent(
     const PTask *__restrict__ tasks, int n_tasks, const int32_t *__restrict__ succ,
     int32_t *counters, int32_t *head, int32_t *err, const MatDesc *__restrict__ mats) {
     constexpr int kNative = (2 * kBK * (128 + lds_pad<T>()) + 2 * kBK * (BN + lds_pad<T>())) * (int)sizeof(T);
@@ -787,6 +789,20 @@ int pick_bn(int64_t Q, int kind) {
     if (Q <= 64) return 64;
     if (Q <= 128) return 128;
     return 256;
+}
+
+int graph_bn(int64_t Q, int elem_bytes, bool split, double task_k) {
+    if (std::getenv("HM_BN")) return pick_bn(Q, 0);
+    const int bn = pick_bn(Q, 3);
+    // Tiles up to 128 columns fit two workgroups per compute unit (at most
+    // 128 VGPRs, see k_persistent), so one workgroup's task switches (fetch,
+    // pipeline fill, epilogue) and barriers overlap the other's MFMAs.  That
+    // pays when tasks are short.  An FP64 graph whose work sits in long
+    // contractions (a flop's task has task_k > 8192 contraction rows) keeps
+    // the 256-wide tile, which reads the block store half as often.  The
+    // split-BF16 instantiation does not fit two workgroups and keeps it too.
+    if (split || (elem_bytes == 8 && task_k > 8192.0)) return bn;
+    return std::min(bn, 128);
 }
 
 hipError_t launch_phase(const hm_matrix_s *h, const Phase &ph, int elem_bytes, int bn, int64_t ldq,

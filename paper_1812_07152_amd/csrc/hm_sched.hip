@@ -16,6 +16,15 @@
 
 namespace hm {
 
+double job_task_k(const std::vector<GJob> &jobs) {
+    double num = 0, den = 0;
+    for (const GJob &j : jobs) {
+        num += (double)j.M * (double)j.kpad * (double)j.kpad;
+        den += (double)j.M * (double)j.kpad;
+    }
+    return den > 0 ? num / den : 0.0;
+}
+
 void free_plan(GraphPlan &p) {
     if (p.d_tasks) (void)hipFree(p.d_tasks);
     if (p.d_succ) (void)hipFree(p.d_succ);

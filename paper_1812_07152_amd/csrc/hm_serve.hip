@@ -296,13 +296,16 @@ hm_status hm_server_add(hm_server S, hm_matrix h, int *mat_id) {
     // allocate or synchronize
     const int slot = S->dtype == HM_F64 ? 0 : 1;
     hm_status st = reserve_ws(h, slot, kMaxCols);
-    const int workers_per_cu = 1;
-    for (int64_t q : {16, 32, 64, 128, 256, 512, 768, 1024}) {
-        if (st != HM_OK) break;
-        const int bn = pick_bn(q, 3);
+    // every (column tile, tile count) that hm_eval can choose for a sweep of
+    // 1..kMaxCols columns
+    std::vector<std::pair<int, int64_t>> shapes;
+    for (int64_t q = 1; q <= kMaxCols && st == HM_OK; q++) {
+        const int bn = graph_bn(q, S->es, false, h->task_k);
+        const std::pair<int, int64_t> key{bn, (q + bn - 1) / bn * bn};
+        if (std::find(shapes.begin(), shapes.end(), key) != shapes.end()) continue;
+        shapes.push_back(key);
         GraphPlan *p = nullptr;
-        st = get_plan(h, slot, bn, (q + bn - 1) / bn * bn,
-                      persistent_occupancy(S->es, bn) * h->n_cu * workers_per_cu, &p);
+        st = get_plan(h, slot, bn, key.second, persistent_occupancy(S->es, bn) * h->n_cu, &p);
     }
     const size_t need = 2 * (size_t)h->N * kMaxCols * S->es;
     for (int i = 0; i < S->max_slots && st == HM_OK; i++)
