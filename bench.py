@@ -43,6 +43,20 @@ def measured_traffic(name: str, launches_bytes_fallback=None):
     return d.get("hbm_bytes_per_launch")
 
 
+def measured_counters(name: str):
+    """MFMA utilisation of the dominant kernel from the committed counter
+    summary, if it was taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", f"{name}.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return {"mfma_busy_frac": d["mfma_busy_frac"],
+            "mfma_executed_tflop_per_launch": d["mfma_executed_tflop_per_launch"],
+            "source": f"profiles/{name}.json (rocprofv3 SQ_VALU_MFMA_BUSY_CYCLES, SQ_INSTS_VALU_MFMA_MOPS_F64)"}
+
+
 def time_variant(hmx, torch, M, w, dtype, steps, warmup):
     W = torch.from_numpy(__import__("workloads").gen_w(w)).to("cuda", dtype)
     Y = torch.empty_like(W)
@@ -419,7 +433,8 @@ def main() -> int:
                                                   "near field, leaf far part)",
                      "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
-                     "launch_ms": graph_ms, "algorithmic_gflop_per_launch": flops / 1e9},
+                     "launch_ms": graph_ms, "algorithmic_gflop_per_launch": flops / 1e9,
+                     "counters": measured_counters("task_graph_counters_c2_fp64")},
         "whole_step_frac_of_fp64_peak": flops / (ms64 * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
         "phase_ms": {k: ph64[i] / max(n64[i], 1) for i, k in
                      enumerate(("permute_in", "up", "down", "graph", "permute_out")) if n64[i]},
