@@ -237,10 +237,12 @@ hm_status hm_eval(hm_matrix h, const void *W, int64_t ldw, void *Y, int64_t ldy,
     if ((st = mark(0, false)) != HM_OK) return st;
     if (!level_sched) {
         // the whole graph (up, down, near, leaf far part) in one launch,
-        // reported as the leaf-pass group
+        // reported as the leaf-pass group; the leaf rows are written straight
+        // into Y in the caller's order, so no permute-out follows
         if ((st = mark(3, true)) != HM_OK) return st;
-        HM_HIP(launch_persistent(*plan, es, h->d_mat, h->d_head, grid, s));
+        HM_HIP(launch_persistent(*plan, es, h->d_mat, h->d_head, grid, s, OutScatter{Y, ldy, Q, perm}));
         if ((st = mark(3, false)) != HM_OK) return st;
+        return HM_OK;
     } else {
         int open_group = -1;
         for (const Phase &ph : h->phases) {

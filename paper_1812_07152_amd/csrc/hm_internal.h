@@ -240,9 +240,18 @@ hipError_t launch_repack(const double *stage, const RepackJob *jobs, int njobs, 
 // max_elems bounds N * ldq over the batch.
 hipError_t launch_permute_batched(const PermDesc *d, int n, int64_t max_elems, int elem_bytes,
                                   bool in, hipStream_t s);
+// Where a single-matrix launch writes the leaf rows: the caller's Y (row
+// perm[t] for tree row t, or t when perm is null; leading dimension ldy;
+// first Q columns).  Y null: the tree-order workspace (then a permute-out
+// follows).
+struct OutScatter {
+    void *Y = nullptr;
+    int64_t ldy = 0, Q = 0;
+    const int64_t *perm = nullptr;
+};
 // Persistent launch of a plan (init + graph kernel) on stream s.
 hipError_t launch_persistent(const GraphPlan &plan, int elem_bytes, const MatDesc *d_mat,
-                             int32_t *d_head, int grid, hipStream_t s);
+                             int32_t *d_head, int grid, hipStream_t s, const OutScatter &out = OutScatter{});
 // Resident workgroups per CU of the persistent kernel for (elem_bytes, bn).
 int persistent_occupancy(int elem_bytes, int bn, bool split = false);
 

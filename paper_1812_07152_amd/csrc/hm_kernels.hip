@@ -97,10 +97,16 @@ constexpr int lds_pad() { return 128 / (int)sizeof(T); }
 //     tile taller than the block;
 //   - workspaces have leading dimension ldq, a multiple of BN.
 
-// One output block of a task as the tile code sees it.
+// One output block of a task as the tile code sees it.  With Y set, the
+// block's rows are rows perm[out_row + row] (perm null: out_row + row) of the
+// caller's Y (leading dimension ldy, first Q columns) instead of rows of the
+// output workspace.
 struct TileJob {
     int64_t out_row;
     int32_t out_buf, M, m0, seg_begin, seg_end, accumulate;
+    void *Y = nullptr;
+    int64_t ldy = 0, Q = 0;
+    const int64_t *perm = nullptr;
 };
 
 // Fragment grid of a BM x BN tile over WAVES_M x WAVES_N waves.
@@ -232,33 +238,47 @@ __device__ __forceinline__ void product_loop(
 }
 
 // Writes (or, with task.accumulate, adds) the tile's accumulators to rows
-// [0, task.M) x columns [n0, n0 + BN) of the task's output block.
+// [0, task.M) x columns [n0, n0 + BN) of the task's output block.  With
+// task.Y set, row r goes to the caller's Y row perm[out_row + r] (first Q
+// columns only); the destination rows are staged in LDS (free once the main
+// loop has ended), so that no index stays live beside the accumulators.
+// Every thread of the workgroup calls it (it holds a barrier).
 template <typename OUT, typename ACC, int BM, int BN, int WAVES_M, int WAVES_N, bool F32_ROWS>
 __device__ __forceinline__ void store_tile(const TileJob &task, OUT *buf0, OUT *buf1, OUT *buf2, OUT *buf3,
-                                           int64_t ldq, int64_t n0,
+                                           int64_t ldq, int64_t n0, void *lds,
                                            const ACC (&acc)[Tile<BM, BN, WAVES_M, WAVES_N>::FM]
                                                            [Tile<BM, BN, WAVES_M, WAVES_N>::FN]) {
     constexpr int WM = Tile<BM, BN, WAVES_M, WAVES_N>::WM, WN = Tile<BM, BN, WAVES_M, WAVES_N>::WN;
     constexpr int FM = WM / 16, FN = WN / 16;
+    typedef __attribute__((address_space(1))) OUT gOUT;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int64_t *rows = reinterpret_cast<int64_t *>(lds);
+    if (task.Y) {
+        if ((int)threadIdx.x < task.M) {
+            const int64_t t = task.out_row + threadIdx.x;
+            rows[threadIdx.x] = task.perm ? *(const __attribute__((address_space(1))) int64_t *)(task.perm + t) : t;
+        }
+        __syncthreads();
+    }
     if (wave >= WAVES_M * WAVES_N) return;
     const int wm = wave / WAVES_N, wn = wave % WAVES_N;
     OUT *base = task.out_buf == 0 ? buf0 : task.out_buf == 1 ? buf1 : task.out_buf == 2 ? buf2 : buf3;
     OUT *out = base + task.out_row * ldq + n0;
+    const int64_t lim = task.Y ? task.Q - n0 : BN;  // columns of this tile to store
 #pragma unroll
     for (int i = 0; i < FM; i++)
 #pragma unroll
-        for (int j = 0; j < FN; j++)
+        for (int r = 0; r < 4; r++) {
+            const int row = wm * WM + i * 16 + frag_row<F32_ROWS>(lane, r);
+            if (row >= task.M) continue;
+            gOUT *o = task.Y ? (gOUT *)((OUT *)task.Y + rows[row] * task.ldy + n0)
+                             : (gOUT *)(out + (int64_t)row * ldq);
 #pragma unroll
-            for (int r = 0; r < 4; r++) {
-                const int row = wm * WM + i * 16 + frag_row<F32_ROWS>(lane, r);
+            for (int j = 0; j < FN; j++) {
                 const int col = wn * WN + j * 16 + (lane & 15);
-                if (row < task.M) {
-                    __attribute__((address_space(1))) OUT *o =
-                        (__attribute__((address_space(1))) OUT *)(out + (int64_t)row * ldq + col);
-                    *o = task.accumulate ? *o + (OUT)acc[i][j][r] : (OUT)acc[i][j][r];
-                }
+                if (col < lim) o[col] = task.accumulate ? o[col] + (OUT)acc[i][j][r] : (OUT)acc[i][j][r];
             }
+        }
 }
 
 // One output tile: out (=|+=) sum over the task's segments of A_s * B_s.
@@ -276,7 +296,7 @@ __device__ __forceinline__ void block_product(const TileJob &task, const Seg *__
     product_loop<T, BM, BN, WAVES_M, WAVES_N, NT>(segs, task.seg_begin, task.seg_end, task.m0, store, buf0,
                                                   buf1, buf2, buf3, ldq, n0, As_, Bs_, acc);
     store_tile<T, typename Mfma<T>::acc_t, BM, BN, WAVES_M, WAVES_N, sizeof(T) == 4>(task, buf0, buf1, buf2,
-                                                                                     buf3, ldq, n0, acc);
+                                                                                     buf3, ldq, n0, As_, acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -454,7 +474,7 @@ __device__ __forceinline__ void block_product_bf16x3(const TileJob &task, const 
         for (int j = 0; j < TL::FN; j++) acc[i][j] = f4_t{0, 0, 0, 0};
     product_loop_bf16x3<BM, BN, WAVES_M, WAVES_N, NT>(segs, task.seg_begin, task.seg_end, task.m0, store16,
                                                       buf0, buf1, buf2, buf3, ldq, n0, lds, acc);
-    store_tile<double, f4_t, BM, BN, WAVES_M, WAVES_N, true>(task, buf0, buf1, buf2, buf3, ldq, n0, acc);
+    store_tile<double, f4_t, BM, BN, WAVES_M, WAVES_N, true>(task, buf0, buf1, buf2, buf3, ldq, n0, lds, acc);
 }
 
 // A down-pass tile of the mixed-precision graph: the far blocks (all
@@ -503,7 +523,7 @@ __device__ __forceinline__ void block_product_split_then_f64(const TileJob &task
     double *Bs = As + 2 * kBK * (BM + lds_pad<double>());
     product_loop<double, BM, BN, WAVES_M, WAVES_N, NT, true>(segs, task.seg_end - 1, task.seg_end, task.m0, store,
                                                              buf0, buf1, buf2, buf3, ldq, n0, As, Bs, acc);
-    store_tile<double, d4_t, BM, BN, WAVES_M, WAVES_N, true>(task, buf0, buf1, buf2, buf3, ldq, n0, acc);
+    store_tile<double, d4_t, BM, BN, WAVES_M, WAVES_N, true>(task, buf0, buf1, buf2, buf3, ldq, n0, lds, acc);
 }
 
 // Split-BF16 copy of one block per workgroup: for chunk c, part h (0 hi,
@@ -535,7 +555,7 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void k_block_products(
     __shared__ __attribute__((aligned(16))) T As[2 * kBK * (BM + lds_pad<T>())];
     __shared__ __attribute__((aligned(16))) T Bs[2 * kBK * (BN + lds_pad<T>())];
     const Task t = tasks[task_begin + blockIdx.x];
-    const TileJob job{t.out_row, t.out_buf, t.M, t.m0, t.seg_begin, t.seg_end, 0};
+    const TileJob job{t.out_row, t.out_buf, t.M, t.m0, t.seg_begin, t.seg_end, 0};  // workspace output
     block_product<T, BM, BN, WAVES_M, WAVES_N, NT>(job, segs, store, buf0, buf1, buf2, buf3, ldq,
                                                    (int64_t)blockIdx.y * BN, As, Bs);
 }
@@ -564,7 +584,8 @@ constexpr int kWaitLimit = 1 << 20;  // polls (each followed by a sleep) before 
 template <typename T, int BN, bool SPLIT>
 __global__ __launch_bounds__(kPersistThreads, BN <= 128 ? 4 : 1) void k_persistent(
     const PTask *__restrict__ tasks, int n_tasks, const int32_t *__restrict__ succ,
-    int32_t *counters, int32_t *head, int32_t *err, const MatDesc *__restrict__ mats) {
+    int32_t *counters, int32_t *head, int32_t *err, const MatDesc *__restrict__ mats, void *Y, int64_t ldy,
+    int64_t Q, const int64_t *__restrict__ perm) {
     constexpr int kNative = (2 * kBK * (128 + lds_pad<T>()) + 2 * kBK * (BN + lds_pad<T>())) * (int)sizeof(T);
     constexpr int kSplit = (SPLIT && sizeof(T) == 8) ? split_f64_lds_bytes<128, BN>() : 0;
     __shared__ __attribute__((aligned(16))) char lds[kNative > kSplit ? kNative : kSplit];
@@ -590,7 +611,13 @@ __global__ __launch_bounds__(kPersistThreads, BN <= 128 ? 4 : 1) void k_persiste
         }
         __syncthreads();
         const MatDesc md = mats[pt.mat];
-        const TileJob job{pt.out_row, pt.out_buf, pt.M, pt.m0, pt.seg_begin, pt.seg_end, pt.accumulate};
+        TileJob job{pt.out_row, pt.out_buf, pt.M, pt.m0, pt.seg_begin, pt.seg_end, pt.accumulate};
+        if (Y && pt.out_buf == BUF_YT) {  // leaf rows go straight to the caller's Y
+            job.Y = Y;
+            job.ldy = ldy;
+            job.Q = Q;
+            job.perm = perm;
+        }
         const int64_t n0 = (int64_t)pt.qtile * BN;
         const T *store = (const T *)md.store;
         const Seg *segs = md.segs;
@@ -816,28 +843,30 @@ namespace {
 
 template <typename T, int BN>
 hipError_t run_persistent(const GraphPlan &plan, const MatDesc *mats, int32_t *head, int grid,
-                          hipStream_t s) {
+                          const OutScatter &out, hipStream_t s) {
     const int nt = plan.n_tasks;
     hipLaunchKernelGGL(k_persistent_init, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s,
                        plan.d_tasks, nt, plan.d_counters, head);
     if (sizeof(T) == 8 && plan.mode == 1)
         hipLaunchKernelGGL((k_persistent<T, BN, true>), dim3((unsigned)grid), dim3(kPersistThreads), 0,
-                           s, plan.d_tasks, nt, plan.d_succ, plan.d_counters, head, head + 1, mats);
+                           s, plan.d_tasks, nt, plan.d_succ, plan.d_counters, head, head + 1, mats, out.Y,
+                           out.ldy, out.Q, out.perm);
     else
         hipLaunchKernelGGL((k_persistent<T, BN, false>), dim3((unsigned)grid), dim3(kPersistThreads), 0,
-                           s, plan.d_tasks, nt, plan.d_succ, plan.d_counters, head, head + 1, mats);
+                           s, plan.d_tasks, nt, plan.d_succ, plan.d_counters, head, head + 1, mats, out.Y,
+                           out.ldy, out.Q, out.perm);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t persistent_bn(const GraphPlan &plan, const MatDesc *mats, int32_t *head, int grid,
-                         hipStream_t s) {
+                         const OutScatter &out, hipStream_t s) {
     switch (plan.bn) {
-        case 16: return run_persistent<T, 16>(plan, mats, head, grid, s);
-        case 32: return run_persistent<T, 32>(plan, mats, head, grid, s);
-        case 64: return run_persistent<T, 64>(plan, mats, head, grid, s);
-        case 128: return run_persistent<T, 128>(plan, mats, head, grid, s);
-        default: return run_persistent<T, 256>(plan, mats, head, grid, s);
+        case 16: return run_persistent<T, 16>(plan, mats, head, grid, out, s);
+        case 32: return run_persistent<T, 32>(plan, mats, head, grid, out, s);
+        case 64: return run_persistent<T, 64>(plan, mats, head, grid, out, s);
+        case 128: return run_persistent<T, 128>(plan, mats, head, grid, out, s);
+        default: return run_persistent<T, 256>(plan, mats, head, grid, out, s);
     }
 }
 
@@ -858,10 +887,10 @@ int occupancy_bn(int bn) {
 }  // namespace
 
 hipError_t launch_persistent(const GraphPlan &plan, int elem_bytes, const MatDesc *d_mat,
-                             int32_t *d_head, int grid, hipStream_t s) {
+                             int32_t *d_head, int grid, hipStream_t s, const OutScatter &out) {
     if (plan.n_tasks == 0) return hipSuccess;
-    return elem_bytes == 8 ? persistent_bn<double>(plan, d_mat, d_head, grid, s)
-                           : persistent_bn<float>(plan, d_mat, d_head, grid, s);
+    return elem_bytes == 8 ? persistent_bn<double>(plan, d_mat, d_head, grid, out, s)
+                           : persistent_bn<float>(plan, d_mat, d_head, grid, out, s);
 }
 
 int persistent_occupancy(int elem_bytes, int bn, bool split) {
