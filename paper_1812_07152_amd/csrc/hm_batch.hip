@@ -112,7 +112,7 @@ hm_status configure(hm_batch b, int bn) {
     HM_HIP(hipMemcpy(b->d_mats, mats.data(), sizeof(MatDesc) * b->n, hipMemcpyHostToDevice));
     const int occ = persistent_occupancy(b->es, bn);
     const int workers = std::max(1, occ * b->hs[0]->n_cu);
-    hm_status st = build_plan(parts, bn, workers, b->plan);
+    hm_status st = build_plan(parts, bn, b->es, workers, b->plan);
     if (st != HM_OK) return st;
     b->grid = std::min(b->plan.n_tasks, workers);
     return HM_OK;

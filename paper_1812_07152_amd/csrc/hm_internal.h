@@ -95,7 +95,7 @@ struct RepackJob {
 struct PTask {
     int64_t out_row;
     int32_t out_buf, M, m0, seg_begin, seg_end;
-    int32_t bm;          // tile height: 64 or 128
+    int32_t bm;          // tile height: 32, 64, 96 or 128 (64 or 128 in a mixed-precision launch)
     int32_t accumulate;  // 1: out += product (a leaf's far part after its near part)
     int32_t qtile;       // column tile: columns [qtile * BN, (qtile + 1) * BN)
     int32_t mat;         // index into the MatDesc table
@@ -218,6 +218,13 @@ hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_mat
 // 2 down, 3 leaf), honouring the HM_BN_UP / HM_BN_DOWN / HM_BN_LEAF / HM_BN
 // environment overrides.
 int pick_bn(int64_t Q, int kind);
+// Whether a persistent launch with column tile bn over elem_bytes elements
+// also has 32- and 96-row tiles (besides 64 and 128).  Not in mixed-precision
+// launches, nor for FP64 with 128-column tiles, which is held to 128 VGPRs
+// (two workgroups per compute unit) and has no registers to spare.
+constexpr bool fine_tiles(int elem_bytes, int bn, bool split) {
+    return !split && !(elem_bytes == 8 && bn == 128);
+}
 // Column tile of the persistent task-graph launch for Q columns of elem_bytes
 // (split: the launch runs split-BF16 tiles; task_k: the flop-weighted mean
 // contraction length of the graph's jobs, see job_task_k).
@@ -269,7 +276,7 @@ struct PlanPart {
     int nq;   // column tiles
     int mode = 0;  // which job graph of h: 0 native, 1 mixed precision
 };
-hm_status build_plan(const std::vector<PlanPart> &parts, int bn, int workers, GraphPlan &plan);
+hm_status build_plan(const std::vector<PlanPart> &parts, int bn, int elem_bytes, int workers, GraphPlan &plan);
 void free_plan(GraphPlan &p);
 
 }  // namespace hm

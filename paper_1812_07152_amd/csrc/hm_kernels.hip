@@ -565,7 +565,11 @@ template <int BM, int BN>
 struct PLayout {
     static constexpr int WN = BN >= 256 ? (BM == 128 ? 4 : 8) : BN == 128 ? (BM == 128 ? 2 : 4)
                             : BN == 64 ? (BM == 128 ? 1 : 2) : BN == 32 ? (BM == 128 ? 1 : 2) : 1;
-    static constexpr int WMv = (BM / 16 < 8 / WN) ? BM / 16 : 8 / WN;
+    // waves along M: as many as fit beside WN, dividing the BM / 16 fragment
+    // rows evenly (96 rows: 6 fragment rows over 1, 2, 3 or 6 waves)
+    static constexpr int kMaxM = 8 / WN;
+    static constexpr int WMv = BM == 96 ? (kMaxM >= 6 ? 6 : kMaxM >= 3 ? 3 : kMaxM >= 2 ? 2 : 1)
+                                        : ((BM / 16 < kMaxM) ? BM / 16 : kMaxM);
 };
 
 // 8 waves per workgroup.  With column tiles up to 128 the kernel is held to
@@ -643,14 +647,26 @@ __global__ __launch_bounds__(kPersistThreads, BN <= 128 ? 4 : 1) void k_persiste
                                                  kPersistThreads>(job, segs, (const double *)store, s16, b0, b1,
                                                                   b2, b3, md.ldq, n0, lds);
             }
-        } else if (pt.bm == 128)
+        } else if (pt.bm == 128) {
             block_product<T, 128, BN, PLayout<128, BN>::WMv, PLayout<128, BN>::WN, kPersistThreads>(
                 job, segs, store, (T *)md.buf[0], (T *)md.buf[1], (T *)md.buf[2], (T *)md.buf[3],
                 md.ldq, n0, As, Bs);
-        else
+        } else if (!fine_tiles(sizeof(T), BN, SPLIT) || pt.bm == 64) {
             block_product<T, 64, BN, PLayout<64, BN>::WMv, PLayout<64, BN>::WN, kPersistThreads>(
                 job, segs, store, (T *)md.buf[0], (T *)md.buf[1], (T *)md.buf[2], (T *)md.buf[3],
                 md.ldq, n0, As, Bs);
+        } else if constexpr (fine_tiles(sizeof(T), BN, SPLIT)) {
+            // 32- and 96-row tiles, for output blocks whose row count would
+            // waste most of a 64- or 128-row tile
+            if (pt.bm == 96)
+                block_product<T, 96, BN, PLayout<96, BN>::WMv, PLayout<96, BN>::WN, kPersistThreads>(
+                    job, segs, store, (T *)md.buf[0], (T *)md.buf[1], (T *)md.buf[2], (T *)md.buf[3],
+                    md.ldq, n0, As, Bs);
+            else
+                block_product<T, 32, BN, PLayout<32, BN>::WMv, PLayout<32, BN>::WN, kPersistThreads>(
+                    job, segs, store, (T *)md.buf[0], (T *)md.buf[1], (T *)md.buf[2], (T *)md.buf[3],
+                    md.ldq, n0, As, Bs);
+        }
         __syncthreads();  // every wave's stores of this task are done
         if (threadIdx.x == 0 && pt.succ_end > pt.succ_begin) {
             __threadfence();  // release this task's output to every XCD

@@ -32,13 +32,14 @@ void free_plan(GraphPlan &p) {
     p = GraphPlan{};
 }
 
-hm_status build_plan(const std::vector<PlanPart> &parts, int bn, int workers, GraphPlan &plan) {
+hm_status build_plan(const std::vector<PlanPart> &parts, int bn, int elem_bytes, int workers, GraphPlan &plan) {
     // per part: row tiles per job, entry offsets
     struct P {
         const std::vector<GJob> *jobs;
         int mat, nq, per_q;
         int64_t base;
-        std::vector<int32_t> rows, bm, first;
+        std::vector<int32_t> rows, bm, first;  // bm: height of a job's row tiles (its last one: last_bm)
+        std::vector<int32_t> last_bm;
         std::vector<std::vector<int32_t>> succ_jobs;
         std::vector<double> cost, blevel;  // per local entry (one column tile)
     };
@@ -54,10 +55,20 @@ hm_status build_plan(const std::vector<PlanPart> &parts, int bn, int workers, Gr
         const int nj = (int)jobs.size();
         p.rows.resize(nj);
         p.bm.resize(nj);
+        p.last_bm.resize(nj);
         p.first.assign(nj + 1, 0);
         for (int j = 0; j < nj; j++) {
-            p.bm[j] = jobs[j].M <= 64 ? 64 : 128;
-            p.rows[j] = std::max(1, (jobs[j].M + p.bm[j] - 1) / p.bm[j]);
+            // row tiles of 128 rows; a job's last (or only) tile takes the
+            // smallest height that holds its remaining rows: 32, 64, 96 or
+            // 128 where the launch has the fine tiles (fine_tiles), else 64 or
+            // 128
+            const int M = std::max(1, jobs[j].M);
+            p.bm[j] = 128;
+            p.rows[j] = (M + 127) / 128;
+            const int rem = M - (p.rows[j] - 1) * 128;
+            p.last_bm[j] = !fine_tiles(elem_bytes, bn, parts[i].mode == 1)
+                               ? (rem <= 64 ? 64 : 128)
+                               : rem <= 32 ? 32 : rem <= 64 ? 64 : rem <= 96 ? 96 : 128;
             p.first[j + 1] = p.first[j] + p.rows[j];
         }
         p.per_q = p.first[nj];
@@ -70,8 +81,8 @@ hm_status build_plan(const std::vector<PlanPart> &parts, int bn, int workers, Gr
         p.blevel.resize(p.per_q);
         for (int j = 0; j < nj; j++)
             for (int r = 0; r < p.rows[j]; r++)
-                p.cost[p.first[j] + r] =
-                    2.0 * p.bm[j] * bn * (jobs[j].kpad - 0.65 * jobs[j].kpad_split) + overhead;
+                p.cost[p.first[j] + r] = 2.0 * (r + 1 < p.rows[j] ? p.bm[j] : p.last_bm[j]) * bn *
+                                             (jobs[j].kpad - 0.65 * jobs[j].kpad_split) + overhead;
         // critical path to the end of the graph (jobs are topologically ordered)
         std::vector<double> jbl(nj, 0.0);
         for (int j = nj - 1; j >= 0; j--) {
@@ -203,13 +214,14 @@ hm_status build_plan(const std::vector<PlanPart> &parts, int bn, int workers, Gr
         const P &p = ps[pi];
         const GJob &g = (*p.jobs)[j];
         PTask t{};
+        const int tile_bm = r + 1 < p.rows[j] ? p.bm[j] : p.last_bm[j];
         t.out_row = g.out_row + (int64_t)r * p.bm[j];
         t.out_buf = g.out_buf;
         t.M = std::min(p.bm[j], g.M - r * p.bm[j]);
         t.m0 = r * p.bm[j];
         t.seg_begin = g.seg_begin;
         t.seg_end = g.seg_end;
-        t.bm = p.bm[j];
+        t.bm = tile_bm;
         t.accumulate = g.accumulate;
         t.qtile = q;
         t.mat = p.mat;
@@ -256,7 +268,7 @@ hm_status get_plan(hm_matrix h, int slot, int bn, int64_t ldq, int workers, Grap
     }
     GraphPlan p;
     std::vector<PlanPart> parts{{h, 0, nq, mode}};
-    hm_status st = build_plan(parts, bn, workers, p);
+    hm_status st = build_plan(parts, bn, slot == 0 ? 8 : 4, workers, p);
     if (st != HM_OK) return st;
     p.Q = nq;  // cache key: column tiles
     p.mode = mode;
