@@ -205,3 +205,38 @@ def test_mixed_precision_bf16x3(hmx, name, sched):
     err = rel(Yd.cpu().numpy(), H.eval(W))
     _say(f"[mixed] case={name} rel err={err:.3e}")
     assert err <= 5e-5
+
+
+def test_mixed_precision_shapes_and_flags(hmx, sched):
+    """Split BF16 through the same entry point with Q = 1 and ragged Q (the
+    last column tile partly empty), strided W/Y views (columns beyond Q must
+    stay untouched) and tree-order rows; the 5e-5 bar of the four-structure
+    test against the FP64 oracle."""
+    if sched == "level":
+        pytest.skip("mixed precision runs on the task-graph launch only")
+    w, H = built("mix8")
+    M = hmx.hm_load_compressed_mem(H, 0, hmx.precbit(hmx.HM_PREC_FP64) | hmx.precbit(hmx.HM_PREC_BF16X3))
+    for Q in (1, 17, 300):
+        W = wl.gen_w(w, Q=Q, seed=200 + Q)
+        Wd = torch.from_numpy(W).cuda()
+        Yd = torch.full_like(Wd, float("nan"))
+        hmx.hm_eval(M, Wd, Yd, prec=hmx.HM_PREC_BF16X3)
+        hmx.hm_check(M)
+        err = rel(Yd.cpu().numpy(), H.eval(W))
+        _say(f"[mixed] case=mix8 Q={Q} rel err={err:.3e}")
+        assert err <= 5e-5
+    W = wl.gen_w(w)
+    Yref = H.eval(W)
+    big_w = torch.zeros(w.N, w.Q + 11, dtype=torch.float64, device="cuda")
+    big_y = torch.full((w.N, w.Q + 5), 7.0, dtype=torch.float64, device="cuda")
+    big_w[:, 3:3 + w.Q] = torch.from_numpy(W).cuda()
+    hmx.hm_eval(M, big_w[:, 3:], big_y, Q=w.Q, prec=hmx.HM_PREC_BF16X3)
+    hmx.hm_check(M)
+    out = big_y.cpu().numpy()
+    assert rel(out[:, :w.Q], Yref) <= 5e-5
+    assert np.all(out[:, w.Q:] == 7.0), "columns beyond Q must be untouched"
+    Wt = torch.from_numpy(W[H.perm]).cuda()
+    Yt = torch.empty_like(Wt)
+    hmx.hm_eval(M, Wt, Yt, prec=hmx.HM_PREC_BF16X3, flags=hmx.HM_TREE_ORDER)
+    hmx.hm_check(M)
+    assert rel(Yt.cpu().numpy(), Yref[H.perm]) <= 5e-5
