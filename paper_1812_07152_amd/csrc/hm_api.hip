@@ -56,6 +56,23 @@ hm_status ensure_ws(hm_matrix h, int slot, int b, size_t bytes) {
     return HM_OK;
 }
 
+// Grow split workspace `b` (see Split16) to `bytes`, zero-filled: rows past a
+// node's last row are read as zeros by the split-BF16 products.
+hm_status ensure_ws16(hm_matrix h, int b, size_t bytes) {
+    bytes = std::max<size_t>(bytes, 256);
+    if (h->ws16_bytes[b] >= bytes) return HM_OK;
+    if (h->ws16[b]) {
+        HM_HIP(hipDeviceSynchronize());
+        HM_HIP(hipFree(h->ws16[b]));
+        h->ws16[b] = nullptr;
+        h->ws16_bytes[b] = 0;
+    }
+    HM_HIP(hipMalloc(&h->ws16[b], bytes));
+    HM_HIP(hipMemset(h->ws16[b], 0, bytes));
+    h->ws16_bytes[b] = bytes;
+    return HM_OK;
+}
+
 }  // namespace
 
 hm_status reserve_ws(hm_matrix h, int slot, int64_t ldq) {
@@ -148,6 +165,9 @@ hm_status hm_free(hm_matrix h) {
     for (int i = 0; i < 2; i++)
         if (h->prec[i].blocks) (void)hipFree(h->prec[i].blocks);
     if (h->store16) (void)hipFree(h->store16);
+    for (int b = 0; b < BUF_COUNT; b++)
+        if (h->ws16[b]) (void)hipFree(h->ws16[b]);
+    if (h->d_wchunks) (void)hipFree(h->d_wchunks);
     for (int s = 0; s < 2; s++)
         for (int b = 0; b < BUF_COUNT; b++)
             if (h->ws[s][b]) (void)hipFree(h->ws[s][b]);
@@ -194,6 +214,10 @@ hm_status hm_eval(hm_matrix h, const void *W, int64_t ldw, void *Y, int64_t ldy,
     const int64_t Qp = (Q + bn_max - 1) / bn_max * bn_max;  // workspace leading dimension
     {
         hm_status st = reserve_ws(h, slot, Qp);
+        // split workspaces: W (leaf rows), Ŵ and Ŷ (skeleton rows), 4 bytes a value
+        if (st == HM_OK && mixed) st = ensure_ws16(h, BUF_WT, (size_t)h->rows16_w * Qp * 4);
+        if (st == HM_OK && mixed) st = ensure_ws16(h, BUF_WHAT, (size_t)h->rows16_h * Qp * 4);
+        if (st == HM_OK && mixed) st = ensure_ws16(h, BUF_YHAT, (size_t)h->rows16_h * Qp * 4);
         if (st != HM_OK) return st;
     }
     void *bufs[BUF_COUNT];
@@ -209,7 +233,9 @@ hm_status hm_eval(hm_matrix h, const void *W, int64_t ldw, void *Y, int64_t ldy,
         hm_status pst = get_plan(h, slot, bn_kind[3], Qp, workers, &plan, mixed ? 1 : 0);
         if (pst != HM_OK) return pst;
         MatDesc md{h->prec[mixed ? HM_PREC_FP64 : prec].blocks, {bufs[0], bufs[1], bufs[2], bufs[3]},
-                   Qp, h->d_segs, mixed ? h->store16 : nullptr};
+                   Qp, h->d_segs, mixed ? h->store16 : nullptr,
+                   {mixed ? h->ws16[BUF_WT] : nullptr, nullptr, mixed ? h->ws16[BUF_WHAT] : nullptr,
+                    mixed ? h->ws16[BUF_YHAT] : nullptr}};
         MatDesc &cache = h->mat_cache[slot];
         if (std::memcmp(&md, &cache, sizeof(MatDesc)) != 0 || h->mat_slot != slot) {
             HM_HIP(hipStreamSynchronize(s));
@@ -233,7 +259,11 @@ hm_status hm_eval(hm_matrix h, const void *W, int64_t ldw, void *Y, int64_t ldy,
     };
     hm_status st;
     if ((st = mark(0, true)) != HM_OK) return st;
-    HM_HIP(launch_permute_in(W, ldw, bufs[BUF_WT], Qp, perm, h->N, Q, es, s));
+    if (mixed)  // only split-BF16 products read W in the mixed-precision graph
+        HM_HIP(launch_permute_in_split((const double *)W, ldw, h->ws16[BUF_WT], Qp, perm, h->d_wchunks,
+                                       h->n_wchunks, Q, s));
+    else
+        HM_HIP(launch_permute_in(W, ldw, bufs[BUF_WT], Qp, perm, h->N, Q, es, s));
     if ((st = mark(0, false)) != HM_OK) return st;
     if (!level_sched) {
         // the whole graph (up, down, near, leaf far part) in one launch,

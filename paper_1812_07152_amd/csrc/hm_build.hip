@@ -25,8 +25,9 @@ namespace {
 
 int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
-Seg seg(int64_t a_off, int64_t b_row, int32_t lda, int32_t K, int32_t buf) {
-    return Seg{a_off, b_row, lda, K, buf, (int32_t)round_up(K, 16)};
+// b_row16: the B operand node's first row in its split-BF16 workspace
+Seg seg(int64_t a_off, int64_t b_row, int32_t lda, int32_t K, int32_t buf, int64_t b_row16) {
+    return Seg{a_off, b_row, lda, K, buf, (int32_t)round_up(K, 16), 0, b_row16};
 }
 
 struct Block {            // one output block of a phase before tiling
@@ -166,6 +167,19 @@ hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_mat
     auto leaf = [&](int a) { return r.left[a] < 0; };
     std::vector<int64_t> wrow((size_t)n + 1, 0);
     for (int a = 0; a < n; a++) wrow[a + 1] = wrow[a] + r.rank[a];
+    // padded row starts in the split-BF16 workspaces: leaves' point rows (W)
+    // and nodes' skeleton rows (Ŵ, Ŷ), each node starting at a multiple of 32
+    std::vector<int64_t> w16row((size_t)n, 0), h16row((size_t)n + 1, 0);
+    std::vector<int32_t> leaves;
+    for (int a = 0; a < n; a++)
+        if (leaf(a)) leaves.push_back(a);
+    std::sort(leaves.begin(), leaves.end(), [&](int x, int y) { return r.start[x] < r.start[y]; });
+    int64_t rows16_w = 0;
+    for (int a : leaves) {
+        w16row[a] = rows16_w;
+        rows16_w += round_up(r.size[a], Split16::kRows);
+    }
+    for (int a = 0; a < n; a++) h16row[a + 1] = h16row[a] + round_up(r.rank[a], Split16::kRows);
 
     Planner P;
     std::vector<std::vector<int>> by_level((size_t)r.depth + 1);
@@ -184,7 +198,7 @@ hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_mat
                 const int32_t m = (int32_t)r.size[a];
                 int64_t off = P.alloc(m, kp);
                 P.jobs[0].push_back({r.basis_off[a], off, k, m, 0, 0, m, kp});
-                b.segs.push_back(seg(off, r.start[a], kp, m, BUF_WT));
+                b.segs.push_back(seg(off, r.start[a], kp, m, BUF_WT, w16row[a]));
                 E_V += (int64_t)k * m;
             } else {
                 // T_a's column halves (left / right child skeletons) are stored
@@ -193,12 +207,12 @@ hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_mat
                 if (kl > 0) {
                     int64_t off = P.alloc(kl, kp);
                     P.jobs[0].push_back({r.basis_off[a], off, k, kl + kr, 0, 0, kl, kp});
-                    b.segs.push_back(seg(off, wrow[r.left[a]], kp, kl, BUF_WHAT));
+                    b.segs.push_back(seg(off, wrow[r.left[a]], kp, kl, BUF_WHAT, h16row[r.left[a]]));
                 }
                 if (kr > 0) {
                     int64_t off = P.alloc(kr, kp);
                     P.jobs[0].push_back({r.basis_off[a], off, k, kl + kr, 0, kl, kr, kp});
-                    b.segs.push_back(seg(off, wrow[r.right[a]], kp, kr, BUF_WHAT));
+                    b.segs.push_back(seg(off, wrow[r.right[a]], kp, kr, BUF_WHAT, h16row[r.right[a]]));
                 }
                 E_T += (int64_t)k * (kl + kr);
             }
@@ -220,7 +234,7 @@ hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_mat
                 if (kb == 0) continue;
                 int64_t off = P.alloc(kb, kap);
                 P.jobs[1].push_back({r.far_off[e], off, ka, kb, 0, 0, kb, kap});
-                b.segs.push_back(seg(off, wrow[bn], kap, kb, BUF_WHAT));
+                b.segs.push_back(seg(off, wrow[bn], kap, kb, BUF_WHAT, h16row[bn]));
                 E_B += (int64_t)ka * kb;
             }
             const int32_t p = r.parent[a];
@@ -229,7 +243,7 @@ hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_mat
                 const int32_t c0 = (a == r.left[p]) ? 0 : kl;
                 int64_t off = P.alloc(kpar, kap);
                 P.jobs[0].push_back({r.basis_off[p], off, kpar, kl + kr, 1, c0, ka, kap});
-                b.segs.push_back(seg(off, wrow[p], kap, kpar, BUF_YHAT));
+                b.segs.push_back(seg(off, wrow[p], kap, kpar, BUF_YHAT, h16row[p]));
             }
             blocks.push_back(std::move(b));
         }
@@ -248,14 +262,14 @@ hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_mat
                 const int32_t mb = (int32_t)r.size[bn];
                 int64_t off = P.alloc(mb, map);
                 P.jobs[2].push_back({r.near_off[e], off, ma, mb, 0, 0, mb, map});
-                b.segs.push_back(seg(off, r.start[bn], map, mb, BUF_WT));
+                b.segs.push_back(seg(off, r.start[bn], map, mb, BUF_WT, w16row[bn]));
                 E_D += (int64_t)ma * mb;
             }
             const int32_t k = r.rank[a];
             if (k > 0 && r.level[a] >= 1) {
                 int64_t off = P.alloc(k, map);
                 P.jobs[0].push_back({r.basis_off[a], off, k, ma, 1, 0, ma, map});
-                b.segs.push_back(seg(off, wrow[a], map, k, BUF_YHAT));
+                b.segs.push_back(seg(off, wrow[a], map, k, BUF_YHAT, h16row[a]));
             }
             blocks.push_back(std::move(b));
         }
@@ -344,6 +358,8 @@ hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_mat
                 j.mode = leaf(a) ? 1 : 0;
                 j.kpad = pl.kpad;
                 j.kpad_split = leaf(a) ? pl.kpad : 0;
+                j.out16 = h16row[a];  // Ŵ: FP64 (parent's transfer) and split (far blocks)
+                j.out_split = 1;
                 if (!leaf(a)) {
                     if (r.rank[r.left[a]] > 0) j.preds.push_back(up_job[r.left[a]]);
                     if (r.rank[r.right[a]] > 0) j.preds.push_back(up_job[r.right[a]]);
@@ -364,6 +380,10 @@ hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_mat
                 dj.kpad_split = kpad_of(pl.seg_begin, far_end);
                 dj.mode = !has_td ? 1 : far_end > pl.seg_begin ? 2 : 0;
                 if (dj.mode == 0) dj.kpad_split = 0;
+                if (leaf(a)) {  // a leaf's Ŷ feeds only its leaf far part (split BF16)
+                    dj.out16 = h16row[a];
+                    dj.out_split = 2;
+                }
                 for (int64_t e = r.far_ptr[a]; e < r.far_ptr[a + 1]; e++)
                     if (r.rank[r.far_col[e]] > 0) dj.preds.push_back(up_job[r.far_col[e]]);
                 if (has_td) dj.preds.push_back(down_job[p]);
@@ -497,6 +517,21 @@ hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_mat
     if (!P.segs.empty())
         HM_HIP(hipMemcpyAsync(h->d_segs, P.segs.data(), sizeof(Seg) * P.segs.size(),
                               hipMemcpyHostToDevice, s));
+    h->rows16_w = rows16_w;
+    h->rows16_h = h16row[n];
+    if (prec_mask & HM_PRECBIT(HM_PREC_BF16X3)) {
+        // W's 32-row chunks for the split permute-in
+        std::vector<int64_t> ch;
+        for (int a : leaves)
+            for (int64_t c = 0; c < r.size[a]; c += Split16::kRows) {
+                ch.push_back(r.start[a] + c);
+                ch.push_back(std::min<int64_t>(Split16::kRows, r.size[a] - c));
+                ch.push_back(w16row[a] + c);
+            }
+        h->n_wchunks = (int64_t)ch.size() / 3;
+        HM_HIP(hipMalloc(&h->d_wchunks, sizeof(int64_t) * std::max<size_t>(ch.size(), 3)));
+        if (!ch.empty()) HM_HIP(hipMemcpy(h->d_wchunks, ch.data(), sizeof(int64_t) * ch.size(), hipMemcpyHostToDevice));
+    }
     HM_HIP(hipMalloc(&h->d_mat, sizeof(MatDesc)));
     HM_HIP(hipMalloc(&h->d_head, 2 * sizeof(int32_t)));
     HM_HIP(hipMemsetAsync(h->d_head, 0, 2 * sizeof(int32_t), s));

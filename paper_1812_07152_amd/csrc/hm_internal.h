@@ -34,6 +34,20 @@ struct Seg {
     int32_t b_buf;
     int32_t Kpad;   // stored contraction rows (multiple of 16)
     int64_t a_off16; // element offset of the block in the split-BF16 store (see k_make_bf16x3)
+    int64_t b_row16; // first row of the B operand's node in its split-BF16 workspace (see Split16)
+};
+
+// Split-BF16 workspaces of the mixed-precision evaluation: W (tree order),
+// Ŵ and the leaves' Ŷ, each value v stored as hi = bf16(v), lo = bf16(v - hi)
+// (from the FP32 value).  Every node's rows start at a multiple of 32 (its
+// padded row start, b_row16 / out16) and are cut into 32-row chunks; the
+// chunk of rows [g, g + 32) holds, for each column n < ldq, the 32 hi values
+// then the 32 lo values: element (row g + k, column n, part h) at
+//     g * 2 * ldq + n * 64 + h * 32 + k      (bf16 elements, g % 32 == 0).
+// A chunk of a column tile is then one contiguous run, copied as is into the
+// LDS layout of the split-BF16 products.  Rows past a node's last row are zero.
+struct Split16 {
+    static constexpr int kRows = 32;
 };
 
 // One output block: rows [out_row, out_row + M) of buffer out_buf (M <= tile
@@ -94,6 +108,7 @@ struct RepackJob {
 // tile of one output block for one column tile, with its dependencies.
 struct PTask {
     int64_t out_row;
+    int64_t out16;       // split-BF16 copy of the output: first row in the split workspace, or -1
     int32_t out_buf, M, m0, seg_begin, seg_end;
     int32_t bm;          // tile height: 32, 64, 96 or 128 (64 or 128 in a mixed-precision launch)
     int32_t accumulate;  // 1: out += product (a leaf's far part after its near part)
@@ -104,6 +119,7 @@ struct PTask {
     int32_t mode;        // 0: products in the launch's type; 1: split BF16 (hi+lo) with FP32
                          // accumulation; 2: split BF16 for all segments but the last, FP64 for
                          // the last one, continuing from the FP32 partial sums
+    int32_t out_split;   // with out16 >= 0: 1 = FP64 output and split copy, 2 = split copy only
 };
 
 // Device addresses of one matrix for the persistent launch.
@@ -113,6 +129,7 @@ struct MatDesc {
     int64_t ldq;
     const Seg *segs;
     const void *store16;  // split-BF16 store (mixed precision), or null
+    void *buf16[4];       // split-BF16 workspaces (mixed precision): [BUF_WT] W, [BUF_WHAT] Ŵ, [BUF_YHAT] Ŷ
 };
 
 // One matrix's permutes in a batched launch.
@@ -140,6 +157,8 @@ struct GJob {
     int32_t mode;        // 0 native, 1 split BF16, 2 split BF16 then FP64 (see PTask)
     int64_t kpad;        // sum of Kpad over its segments (work model)
     int64_t kpad_split;  // the part of kpad computed in split BF16
+    int64_t out16 = -1;  // split-BF16 copy of the output (see PTask)
+    int32_t out_split = 0;
     std::vector<int32_t> preds;  // job indices
 };
 
@@ -186,6 +205,11 @@ struct hm_matrix_s {
     double task_k = 0;                     // job_task_k(gjobs)
     void *store16 = nullptr;               // split-BF16 block store (HM_PREC_BF16X3)
     size_t store16_bytes = 0;
+    int64_t rows16_w = 0, rows16_h = 0;    // rows of the split W / Ŵ, Ŷ workspaces (see Split16)
+    int64_t *d_wchunks = nullptr;          // W's 32-row chunks: (first tree row, rows, split row)
+    int64_t n_wchunks = 0;
+    void *ws16[hm::BUF_COUNT] = {nullptr};  // split workspaces, grown on demand ([BUF_WT], [BUF_WHAT], [BUF_YHAT])
+    size_t ws16_bytes[hm::BUF_COUNT] = {0};
     std::vector<hm::GraphPlan> plans[2];   // per element size: one plan per (tile, tile count)
     hm::MatDesc *d_mat = nullptr;          // one descriptor (persistent launch)
     hm::MatDesc mat_cache[2] = {};         // last uploaded descriptor per element size
@@ -239,6 +263,11 @@ hipError_t launch_permute_out(const void *Yt, int64_t Qp, void *Y, int64_t ldy, 
                               int64_t N, int64_t Q, int elem_bytes, hipStream_t s);
 hipError_t launch_convert_f64_to_f32(const double *src, float *dst, int64_t n, hipStream_t s);
 // Split-BF16 copies of blocks (one per segment) of the FP64 store.
+// W (original order, ldw, FP64) -> split-BF16 W in tree order (see Split16),
+// one 32-row chunk per (chunks entry, column); columns >= Q and rows past a
+// leaf are zero.  perm null: identity.
+hipError_t launch_permute_in_split(const double *W, int64_t ldw, void *W16, int64_t ldq, const int64_t *perm,
+                                   const int64_t *chunks, int64_t n_chunks, int64_t Q, hipStream_t s);
 hipError_t launch_make_bf16x3(const double *store, const Seg *segs, int nsegs, void *store16,
                               hipStream_t s);
 hipError_t launch_repack(const double *stage, const RepackJob *jobs, int njobs, double *store,

@@ -80,7 +80,18 @@ __device__ __forceinline__ Seg load_seg(const Seg *p) {
     s.b_buf = g->b_buf;
     s.Kpad = g->Kpad;
     s.a_off16 = g->a_off16;
+    s.b_row16 = g->b_row16;
     return s;
+}
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef short s16x8_t __attribute__((ext_vector_type(8)));
+
+// v ~= hi + lo with hi = bf16(v) and lo = bf16(v - hi), from the FP32 value.
+__device__ __forceinline__ void split_bf16(float f, __bf16 &hi, __bf16 &lo) {
+    hi = (__bf16)f;
+    lo = (__bf16)(f - (float)hi);
 }
 
 constexpr int kBK = 16;
@@ -107,6 +118,11 @@ struct TileJob {
     void *Y = nullptr;
     int64_t ldy = 0, Q = 0;
     const int64_t *perm = nullptr;
+    // split-BF16 copy of the block (mixed precision): rows out16 + r of the
+    // split workspace Y16; out_split 2: the copy only (no FP64 output)
+    void *Y16 = nullptr;
+    int64_t out16 = -1;
+    int32_t out_split = 0;
 };
 
 // Fragment grid of a BM x BN tile over WAVES_M x WAVES_N waves.
@@ -237,12 +253,25 @@ __device__ __forceinline__ void product_loop(
     }
 }
 
+// LDS of the split-BF16 copy in store_tile: the tile as FP32, column-major
+// with a pitch of BM + 4 values (16-byte accesses without bank conflicts).
+template <int BM, int BN>
+constexpr int split_copy_lds_bytes() {
+    return BN * (BM + 4) * 4;
+}
+
 // Writes (or, with task.accumulate, adds) the tile's accumulators to rows
 // [0, task.M) x columns [n0, n0 + BN) of the task's output block.  With
 // task.Y set, row r goes to the caller's Y row perm[out_row + r] (first Q
 // columns only); the destination rows are staged in LDS (free once the main
 // loop has ended), so that no index stays live beside the accumulators.
-// Every thread of the workgroup calls it (it holds a barrier).
+// With task.out16 >= 0 (mixed precision; FP64 output in the FP32 register
+// layout) the tile is also written to the split-BF16 workspace task.Y16 at
+// rows out16.. (zero past row M); out_split 2 writes that copy only.  The
+// copy goes through LDS (split_copy_lds_bytes), so that it runs after the
+// accumulators are dead.  Y and out16 never come together (the caller's Y
+// receives leaf outputs, the split copies are of Ŵ and Ŷ).
+// Every thread of the workgroup calls it (it holds barriers).
 template <typename OUT, typename ACC, int BM, int BN, int WAVES_M, int WAVES_N, bool F32_ROWS>
 __device__ __forceinline__ void store_tile(const TileJob &task, OUT *buf0, OUT *buf1, OUT *buf2, OUT *buf3,
                                            int64_t ldq, int64_t n0, void *lds,
@@ -251,38 +280,98 @@ __device__ __forceinline__ void store_tile(const TileJob &task, OUT *buf0, OUT *
     constexpr int WM = Tile<BM, BN, WAVES_M, WAVES_N>::WM, WN = Tile<BM, BN, WAVES_M, WAVES_N>::WN;
     constexpr int FM = WM / 16, FN = WN / 16;
     typedef __attribute__((address_space(1))) OUT gOUT;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // thread index made opaque here, so that no address below is computed
+    // once per kernel and held in registers through the product loops
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const bool computes = wave < WAVES_M * WAVES_N;
+    const int wm = wave / WAVES_N, wn = wave % WAVES_N;
+    constexpr bool kSplitCopy = F32_ROWS && sizeof(OUT) == 8;
+    constexpr int kPitch = BM + 4;
+    const bool split_copy = kSplitCopy && task.out16 >= 0;  // uniform over the workgroup
+    if constexpr (kSplitCopy) {
+        if (split_copy && computes) {
+            float *tile = reinterpret_cast<float *>(lds);
+            // registers r = 0..3 of a lane are rows 4(l/16) + r of one column
+#pragma unroll
+            for (int i = 0; i < FM; i++)
+#pragma unroll
+                for (int j = 0; j < FN; j++) {
+                    const int col = wn * WN + j * 16 + (lane & 15);
+                    const int row = wm * WM + i * 16 + 4 * (lane >> 4);
+                    *reinterpret_cast<f4_t *>(tile + col * kPitch + row) =
+                        f4_t{(float)acc[i][j][0], (float)acc[i][j][1], (float)acc[i][j][2], (float)acc[i][j][3]};
+                }
+        }
+    }
     int64_t *rows = reinterpret_cast<int64_t *>(lds);
     if (task.Y) {
-        if ((int)threadIdx.x < task.M) {
-            const int64_t t = task.out_row + threadIdx.x;
-            rows[threadIdx.x] = task.perm ? *(const __attribute__((address_space(1))) int64_t *)(task.perm + t) : t;
+        if (tid < task.M) {
+            const int64_t t = task.out_row + tid;
+            rows[tid] = task.perm ? *(const __attribute__((address_space(1))) int64_t *)(task.perm + t) : t;
         }
         __syncthreads();
     }
-    if (wave >= WAVES_M * WAVES_N) return;
-    const int wm = wave / WAVES_N, wn = wave % WAVES_N;
-    OUT *base = task.out_buf == 0 ? buf0 : task.out_buf == 1 ? buf1 : task.out_buf == 2 ? buf2 : buf3;
-    OUT *out = base + task.out_row * ldq + n0;
-    const int64_t lim = task.Y ? task.Q - n0 : BN;  // columns of this tile to store
+    if (computes && !(split_copy && task.out_split == 2)) {
+        OUT *base = task.out_buf == 0 ? buf0 : task.out_buf == 1 ? buf1 : task.out_buf == 2 ? buf2 : buf3;
+        OUT *out = base + task.out_row * ldq + n0;
+        const int64_t lim = task.Y ? task.Q - n0 : BN;  // columns of this tile to store
 #pragma unroll
-    for (int i = 0; i < FM; i++)
+        for (int i = 0; i < FM; i++)
 #pragma unroll
-        for (int r = 0; r < 4; r++) {
-            const int row = wm * WM + i * 16 + frag_row<F32_ROWS>(lane, r);
-            if (row >= task.M) continue;
-            gOUT *o = task.Y ? (gOUT *)((OUT *)task.Y + rows[row] * task.ldy + n0)
-                             : (gOUT *)(out + (int64_t)row * ldq);
+            for (int r = 0; r < 4; r++) {
+                const int row = wm * WM + i * 16 + frag_row<F32_ROWS>(lane, r);
+                if (row >= task.M) continue;
+                gOUT *o = task.Y ? (gOUT *)((OUT *)task.Y + rows[row] * task.ldy + n0)
+                                 : (gOUT *)(out + (int64_t)row * ldq);
 #pragma unroll
-            for (int j = 0; j < FN; j++) {
-                const int col = wn * WN + j * 16 + (lane & 15);
-                if (col < lim) o[col] = task.accumulate ? o[col] + (OUT)acc[i][j][r] : (OUT)acc[i][j][r];
+                for (int j = 0; j < FN; j++) {
+                    const int col = wn * WN + j * 16 + (lane & 15);
+                    if (col < lim) o[col] = task.accumulate ? o[col] + (OUT)acc[i][j][r] : (OUT)acc[i][j][r];
+                }
+            }
+    }
+    if constexpr (kSplitCopy) {
+        if (split_copy) {
+            __syncthreads();
+            // one (32-row chunk, column) per step: 32 hi then 32 lo values,
+            // 128 contiguous bytes of the workspace
+            const float *tile = reinterpret_cast<const float *>(lds);
+            __bf16 *Y16 = reinterpret_cast<__bf16 *>(task.Y16);
+            constexpr int kChunks = BM / Split16::kRows;
+            const int chunks = (task.M + Split16::kRows - 1) / Split16::kRows;
+#pragma unroll 1
+            for (int e = tid; e < kChunks * BN; e += blockDim.x) {
+                const int c = e / BN, col = e % BN;
+                if (c >= chunks) break;
+                const float *src = tile + col * kPitch + c * 32;
+                __bf16 *dst = Y16 + (task.out16 + c * 32) * 2 * ldq + (n0 + col) * 64;
+#pragma unroll
+                for (int v = 0; v < 4; v++) {  // rows 8v .. 8v + 7 of the chunk
+                    const f4_t x0 = *reinterpret_cast<const f4_t *>(src + 8 * v);
+                    const f4_t x1 = *reinterpret_cast<const f4_t *>(src + 8 * v + 4);
+                    bf16x8_t hi, lo;
+#pragma unroll
+                    for (int u = 0; u < 8; u++) {
+                        __bf16 h, l;
+                        split_bf16(c * 32 + 8 * v + u < task.M ? (u < 4 ? x0[u] : x1[u - 4]) : 0.0f, h, l);
+                        hi[u] = h;
+                        lo[u] = l;
+                    }
+                    *(__attribute__((address_space(1))) bf16x8_t *)(dst + 8 * v) = hi;
+                    *(__attribute__((address_space(1))) bf16x8_t *)(dst + 32 + 8 * v) = lo;
+                }
             }
         }
+    }
 }
 
 // One output tile: out (=|+=) sum over the task's segments of A_s * B_s.
-template <typename T, int BM, int BN, int WAVES_M, int WAVES_N, int NT>
+// ROWPERM (FP64): accumulate in the FP32 register layout (see product_loop),
+// as the mixed-precision launch does so that the split copy of the output
+// can be written from consecutive rows.
+template <typename T, int BM, int BN, int WAVES_M, int WAVES_N, int NT, bool ROWPERM = false>
 __device__ __forceinline__ void block_product(const TileJob &task, const Seg *__restrict__ segs,
                                               const T *__restrict__ store, T *buf0, T *buf1,
                                               T *buf2, T *buf3, int64_t ldq, int64_t n0, T *As_,
@@ -293,10 +382,10 @@ __device__ __forceinline__ void block_product(const TileJob &task, const Seg *__
     for (int i = 0; i < TL::FM; i++)
 #pragma unroll
         for (int j = 0; j < TL::FN; j++) acc[i][j] = typename Mfma<T>::acc_t{0, 0, 0, 0};
-    product_loop<T, BM, BN, WAVES_M, WAVES_N, NT>(segs, task.seg_begin, task.seg_end, task.m0, store, buf0,
-                                                  buf1, buf2, buf3, ldq, n0, As_, Bs_, acc);
-    store_tile<T, typename Mfma<T>::acc_t, BM, BN, WAVES_M, WAVES_N, sizeof(T) == 4>(task, buf0, buf1, buf2,
-                                                                                     buf3, ldq, n0, As_, acc);
+    product_loop<T, BM, BN, WAVES_M, WAVES_N, NT, ROWPERM>(segs, task.seg_begin, task.seg_end, task.m0, store,
+                                                           buf0, buf1, buf2, buf3, ldq, n0, As_, Bs_, acc);
+    store_tile<T, typename Mfma<T>::acc_t, BM, BN, WAVES_M, WAVES_N, ROWPERM || sizeof(T) == 4>(
+        task, buf0, buf1, buf2, buf3, ldq, n0, As_, acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -310,28 +399,23 @@ __device__ __forceinline__ void block_product(const TileJob &task, const Seg *__
 // block is a run of 32-wide contraction chunks, each chunk the hi part
 // (lda rows x 32 contraction values, row-major) followed by the lo part.
 // B rows come from the FP64 workspaces and are split while being staged.
-typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
-typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
-typedef short s16x8_t __attribute__((ext_vector_type(8)));
 
 constexpr int kKC = 32;              // contraction rows per chunk
 constexpr int kKCP = kKC + 8;        // LDS row pitch in bf16 (80 bytes)
 
-__device__ __forceinline__ void split_bf16(float f, __bf16 &hi, __bf16 &lo) {
-    hi = (__bf16)f;
-    lo = (__bf16)(f - (float)hi);
-}
 
 // LDS: As[2 stages][2 (hi, lo)][BM][kKCP], Bs[2][2][BN][kKCP] (bf16).
 template <int BM, int BN>
 constexpr int bf16_lds_bytes() {
     return 2 * 2 * (BM + BN) * kKCP * 2;
 }
-// LDS of a split-then-FP64 tile: the split-BF16 buffers, or the FP32 partial
-// sums of the whole tile while they are handed over, whichever is larger.
+// LDS of a tile of the mixed-precision launch: the split-BF16 buffers, the
+// FP32 partial sums of the whole tile while they are handed over, or the
+// split copy of the output, whichever is largest.
 template <int BM, int BN>
 constexpr int split_f64_lds_bytes() {
-    return bf16_lds_bytes<BM, BN>() > BM * BN * 4 ? bf16_lds_bytes<BM, BN>() : BM * BN * 4;
+    constexpr int a = bf16_lds_bytes<BM, BN>() > BM * BN * 4 ? bf16_lds_bytes<BM, BN>() : BM * BN * 4;
+    return a > split_copy_lds_bytes<BM, BN>() ? a : split_copy_lds_bytes<BM, BN>();
 }
 
 // Accumulates rows [m0, m0 + BM) x columns [n0, n0 + BN) of the split-BF16
@@ -339,8 +423,8 @@ constexpr int split_f64_lds_bytes() {
 // layout, frag_row<true>).
 template <int BM, int BN, int WAVES_M, int WAVES_N, int NT>
 __device__ __forceinline__ void product_loop_bf16x3(
-    const Seg *__restrict__ segs, int sb, int se, int m0, const __bf16 *__restrict__ store16, double *buf0,
-    double *buf1, double *buf2, double *buf3, int64_t ldq, int64_t n0, char *lds,
+    const Seg *__restrict__ segs, int sb, int se, int m0, const __bf16 *__restrict__ store16,
+    const __bf16 *w16, const __bf16 *what16, const __bf16 *yhat16, int64_t ldq, int64_t n0, char *lds,
     f4_t (&acc)[Tile<BM, BN, WAVES_M, WAVES_N>::FM][Tile<BM, BN, WAVES_M, WAVES_N>::FN]) {
     constexpr int WM = BM / WAVES_M, WN = BN / WAVES_N;
     constexpr int FM = WM / 16, FN = WN / 16;
@@ -348,9 +432,10 @@ __device__ __forceinline__ void product_loop_bf16x3(
     // A chunk: BM rows x 32 values x {hi, lo}, as 16-byte vectors (4 per row and part)
     constexpr int A_VECS = 2 * BM * (kKC / 8);
     constexpr int A_PER = (A_VECS + NT - 1) / NT;
-    // B chunk: (16 contraction pairs) x (BN / 2 column pairs), 2 x 16-byte loads each
-    constexpr int B_ITEMS = (kKC / 2) * (BN / 2);
-    constexpr int B_PER = (B_ITEMS + NT - 1) / NT;
+    // B chunk: BN columns x {hi, lo} x 32 values from a split workspace (one
+    // contiguous run, see Split16), as 16-byte vectors (8 per column)
+    constexpr int B_VECS = BN * 8;
+    constexpr int B_PER = (B_VECS + NT - 1) / NT;
     __bf16(*As)[2][BM][kKCP] = reinterpret_cast<__bf16(*)[2][BM][kKCP]>(lds);
     __bf16(*Bs)[2][BN][kKCP] =
         reinterpret_cast<__bf16(*)[2][BN][kKCP]>(lds + 2 * 2 * BM * kKCP * 2);
@@ -358,10 +443,10 @@ __device__ __forceinline__ void product_loop_bf16x3(
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const bool computes = wave < WAVES_M * WAVES_N;
     const int wm = wave / WAVES_N, wn = wave % WAVES_N;
-    auto bufp = [&](int b) { return b == 0 ? buf0 : b == 1 ? buf1 : b == 2 ? buf2 : buf3; };
+    // the split workspace of a segment's B operand (by its FP64 buffer id)
+    auto b16p = [&](int b) { return b == BUF_WT ? w16 : b == BUF_WHAT ? what16 : yhat16; };
 
-    s16x8_t ra[A_PER];
-    d2_t rb0[B_PER], rb1[B_PER];
+    s16x8_t ra[A_PER], rb[B_PER];
 
     auto load = [&](const Seg &sg, int kk) {
         // chunk kk / 32 of the block; rows m0.. of the hi and lo parts
@@ -372,14 +457,13 @@ __device__ __forceinline__ void product_loop_bf16x3(
             const int part = idx / (BM * 4), rem = idx % (BM * 4), r = rem / 4, c = (rem % 4) * 8;
             ra[u] = load_global<s16x8_t>(A + (int64_t)part * sg.lda * kKC + (int64_t)(m0 + r) * kKC + c);
         }
-        const double *Bp = bufp(sg.b_buf) + sg.b_row * ldq + n0;
+        // chunk rows [b_row16 + kk, + 32) of the node, columns n0..: rows past
+        // the node's last row are zero in the workspace (and in A)
+        const __bf16 *B = b16p(sg.b_buf) + (sg.b_row16 + kk) * 2 * ldq + n0 * 64;
 #pragma unroll
         for (int u = 0; u < B_PER; u++) {
-            const int idx = min(tid + u * NT, B_ITEMS - 1);
-            const int pr = idx % (kKC / 2), cp = idx / (kKC / 2);
-            const int k0 = min(kk + 2 * pr, sg.K - 1), k1 = min(kk + 2 * pr + 1, sg.K - 1);
-            rb0[u] = load_global<d2_t>(Bp + (int64_t)k0 * ldq + 2 * cp);
-            rb1[u] = load_global<d2_t>(Bp + (int64_t)k1 * ldq + 2 * cp);
+            const int idx = min(tid + u * NT, B_VECS - 1);
+            rb[u] = load_global<s16x8_t>(B + (int64_t)idx * 8);
         }
     };
     auto stash = [&](int b) {
@@ -394,16 +478,9 @@ __device__ __forceinline__ void product_loop_bf16x3(
 #pragma unroll
         for (int u = 0; u < B_PER; u++) {
             const int idx = tid + u * NT;
-            if (B_ITEMS % NT == 0 || idx < B_ITEMS) {
-                const int pr = idx % (kKC / 2), cp = idx / (kKC / 2);
-#pragma unroll
-                for (int e = 0; e < 2; e++) {  // the two columns of the pair
-                    __bf16 h0, l0, h1, l1;
-                    split_bf16((float)rb0[u][e], h0, l0);
-                    split_bf16((float)rb1[u][e], h1, l1);
-                    *reinterpret_cast<bf16x2_t *>(&Bs[b][0][2 * cp + e][2 * pr]) = bf16x2_t{h0, h1};
-                    *reinterpret_cast<bf16x2_t *>(&Bs[b][1][2 * cp + e][2 * pr]) = bf16x2_t{l0, l1};
-                }
+            if (B_VECS % NT == 0 || idx < B_VECS) {
+                const int n = idx / 8, part = (idx / 4) % 2, kv = (idx % 4) * 8;
+                *reinterpret_cast<s16x8_t *>(&Bs[b][part][n][kv]) = rb[u];
             }
         }
     };
@@ -463,7 +540,8 @@ __device__ __forceinline__ void product_loop_bf16x3(
 // One output tile in split BF16: out (=|+=) sum over the task's segments.
 template <int BM, int BN, int WAVES_M, int WAVES_N, int NT>
 __device__ __forceinline__ void block_product_bf16x3(const TileJob &task, const Seg *__restrict__ segs,
-                                                     const __bf16 *__restrict__ store16, double *buf0,
+                                                     const __bf16 *__restrict__ store16, const __bf16 *w16,
+                                                     const __bf16 *what16, const __bf16 *yhat16, double *buf0,
                                                      double *buf1, double *buf2, double *buf3,
                                                      int64_t ldq, int64_t n0, char *lds) {
     typedef Tile<BM, BN, WAVES_M, WAVES_N> TL;
@@ -473,7 +551,7 @@ __device__ __forceinline__ void block_product_bf16x3(const TileJob &task, const 
 #pragma unroll
         for (int j = 0; j < TL::FN; j++) acc[i][j] = f4_t{0, 0, 0, 0};
     product_loop_bf16x3<BM, BN, WAVES_M, WAVES_N, NT>(segs, task.seg_begin, task.seg_end, task.m0, store16,
-                                                      buf0, buf1, buf2, buf3, ldq, n0, lds, acc);
+                                                      w16, what16, yhat16, ldq, n0, lds, acc);
     store_tile<double, f4_t, BM, BN, WAVES_M, WAVES_N, true>(task, buf0, buf1, buf2, buf3, ldq, n0, lds, acc);
 }
 
@@ -484,8 +562,9 @@ __device__ __forceinline__ void block_product_bf16x3(const TileJob &task, const 
 template <int BM, int BN, int WAVES_M, int WAVES_N, int NT>
 __device__ __forceinline__ void block_product_split_then_f64(const TileJob &task, const Seg *__restrict__ segs,
                                                              const double *__restrict__ store,
-                                                             const __bf16 *__restrict__ store16, double *buf0,
-                                                             double *buf1, double *buf2, double *buf3,
+                                                             const __bf16 *__restrict__ store16, const __bf16 *w16,
+                                                             const __bf16 *what16, const __bf16 *yhat16,
+                                                             double *buf0, double *buf1, double *buf2, double *buf3,
                                                              int64_t ldq, int64_t n0, char *lds) {
     typedef Tile<BM, BN, WAVES_M, WAVES_N> TL;
     f4_t acc32[TL::FM][TL::FN];
@@ -494,7 +573,7 @@ __device__ __forceinline__ void block_product_split_then_f64(const TileJob &task
 #pragma unroll
         for (int j = 0; j < TL::FN; j++) acc32[i][j] = f4_t{0, 0, 0, 0};
     product_loop_bf16x3<BM, BN, WAVES_M, WAVES_N, NT>(segs, task.seg_begin, task.seg_end - 1, task.m0, store16,
-                                                      buf0, buf1, buf2, buf3, ldq, n0, lds, acc32);
+                                                      w16, what16, yhat16, ldq, n0, lds, acc32);
     // hand the partial sums over through LDS (free once the split loop has
     // ended), so that the FP32 and FP64 accumulators are never live together
     constexpr int kVals = TL::FM * TL::FN * 4;
@@ -599,7 +678,7 @@ __global__ __launch_bounds__(kPersistThreads, BN <= 128 ? 4 : 1) void k_persiste
     while (true) {
         if (threadIdx.x == 0) s_t = __hip_atomic_fetch_add(head, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __syncthreads();
-        const int t = s_t;
+        const int t = __builtin_amdgcn_readfirstlane(s_t);  // uniform: task fields load as scalars
         __syncthreads();
         if (t >= n_tasks) break;
         const PTask pt = tasks[t];
@@ -622,6 +701,13 @@ __global__ __launch_bounds__(kPersistThreads, BN <= 128 ? 4 : 1) void k_persiste
             job.Q = Q;
             job.perm = perm;
         }
+        if constexpr (SPLIT && sizeof(T) == 8) {
+            if (pt.out16 >= 0) {  // split copy of Ŵ or of a leaf's Ŷ (mixed precision)
+                job.Y16 = md.buf16[pt.out_buf];
+                job.out16 = pt.out16;
+                job.out_split = pt.out_split;
+            }
+        }
         const int64_t n0 = (int64_t)pt.qtile * BN;
         const T *store = (const T *)md.store;
         const Seg *segs = md.segs;
@@ -630,31 +716,33 @@ __global__ __launch_bounds__(kPersistThreads, BN <= 128 ? 4 : 1) void k_persiste
         if (mode != 0) {
             if constexpr (SPLIT && sizeof(T) == 8) {
                 const __bf16 *s16 = (const __bf16 *)md.store16;
+                const __bf16 *w16 = (const __bf16 *)md.buf16[BUF_WT], *wh16 = (const __bf16 *)md.buf16[BUF_WHAT],
+                             *yh16 = (const __bf16 *)md.buf16[BUF_YHAT];
                 double *b0 = (double *)md.buf[0], *b1 = (double *)md.buf[1], *b2 = (double *)md.buf[2],
                        *b3 = (double *)md.buf[3];
                 if (mode == 1 && pt.bm == 128)
                     block_product_bf16x3<128, BN, PLayout<128, BN>::WMv, PLayout<128, BN>::WN, kPersistThreads>(
-                        job, segs, s16, b0, b1, b2, b3, md.ldq, n0, lds);
+                        job, segs, s16, w16, wh16, yh16, b0, b1, b2, b3, md.ldq, n0, lds);
                 else if (mode == 1)
                     block_product_bf16x3<64, BN, PLayout<64, BN>::WMv, PLayout<64, BN>::WN, kPersistThreads>(
-                        job, segs, s16, b0, b1, b2, b3, md.ldq, n0, lds);
+                        job, segs, s16, w16, wh16, yh16, b0, b1, b2, b3, md.ldq, n0, lds);
                 else if (pt.bm == 128)
                     block_product_split_then_f64<128, BN, PLayout<128, BN>::WMv, PLayout<128, BN>::WN,
-                                                 kPersistThreads>(job, segs, (const double *)store, s16, b0, b1,
-                                                                  b2, b3, md.ldq, n0, lds);
+                                                 kPersistThreads>(job, segs, (const double *)store, s16, w16, wh16,
+                                                                  yh16, b0, b1, b2, b3, md.ldq, n0, lds);
                 else
                     block_product_split_then_f64<64, BN, PLayout<64, BN>::WMv, PLayout<64, BN>::WN,
-                                                 kPersistThreads>(job, segs, (const double *)store, s16, b0, b1,
-                                                                  b2, b3, md.ldq, n0, lds);
+                                                 kPersistThreads>(job, segs, (const double *)store, s16, w16, wh16,
+                                                                  yh16, b0, b1, b2, b3, md.ldq, n0, lds);
             }
         } else if (pt.bm == 128) {
-            block_product<T, 128, BN, PLayout<128, BN>::WMv, PLayout<128, BN>::WN, kPersistThreads>(
-                job, segs, store, (T *)md.buf[0], (T *)md.buf[1], (T *)md.buf[2], (T *)md.buf[3],
-                md.ldq, n0, As, Bs);
+            block_product<T, 128, BN, PLayout<128, BN>::WMv, PLayout<128, BN>::WN, kPersistThreads,
+                          SPLIT && sizeof(T) == 8>(job, segs, store, (T *)md.buf[0], (T *)md.buf[1],
+                                                   (T *)md.buf[2], (T *)md.buf[3], md.ldq, n0, As, Bs);
         } else if (!fine_tiles(sizeof(T), BN, SPLIT) || pt.bm == 64) {
-            block_product<T, 64, BN, PLayout<64, BN>::WMv, PLayout<64, BN>::WN, kPersistThreads>(
-                job, segs, store, (T *)md.buf[0], (T *)md.buf[1], (T *)md.buf[2], (T *)md.buf[3],
-                md.ldq, n0, As, Bs);
+            block_product<T, 64, BN, PLayout<64, BN>::WMv, PLayout<64, BN>::WN, kPersistThreads,
+                          SPLIT && sizeof(T) == 8>(job, segs, store, (T *)md.buf[0], (T *)md.buf[1],
+                                                   (T *)md.buf[2], (T *)md.buf[3], md.ldq, n0, As, Bs);
         } else if constexpr (fine_tiles(sizeof(T), BN, SPLIT)) {
             // 32- and 96-row tiles, for output blocks whose row count would
             // waste most of a 64- or 128-row tile
@@ -695,6 +783,39 @@ __global__ void k_permute_in(const T *__restrict__ W, int64_t ldw, T *__restrict
         const int64_t t = e / Qp, c = e % Qp;
         const int64_t src = perm ? perm[t] : t;
         Wt[e] = c < Q ? W[src * ldw + c] : T(0);
+    }
+}
+
+// Split-BF16 W in tree order (see Split16): one thread per (32-row chunk,
+// column); chunks[3c..3c+2] = (first tree row, rows, first split row).  Rows
+// past the chunk's rows and columns >= Q are zero.
+__global__ void k_permute_in_split(const double *__restrict__ W, int64_t ldw, __bf16 *__restrict__ W16,
+                                   int64_t ldq, const int64_t *__restrict__ perm,
+                                   const int64_t *__restrict__ chunks, int64_t n_chunks, int64_t Q) {
+    const int64_t total = n_chunks * ldq;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = e / ldq, col = e % ldq;
+        const int64_t t0 = chunks[3 * c], nr = chunks[3 * c + 1], g = chunks[3 * c + 2];
+        bf16x8_t hi[4], lo[4];
+#pragma unroll
+        for (int k = 0; k < 32; k++) {
+            double v = 0.0;
+            if (k < nr && col < Q) {
+                const int64_t t = t0 + k;
+                v = W[(perm ? perm[t] : t) * ldw + col];
+            }
+            __bf16 h, l;
+            split_bf16((float)v, h, l);
+            hi[k / 8][k % 8] = h;
+            lo[k / 8][k % 8] = l;
+        }
+        __bf16 *dst = W16 + g * 2 * ldq + col * 64;
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+            *reinterpret_cast<bf16x8_t *>(dst + v * 8) = hi[v];
+            *reinterpret_cast<bf16x8_t *>(dst + 32 + v * 8) = lo[v];
+        }
     }
 }
 
@@ -960,6 +1081,14 @@ hipError_t launch_repack(const double *stage, const RepackJob *jobs, int njobs, 
                          hipStream_t s) {
     if (njobs == 0) return hipSuccess;
     hipLaunchKernelGGL(k_repack, dim3((unsigned)njobs), dim3(256), 0, s, stage, jobs, store);
+    return hipGetLastError();
+}
+
+hipError_t launch_permute_in_split(const double *W, int64_t ldw, void *W16, int64_t ldq, const int64_t *perm,
+                                   const int64_t *chunks, int64_t n_chunks, int64_t Q, hipStream_t s) {
+    if (n_chunks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_permute_in_split, dim3(grid_for(n_chunks * ldq, 256)), dim3(256), 0, s, W, ldw,
+                       (__bf16 *)W16, ldq, perm, chunks, n_chunks, Q);
     return hipGetLastError();
 }
 

@@ -222,6 +222,8 @@ hm_status build_plan(const std::vector<PlanPart> &parts, int bn, int elem_bytes,
         t.seg_begin = g.seg_begin;
         t.seg_end = g.seg_end;
         t.bm = tile_bm;
+        t.out16 = g.out16 >= 0 ? g.out16 + t.m0 : -1;
+        t.out_split = g.out16 >= 0 ? g.out_split : 0;
         t.accumulate = g.accumulate;
         t.qtile = q;
         t.mat = p.mat;
