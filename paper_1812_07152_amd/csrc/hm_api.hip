@@ -69,6 +69,7 @@ hm_status ensure_ws16(hm_matrix h, int b, size_t bytes) {
     }
     HM_HIP(hipMalloc(&h->ws16[b], bytes));
     HM_HIP(hipMemset(h->ws16[b], 0, bytes));
+    HM_HIP(hipDeviceSynchronize());  // the fill is done before work on any stream reads the buffer
     h->ws16_bytes[b] = bytes;
     return HM_OK;
 }

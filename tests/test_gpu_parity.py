@@ -46,6 +46,9 @@ CASES = {
     "hss_lap": wl.small("hss_lap", N=2500, d=3, m=70, adm=wl.ADM_HSS, kernel=wl.KERNEL_LAPLACE,
                         h=2.0, rmax=70, Q=20),
     "single_node": wl.small("single_node", N=100, d=3, m=128, Q=5),
+    # ranks and leaves above 128: every node's blocks span two row tiles
+    "tall": wl.small("tall", N=4096, d=28, points="normal", m=256, adm=wl.ADM_HSS,
+                     kernel=wl.KERNEL_LAPLACE, h=4.0, tol=1e-4, rmax=200, Q=40),
     "deep_small_leaves": wl.small("deep", N=2048, d=3, m=8, Q=4, rmax=8),
 }
 _built = {}
@@ -205,6 +208,28 @@ def test_mixed_precision_bf16x3(hmx, name, sched):
     err = rel(Yd.cpu().numpy(), H.eval(W))
     _say(f"[mixed] case={name} rel err={err:.3e}")
     assert err <= 5e-5
+
+
+def test_mixed_precision_tall_tiles(hmx, sched):
+    """Split BF16 where ranks (200) and leaves (256 points) exceed one 128-row
+    tile: the split copies of Ŵ and of the leaves' Ŷ are written by two row
+    tiles per node (the second starting 128 rows into the node's 32-row
+    chunks).  Q = 40 and 300 run different column tiles; 5e-5 bar against the
+    FP64 oracle."""
+    if sched == "level":
+        pytest.skip("mixed precision runs on the task-graph launch only")
+    w, H = built("tall")
+    assert int(np.max(H.rank)) > 128
+    M = hmx.hm_load_compressed_mem(H, 0, hmx.precbit(hmx.HM_PREC_FP64) | hmx.precbit(hmx.HM_PREC_BF16X3))
+    for Q in (40, 300):
+        W = wl.gen_w(w, Q=Q, seed=300 + Q)
+        Wd = torch.from_numpy(W).cuda()
+        Yd = torch.full_like(Wd, float("nan"))
+        hmx.hm_eval(M, Wd, Yd, prec=hmx.HM_PREC_BF16X3)
+        hmx.hm_check(M)
+        err = rel(Yd.cpu().numpy(), H.eval(W))
+        _say(f"[mixed] case=tall Q={Q} rel err={err:.3e}")
+        assert err <= 5e-5
 
 
 def test_mixed_precision_shapes_and_flags(hmx, sched):
