@@ -167,7 +167,11 @@ __device__ __forceinline__ void product_loop(
     T(*As)[kBK][LA] = reinterpret_cast<T(*)[kBK][LA]>(As_);
     T(*Bs)[kBK][LB] = reinterpret_cast<T(*)[kBK][LB]>(Bs_);
 
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // thread index made opaque (as in store_tile): per-thread offsets are
+    // computed per task instead of being held through the persistent loop
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const bool computes = wave < WAVES_M * WAVES_N;
     const int wm = wave / WAVES_N, wn = wave % WAVES_N;
     const int arow = ROWPERM ? 4 * (lane & 3) + ((lane >> 2) & 3) : (lane & 15);
@@ -398,18 +402,33 @@ __device__ __forceinline__ void block_product(const TileJob &task, const Seg *__
 // D[4(l/16)+r][l%16]).  A blocks come from the split-BF16 store, where a
 // block is a run of 32-wide contraction chunks, each chunk the hi part
 // (lda rows x 32 contraction values, row-major) followed by the lo part.
-// B rows come from the FP64 workspaces and are split while being staged.
+// B rows come pre-split from the split-BF16 workspaces (see Split16).
 
-constexpr int kKC = 32;              // contraction rows per chunk
-constexpr int kKCP = kKC + 8;        // LDS row pitch in bf16 (80 bytes)
+constexpr int kKC = 32;     // contraction rows per chunk
+constexpr int kStages = 3;  // LDS stages: one consumed, two being filled
 
-
-// LDS: As[2 stages][2 (hi, lo)][BM][kKCP], Bs[2][2][BN][kKCP] (bf16).
+// One LDS stage of a split-BF16 chunk, unpadded: A as [hi, lo][BM rows][32]
+// (64 bytes a row), then B as [BN columns][hi 32, lo 32] (128 bytes a
+// column), both in 16-byte slots.  The stage is filled by direct
+// global-to-LDS loads (each wave instruction writes 64 consecutive slots), so
+// bank conflicts of the MFMA operand reads are avoided by permuting the slots
+// within a row (A) or column (B) instead of padding: logical 16-byte vector
+// g of A row r sits in slot g ^ swz_a(r), logical vector j of B column n in
+// slot j ^ swz_b(n).  For the 16 rows (columns) that one 16-lane group of a
+// fragment read touches, and for any 8 consecutive of them, the slots then
+// fall into distinct 16-byte bank groups.
+template <int BM, int BN>
+constexpr int bf16_stage_bytes() {
+    return (BM + BN) * 128;
+}
 template <int BM, int BN>
 constexpr int bf16_lds_bytes() {
-    return 2 * 2 * (BM + BN) * kKCP * 2;
+    return kStages * bf16_stage_bytes<BM, BN>();
 }
-// LDS of a tile of the mixed-precision launch: the split-BF16 buffers, the
+__device__ __forceinline__ int swz_a(int r) { return ((r >> 1) ^ (r >> 3)) & 3; }
+__device__ __forceinline__ int swz_b(int n) { return ((n >> 1) & 7) ^ ((n & 1) << 2); }
+
+// LDS of a tile of the mixed-precision launch: the split-BF16 stages, the
 // FP32 partial sums of the whole tile while they are handed over, or the
 // split copy of the output, whichever is largest.
 template <int BM, int BN>
@@ -418,9 +437,60 @@ constexpr int split_f64_lds_bytes() {
     return a > split_copy_lds_bytes<BM, BN>() ? a : split_copy_lds_bytes<BM, BN>();
 }
 
+// One direct global-to-LDS load: the 64 lanes' 16-byte vectors at src land
+// in 1 KB of LDS from the wave-uniform address lds_addr, lane l at
+// lds_addr + 16 l.  Written as inline asm so that the compiler does not track
+// these LDS writes: it would otherwise wait for every outstanding one before
+// any LDS read, including the reads of the stage already complete; the
+// chunk pipeline below waits for them itself (wait_vm_barrier).
+__device__ __forceinline__ void load_lds16(const void *src, const char *lds_dst) {
+    const uint32_t a = (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) char *)lds_dst;
+    asm volatile("global_load_lds_dwordx4 %0, off" ::"v"(src), "{m0}"(__builtin_amdgcn_readfirstlane(a))
+                 : "memory");
+}
+
+// Segment descriptor through a scalar (constant address space) load: it
+// counts against the scalar counter, so the compiler's wait for it never
+// covers the chunk loads in flight.  The descriptors are read-only during a
+// launch and the address is uniform.
+__device__ __forceinline__ Seg load_seg_scalar(const Seg *p) {
+    const __attribute__((address_space(4))) Seg *g = (const __attribute__((address_space(4))) Seg *)p;
+    Seg s;
+    s.a_off = g->a_off;
+    s.b_row = g->b_row;
+    s.lda = g->lda;
+    s.K = g->K;
+    s.b_buf = g->b_buf;
+    s.Kpad = g->Kpad;
+    s.a_off16 = g->a_off16;
+    s.b_row16 = g->b_row16;
+    return s;
+}
+
+// Waits until at most N of this wave's vector memory operations are
+// outstanding, then joins the workgroup barrier.  No fence: the barrier of
+// __syncthreads() also waits for every outstanding load, which would drain
+// the loads that are meant to stay in flight across it.  The direct
+// global-to-LDS writes of a chunk are complete once the counter covers them.
+template <int N>
+__device__ __forceinline__ void wait_vm_barrier() {
+    static_assert(N >= 0 && N < 64, "vmcnt out of range");
+    asm volatile("s_waitcnt vmcnt(%0)\n\ts_barrier" ::"n"(N) : "memory");
+}
+
 // Accumulates rows [m0, m0 + BM) x columns [n0, n0 + BN) of the split-BF16
 // products of segments [sb, se) into FP32 accumulators (FP32 register
 // layout, frag_row<true>).
+//
+// Pipeline: chunks of 32 contraction rows go straight from global memory
+// into one of three LDS stages (global_load_lds_dwordx4, no staging
+// registers).  While the MFMAs consume chunk c, the loads of chunks c + 1
+// and c + 2 are in flight; one barrier per chunk.  Every wave issues the same
+// number of loads per chunk (block indices past the stage re-load its last
+// block, the same bytes to the same place), so a chunk is complete once the
+// wave's counter is down to the one later chunk's loads.  Past the last chunk
+// the loads repeat a valid chunk into a stage nobody reads, and the loop ends
+// with every load drained, since the LDS is reused after it.
 template <int BM, int BN, int WAVES_M, int WAVES_N, int NT>
 __device__ __forceinline__ void product_loop_bf16x3(
     const Seg *__restrict__ segs, int sb, int se, int m0, const __bf16 *__restrict__ store16,
@@ -429,75 +499,61 @@ __device__ __forceinline__ void product_loop_bf16x3(
     constexpr int WM = BM / WAVES_M, WN = BN / WAVES_N;
     constexpr int FM = WM / 16, FN = WN / 16;
     static_assert(FM >= 1 && FN >= 1, "bad tile");
-    // A chunk: BM rows x 32 values x {hi, lo}, as 16-byte vectors (4 per row and part)
-    constexpr int A_VECS = 2 * BM * (kKC / 8);
-    constexpr int A_PER = (A_VECS + NT - 1) / NT;
-    // B chunk: BN columns x {hi, lo} x 32 values from a split workspace (one
-    // contiguous run, see Split16), as 16-byte vectors (8 per column)
-    constexpr int B_VECS = BN * 8;
-    constexpr int B_PER = (B_VECS + NT - 1) / NT;
-    __bf16(*As)[2][BM][kKCP] = reinterpret_cast<__bf16(*)[2][BM][kKCP]>(lds);
-    __bf16(*Bs)[2][BN][kKCP] =
-        reinterpret_cast<__bf16(*)[2][BN][kKCP]>(lds + 2 * 2 * BM * kKCP * 2);
+    static_assert(NT == 512, "8 waves fill a stage");
+    constexpr int kStage = bf16_stage_bytes<BM, BN>();
+    constexpr int A_BLOCKS = BM / 8;                  // 1 KB blocks (64 slots) of A: 2 parts x BM rows x 4 slots
+    constexpr int BLOCKS = (BM + BN) / 8;             // A then B (8 slots a column)
+    constexpr int PER_WAVE = (BLOCKS + 7) / 8;        // loads per wave and chunk
+    static_assert(BLOCKS * 1024 == kStage, "stage size");
 
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // thread index made opaque (as in store_tile): the per-thread load and
+    // LDS offsets are computed per task, not once per kernel and held
+    // through every other path of the persistent loop
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const bool computes = wave < WAVES_M * WAVES_N;
     const int wm = wave / WAVES_N, wn = wave % WAVES_N;
     // the split workspace of a segment's B operand (by its FP64 buffer id)
     auto b16p = [&](int b) { return b == BUF_WT ? w16 : b == BUF_WHAT ? what16 : yhat16; };
 
-    s16x8_t ra[A_PER], rb[B_PER];
-
-    auto load = [&](const Seg &sg, int kk) {
-        // chunk kk / 32 of the block; rows m0.. of the hi and lo parts
+    // Chunk kk / 32 of segment sg into LDS stage st.  Slot t = 64 q + lane of
+    // block q: A slots are (part, row, slot), B slots are (column, slot).
+    auto issue = [&](int st, const Seg &sg, int kk) {
         const __bf16 *A = store16 + sg.a_off16 + (int64_t)(kk / kKC) * 2 * sg.lda * kKC;
-#pragma unroll
-        for (int u = 0; u < A_PER; u++) {
-            const int idx = min(tid + u * NT, A_VECS - 1);
-            const int part = idx / (BM * 4), rem = idx % (BM * 4), r = rem / 4, c = (rem % 4) * 8;
-            ra[u] = load_global<s16x8_t>(A + (int64_t)part * sg.lda * kKC + (int64_t)(m0 + r) * kKC + c);
-        }
-        // chunk rows [b_row16 + kk, + 32) of the node, columns n0..: rows past
-        // the node's last row are zero in the workspace (and in A)
         const __bf16 *B = b16p(sg.b_buf) + (sg.b_row16 + kk) * 2 * ldq + n0 * 64;
+        char *stage = lds + st * kStage;
 #pragma unroll
-        for (int u = 0; u < B_PER; u++) {
-            const int idx = min(tid + u * NT, B_VECS - 1);
-            rb[u] = load_global<s16x8_t>(B + (int64_t)idx * 8);
+        for (int u = 0; u < PER_WAVE; u++) {
+            const int q = min(u * 8 + wave, BLOCKS - 1);  // wave-uniform
+            const __bf16 *src;
+            if (q < A_BLOCKS) {
+                const int t = q * 64 + lane, part = t / (BM * 4), r = (t / 4) % BM, g = (t % 4) ^ swz_a(r);
+                src = A + (int64_t)part * sg.lda * kKC + (int64_t)(m0 + r) * kKC + g * 8;
+            } else {
+                const int t = (q - A_BLOCKS) * 64 + lane, n = t / 8, j = (t % 8) ^ swz_b(n);
+                src = B + n * 64 + j * 8;
+            }
+            load_lds16(src, stage + q * 1024);
         }
     };
-    auto stash = [&](int b) {
-#pragma unroll
-        for (int u = 0; u < A_PER; u++) {
-            const int idx = tid + u * NT;
-            if (A_VECS % NT == 0 || idx < A_VECS) {
-                const int part = idx / (BM * 4), rem = idx % (BM * 4), r = rem / 4, c = (rem % 4) * 8;
-                *reinterpret_cast<s16x8_t *>(&As[b][part][r][c]) = ra[u];
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < B_PER; u++) {
-            const int idx = tid + u * NT;
-            if (B_VECS % NT == 0 || idx < B_VECS) {
-                const int n = idx / 8, part = (idx / 4) % 2, kv = (idx % 4) * 8;
-                *reinterpret_cast<s16x8_t *>(&Bs[b][part][n][kv]) = rb[u];
-            }
-        }
-    };
-    auto compute = [&](int b) {
-        const int kg = (lane >> 4) * 8;
+    auto compute = [&](int st) {
+        const char *stage = lds + st * kStage;
+        const int kg = lane >> 4;
         bf16x8_t ah[FM], al[FM], bh[FN], bl[FN];
 #pragma unroll
         for (int i = 0; i < FM; i++) {
             const int r = wm * WM + i * 16 + (lane & 15);
-            ah[i] = *reinterpret_cast<const bf16x8_t *>(&As[b][0][r][kg]);
-            al[i] = *reinterpret_cast<const bf16x8_t *>(&As[b][1][r][kg]);
+            const int off = r * 64 + ((kg ^ swz_a(r)) * 16);
+            ah[i] = *reinterpret_cast<const bf16x8_t *>(stage + off);
+            al[i] = *reinterpret_cast<const bf16x8_t *>(stage + BM * 64 + off);
         }
 #pragma unroll
         for (int j = 0; j < FN; j++) {
             const int n = wn * WN + j * 16 + (lane & 15);
-            bh[j] = *reinterpret_cast<const bf16x8_t *>(&Bs[b][0][n][kg]);
-            bl[j] = *reinterpret_cast<const bf16x8_t *>(&Bs[b][1][n][kg]);
+            const char *col = stage + BM * 128 + n * 128;
+            bh[j] = *reinterpret_cast<const bf16x8_t *>(col + ((kg ^ swz_b(n)) * 16));
+            bl[j] = *reinterpret_cast<const bf16x8_t *>(col + (((4 + kg) ^ swz_b(n)) * 16));
         }
 #pragma unroll
         for (int i = 0; i < FM; i++)
@@ -509,31 +565,60 @@ __device__ __forceinline__ void product_loop_bf16x3(
             }
     };
 
-    if (sb < se) {
-        int s = sb, kk = 0, b = 0;
-        Seg sg = load_seg(segs + s);
-        load(sg, 0);
-        stash(0);
-        __syncthreads();
-        while (true) {
-            int nkk = kk + kKC, ns = s;
-            Seg nsg = sg;
-            if (nkk >= sg.K) {
-                ns = s + 1;
-                nkk = 0;
-                if (ns < se) nsg = load_seg(segs + ns);
+    // Position of the next chunk to load: chunk kk / 32 of segment s, with
+    // the descriptor of segment s + 1 loaded one segment ahead (so that its
+    // wait never covers the chunk loads issued after it).  Past the last
+    // chunk (s == se) it keeps the last segment with kk = 0: loads issued for
+    // it stay inside that segment's block and node rows.
+    struct Cursor {
+        int s, kk;
+        Seg sg, nsg;
+    };
+    // (readfirstlane: the cursor is wave-uniform, and keeping it in scalar
+    // registers keeps the loop's branches and descriptor loads scalar)
+    auto advance = [&](Cursor c) {
+        if (c.s < se) {
+            c.kk += kKC;
+            if (c.kk >= c.sg.K) {
+                c.s++;
+                c.kk = 0;
+                if (c.s < se) {
+                    c.sg = c.nsg;
+                    if (c.s + 1 < se) c.nsg = load_seg_scalar(segs + c.s + 1);
+                }
             }
-            const bool more = ns < se;
-            load(nsg, more ? nkk : kk);
-            if (computes) compute(b);
-            stash(b ^ 1);
-            __syncthreads();
-            if (!more) break;
-            s = ns;
-            kk = nkk;
-            sg = nsg;
-            b ^= 1;
         }
+        c.s = __builtin_amdgcn_readfirstlane(c.s);
+        c.kk = __builtin_amdgcn_readfirstlane(c.kk);
+        return c;
+    };
+
+    if (sb < se) {
+        // nothing older may be outstanding: the count-based waits below
+        // assume that only this loop's loads are in flight
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        Cursor cur;
+        cur.s = sb;
+        cur.kk = 0;
+        cur.sg = load_seg_scalar(segs + sb);
+        cur.nsg = sb + 1 < se ? load_seg_scalar(segs + sb + 1) : cur.sg;
+        issue(0, cur.sg, cur.kk);  // chunk 0
+        cur = advance(cur);
+        bool next_valid = cur.s < se;  // chunk c + 1 exists
+        issue(1, cur.sg, cur.kk);      // chunk 1 (or a repeat)
+        cur = advance(cur);            // chunk c + 2
+        int st = 0;                    // stage of chunk c
+        while (true) {
+            wait_vm_barrier<PER_WAVE>();  // chunk c has landed in every wave's part; stage c + 2 is free
+            const bool after_valid = cur.s < se;
+            issue(st == 0 ? 2 : st - 1, cur.sg, cur.kk);  // chunk c + 2 (or a repeat)
+            if (computes) compute(st);
+            if (!next_valid) break;
+            next_valid = after_valid;
+            cur = advance(cur);
+            st = __builtin_amdgcn_readfirstlane(st == 2 ? 0 : st + 1);
+        }
+        wait_vm_barrier<0>();  // no load may land in the LDS after the loop
     }
 }
 
@@ -578,14 +663,16 @@ __device__ __forceinline__ void block_product_split_then_f64(const TileJob &task
     // ended), so that the FP32 and FP64 accumulators are never live together
     constexpr int kVals = TL::FM * TL::FN * 4;
     float *stage = reinterpret_cast<float *>(lds);
-    const bool computes = (int)(threadIdx.x >> 6) < WAVES_M * WAVES_N;
+    int tid = threadIdx.x;  // opaque: the LDS addresses are not hoisted out of the task loop
+    asm volatile("" : "+v"(tid));
+    const bool computes = __builtin_amdgcn_readfirstlane(tid >> 6) < WAVES_M * WAVES_N;
     if (computes) {
 #pragma unroll
         for (int i = 0; i < TL::FM; i++)
 #pragma unroll
             for (int j = 0; j < TL::FN; j++)
 #pragma unroll
-                for (int r = 0; r < 4; r++) stage[((i * TL::FN + j) * 4 + r) * NT + threadIdx.x] = acc32[i][j][r];
+                for (int r = 0; r < 4; r++) stage[((i * TL::FN + j) * 4 + r) * NT + tid] = acc32[i][j][r];
     }
     __syncthreads();
     d4_t acc[TL::FM][TL::FN];
@@ -595,7 +682,7 @@ __device__ __forceinline__ void block_product_split_then_f64(const TileJob &task
         for (int j = 0; j < TL::FN; j++)
 #pragma unroll
             for (int r = 0; r < 4; r++)
-                acc[i][j][r] = computes ? (double)stage[((i * TL::FN + j) * 4 + r) * NT + threadIdx.x] : 0.0;
+                acc[i][j][r] = computes ? (double)stage[((i * TL::FN + j) * 4 + r) * NT + tid] : 0.0;
     static_assert(kVals * NT * 4 <= split_f64_lds_bytes<BM, BN>(), "LDS hand-over does not fit");
     __syncthreads();
     double *As = reinterpret_cast<double *>(lds);
@@ -693,7 +780,7 @@ __global__ __launch_bounds__(kPersistThreads, BN <= 128 ? 4 : 1) void k_persiste
             }
         }
         __syncthreads();
-        const MatDesc md = mats[pt.mat];
+        const MatDesc &md = mats[pt.mat];  // fields read in place: a private copy would be indexed dynamically (buf16) and live in scratch
         TileJob job{pt.out_row, pt.out_buf, pt.M, pt.m0, pt.seg_begin, pt.seg_end, pt.accumulate};
         if (Y && pt.out_buf == BUF_YT) {  // leaf rows go straight to the caller's Y
             job.Y = Y;
