@@ -84,6 +84,47 @@ __device__ __forceinline__ Seg load_seg(const Seg *p) {
     return s;
 }
 
+// One direct global-to-LDS load: the 64 lanes' 16-byte vectors at src land
+// in 1 KB of LDS from the wave-uniform address lds_addr, lane l at
+// lds_addr + 16 l.  Written as inline asm so that the compiler does not track
+// these LDS writes: it would otherwise wait for every outstanding one before
+// any LDS read, including the reads of the stage already complete; the
+// chunk pipeline below waits for them itself (wait_vm_barrier).
+__device__ __forceinline__ void load_lds16(const void *src, const char *lds_dst) {
+    const uint32_t a = (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) char *)lds_dst;
+    asm volatile("global_load_lds_dwordx4 %0, off" ::"v"(src), "{m0}"(__builtin_amdgcn_readfirstlane(a))
+                 : "memory");
+}
+
+// Segment descriptor through a scalar (constant address space) load: it
+// counts against the scalar counter, so the compiler's wait for it never
+// covers the chunk loads in flight.  The descriptors are read-only during a
+// launch and the address is uniform.
+__device__ __forceinline__ Seg load_seg_scalar(const Seg *p) {
+    const __attribute__((address_space(4))) Seg *g = (const __attribute__((address_space(4))) Seg *)p;
+    Seg s;
+    s.a_off = g->a_off;
+    s.b_row = g->b_row;
+    s.lda = g->lda;
+    s.K = g->K;
+    s.b_buf = g->b_buf;
+    s.Kpad = g->Kpad;
+    s.a_off16 = g->a_off16;
+    s.b_row16 = g->b_row16;
+    return s;
+}
+
+// Waits until at most N of this wave's vector memory operations are
+// outstanding, then joins the workgroup barrier.  No fence: the barrier of
+// __syncthreads() also waits for every outstanding load, which would drain
+// the loads that are meant to stay in flight across it.  The direct
+// global-to-LDS writes of a chunk are complete once the counter covers them.
+template <int N>
+__device__ __forceinline__ void wait_vm_barrier() {
+    static_assert(N >= 0 && N < 64, "vmcnt out of range");
+    asm volatile("s_waitcnt vmcnt(%0)\n\ts_barrier" ::"n"(N) : "memory");
+}
+
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
 typedef short s16x8_t __attribute__((ext_vector_type(8)));
@@ -167,11 +208,9 @@ __device__ __forceinline__ void product_loop(
     T(*As)[kBK][LA] = reinterpret_cast<T(*)[kBK][LA]>(As_);
     T(*Bs)[kBK][LB] = reinterpret_cast<T(*)[kBK][LB]>(Bs_);
 
-    // thread index made opaque (as in store_tile): per-thread offsets are
-    // computed per task instead of being held through the persistent loop
-    int tid = threadIdx.x;
-    asm volatile("" : "+v"(tid));
-    const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    // (the thread index is not made opaque here: hoisting this loop's
+    // per-thread offsets out of the task loop pays for the FP32 tiles)
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const bool computes = wave < WAVES_M * WAVES_N;
     const int wm = wave / WAVES_N, wn = wave % WAVES_N;
     const int arow = ROWPERM ? 4 * (lane & 3) + ((lane >> 2) & 3) : (lane & 15);
@@ -257,6 +296,169 @@ __device__ __forceinline__ void product_loop(
     }
 }
 
+// FP64 products in the persistent launch: the same loop as product_loop, fed
+// by direct global-to-LDS loads (see product_loop_bf16x3 for the pipeline
+// and its waits).  A stage holds the chunk's 16 contraction rows of A (BM
+// values each) and then of B (BN values each), K-major and unpadded.  An
+// MFMA operand read takes 16 consecutive values of one row per 16 lanes, and
+// two 16-lane groups (rows kr and kr + 1) share an LDS cycle; where a row is
+// an even number of 128-byte halves long, odd rows are stored with their
+// 16-byte slots permuted by slot ^ 8 (their halves swapped within each
+// 256 bytes), so the two groups fall on different bank halves.  STAGES 3
+// keeps two chunks in flight; STAGES 2 (one) fits two workgroups per compute
+// unit at 128 columns.
+template <int BN, bool ROWPERM>
+constexpr int f64_stages() {
+    return (BN == 128 && !ROWPERM) ? 2 : 3;
+}
+template <int BM, int BN, bool ROWPERM>
+constexpr int f64_lds_bytes() {
+    return f64_stages<BN, ROWPERM>() * (BM + BN) * kBK * 8;
+}
+
+template <int BM, int BN, int WAVES_M, int WAVES_N, int NT, bool ROWPERM>
+__device__ __forceinline__ void product_loop_f64_dma(
+    const Seg *__restrict__ segs, int sb, int se, int m0, const double *__restrict__ store, double *buf0,
+    double *buf1, double *buf2, double *buf3, int64_t ldq, int64_t n0, char *lds,
+    d4_t (&acc)[Tile<BM, BN, WAVES_M, WAVES_N>::FM][Tile<BM, BN, WAVES_M, WAVES_N>::FN]) {
+    constexpr int WM = Tile<BM, BN, WAVES_M, WAVES_N>::WM, WN = Tile<BM, BN, WAVES_M, WAVES_N>::WN;
+    constexpr int FM = WM / 16, FN = WN / 16;
+    constexpr int STAGES = f64_stages<BN, ROWPERM>();
+    constexpr int kStage = (BM + BN) * kBK * 8;
+    constexpr int A_BLOCKS = BM / 8;             // 1 KB blocks (64 slots of 2 values) of A
+    constexpr int BLOCKS = (BM + BN) / 8;        // A then B
+    constexpr int PER_WAVE = (BLOCKS + 7) / 8;   // loads per wave and chunk
+    // slot permutation of odd rows (see above), where a row is an even number
+    // of 128-byte halves and a wave's fragments along it are an even number
+    // (so that a fragment's half is known at compile time); else none
+    constexpr int SWA = ((BM / 16) % 2 == 0 && FM % 2 == 0) ? 8 : 0;
+    constexpr int SWB = ((BN / 16) % 2 == 0 && FN % 2 == 0) ? 8 : 0;
+    static_assert(NT == 512, "8 waves fill a stage");
+    static_assert(FM >= 1 && FN >= 1 && WM % 16 == 0 && WN % 16 == 0, "bad tile");
+    static_assert(BLOCKS * 1024 == kStage, "stage size");
+
+    int tid = threadIdx.x;  // opaque, see store_tile
+    asm volatile("" : "+v"(tid));
+    const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const bool computes = WAVES_M * WAVES_N == NT / 64 || wave < WAVES_M * WAVES_N;  // all waves: known at compile time
+    const int wm = wave / WAVES_N, wn = wave % WAVES_N;
+    const int arow = ROWPERM ? 4 * (lane & 3) + ((lane >> 2) & 3) : (lane & 15);
+    auto bufp = [&](int b) { return b == 0 ? buf0 : b == 1 ? buf1 : b == 2 ? buf2 : buf3; };
+
+    // Chunk at contraction row kk of segment sg into stage st.  Slot t =
+    // 64 q + lane of block q is (row kr, value pair p) of A or of B; B rows
+    // past K re-load row K - 1 (multiplied by zero rows of A).
+    auto issue = [&](int st, const Seg &sg, int kk) {
+        const double *A = store + sg.a_off + m0 + (int64_t)kk * sg.lda;
+        const double *Bp = bufp(sg.b_buf) + sg.b_row * ldq + n0;
+        char *stage = lds + st * kStage;
+#pragma unroll
+        for (int u = 0; u < PER_WAVE; u++) {
+            const int q = min(u * 8 + wave, BLOCKS - 1);  // wave-uniform
+            const double *src;
+            if (q < A_BLOCKS) {
+                const int t = q * 64 + lane, kr = t / (BM / 2), pr = (t % (BM / 2)) ^ ((kr & 1) ? SWA : 0);
+                src = A + (int64_t)kr * sg.lda + 2 * pr;
+            } else {
+                const int t = (q - A_BLOCKS) * 64 + lane, kr = t / (BN / 2), pr = (t % (BN / 2)) ^ ((kr & 1) ? SWB : 0);
+                src = Bp + (int64_t)min(kk + kr, sg.K - 1) * ldq + 2 * pr;
+            }
+            load_lds16(src, stage + q * 1024);
+        }
+    };
+    // A lane reads rows kr = ks + lane / 16 (ks % 4 == 0), so its row parity
+    // is fixed.  Fragment i of the wave sits at byte (wm WM + i 16 + arow) 8 of
+    // the row; on a permuted (odd) row its 128-byte half is swapped, which is
+    // +128 bytes for even i and -128 for odd i (wm FM is even).  Two lane
+    // bases, one per parity of i, leave only compile-time offsets.
+    const int odd = (lane >> 4) & 1;
+    const int a_lane = (lane >> 4) * BM * 8 + (wm * WM + arow) * 8, a_sw = (SWA && odd) ? 128 : 0;
+    const int b_lane = (lane >> 4) * BN * 8 + (wn * WN + (lane & 15)) * 8, b_sw = (SWB && odd) ? 128 : 0;
+    const int a_even = a_lane + a_sw, a_odd = a_lane - a_sw, b_even = b_lane + b_sw, b_odd = b_lane - b_sw;
+    auto compute = [&](int st) {
+        const char *sa = lds + st * kStage;
+        const char *sb_ = sa + BM * kBK * 8;
+#pragma unroll
+        for (int ks = 0; ks < kBK; ks += 4) {
+            double af[FM], bf[FN];
+#pragma unroll
+            for (int i = 0; i < FM; i++)
+                af[i] = *reinterpret_cast<const double *>(sa + ks * BM * 8 + ((i & 1) ? a_odd : a_even) + i * 128);
+#pragma unroll
+            for (int j = 0; j < FN; j++)
+                bf[j] = *reinterpret_cast<const double *>(sb_ + ks * BN * 8 + ((j & 1) ? b_odd : b_even) + j * 128);
+#pragma unroll
+            for (int i = 0; i < FM; i++)
+#pragma unroll
+                for (int j = 0; j < FN; j++) acc[i][j] = Mfma<double>::mma(af[i], bf[j], acc[i][j]);
+        }
+    };
+
+    // next chunk to load (see product_loop_bf16x3): chunks of 16 rows over Kpad
+    struct Cursor {
+        int s, kk;
+        Seg sg, nsg;
+    };
+    auto advance = [&](Cursor c) {
+        if (c.s < se) {
+            c.kk += kBK;
+            if (c.kk >= c.sg.Kpad) {
+                c.s++;
+                c.kk = 0;
+                if (c.s < se) {
+                    c.sg = c.nsg;
+                    if (c.s + 1 < se) c.nsg = load_seg_scalar(segs + c.s + 1);
+                }
+            }
+        }
+        c.s = __builtin_amdgcn_readfirstlane(c.s);
+        c.kk = __builtin_amdgcn_readfirstlane(c.kk);
+        return c;
+    };
+
+    if (sb < se) {
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // only this loop's loads in flight
+        Cursor cur;
+        cur.s = sb;
+        cur.kk = 0;
+        cur.sg = load_seg_scalar(segs + sb);
+        cur.nsg = sb + 1 < se ? load_seg_scalar(segs + sb + 1) : cur.sg;
+        issue(0, cur.sg, 0);  // chunk 0
+        cur = advance(cur);   // chunk 1
+        int st = 0;           // stage of chunk c
+        // (the loop test sits at the bottom, after the accumulators' only
+        // update: an exit between the MFMAs and the next iteration made the
+        // register allocator copy every accumulator)
+        if constexpr (STAGES == 3) {
+            bool next_valid = cur.s < se;
+            issue(1, cur.sg, cur.kk);
+            cur = advance(cur);  // chunk c + 2
+            bool more = true;
+            do {
+                wait_vm_barrier<PER_WAVE>();  // chunk c landed; stage of c + 2 free
+                const bool after_valid = cur.s < se;
+                issue(st == 0 ? 2 : st - 1, cur.sg, cur.kk);
+                if (computes) compute(st);
+                more = next_valid;
+                next_valid = after_valid;
+                cur = advance(cur);
+                st = __builtin_amdgcn_readfirstlane(st == 2 ? 0 : st + 1);
+            } while (more);
+        } else {
+            bool more = true;
+            do {
+                wait_vm_barrier<0>();  // chunk c landed; the other stage is free
+                more = cur.s < se;     // chunk c + 1 exists
+                issue(st ^ 1, cur.sg, cur.kk);  // chunk c + 1 (or a repeat)
+                if (computes) compute(st);
+                cur = advance(cur);
+                st = __builtin_amdgcn_readfirstlane(st ^ 1);
+            } while (more);
+        }
+        wait_vm_barrier<0>();  // no load may land in the LDS after the loop
+    }
+}
+
 // LDS of the split-BF16 copy in store_tile: the tile as FP32, column-major
 // with a pitch of BM + 4 values (16-byte accesses without bank conflicts).
 template <int BM, int BN>
@@ -289,7 +491,7 @@ __device__ __forceinline__ void store_tile(const TileJob &task, OUT *buf0, OUT *
     int tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
     const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const bool computes = wave < WAVES_M * WAVES_N;
+    const bool computes = WAVES_M * WAVES_N == 8 || wave < WAVES_M * WAVES_N;  // 8: every wave of the largest workgroup
     const int wm = wave / WAVES_N, wn = wave % WAVES_N;
     constexpr bool kSplitCopy = F32_ROWS && sizeof(OUT) == 8;
     constexpr int kPitch = BM + 4;
@@ -375,7 +577,9 @@ __device__ __forceinline__ void store_tile(const TileJob &task, OUT *buf0, OUT *
 // ROWPERM (FP64): accumulate in the FP32 register layout (see product_loop),
 // as the mixed-precision launch does so that the split copy of the output
 // can be written from consecutive rows.
-template <typename T, int BM, int BN, int WAVES_M, int WAVES_N, int NT, bool ROWPERM = false>
+// DMA (FP64, persistent launch): the direct global-to-LDS loop, with As_ the
+// start of an LDS region of f64_lds_bytes<BM, BN, ROWPERM>() bytes.
+template <typename T, int BM, int BN, int WAVES_M, int WAVES_N, int NT, bool ROWPERM = false, bool DMA = false>
 __device__ __forceinline__ void block_product(const TileJob &task, const Seg *__restrict__ segs,
                                               const T *__restrict__ store, T *buf0, T *buf1,
                                               T *buf2, T *buf3, int64_t ldq, int64_t n0, T *As_,
@@ -386,8 +590,13 @@ __device__ __forceinline__ void block_product(const TileJob &task, const Seg *__
     for (int i = 0; i < TL::FM; i++)
 #pragma unroll
         for (int j = 0; j < TL::FN; j++) acc[i][j] = typename Mfma<T>::acc_t{0, 0, 0, 0};
-    product_loop<T, BM, BN, WAVES_M, WAVES_N, NT, ROWPERM>(segs, task.seg_begin, task.seg_end, task.m0, store,
-                                                           buf0, buf1, buf2, buf3, ldq, n0, As_, Bs_, acc);
+    if constexpr (DMA && sizeof(T) == 8)
+        product_loop_f64_dma<BM, BN, WAVES_M, WAVES_N, NT, ROWPERM>(segs, task.seg_begin, task.seg_end, task.m0,
+                                                                   store, buf0, buf1, buf2, buf3, ldq, n0,
+                                                                   reinterpret_cast<char *>(As_), acc);
+    else
+        product_loop<T, BM, BN, WAVES_M, WAVES_N, NT, ROWPERM>(segs, task.seg_begin, task.seg_end, task.m0, store,
+                                                               buf0, buf1, buf2, buf3, ldq, n0, As_, Bs_, acc);
     store_tile<T, typename Mfma<T>::acc_t, BM, BN, WAVES_M, WAVES_N, ROWPERM || sizeof(T) == 4>(
         task, buf0, buf1, buf2, buf3, ldq, n0, As_, acc);
 }
@@ -437,47 +646,6 @@ constexpr int split_f64_lds_bytes() {
     return a > split_copy_lds_bytes<BM, BN>() ? a : split_copy_lds_bytes<BM, BN>();
 }
 
-// One direct global-to-LDS load: the 64 lanes' 16-byte vectors at src land
-// in 1 KB of LDS from the wave-uniform address lds_addr, lane l at
-// lds_addr + 16 l.  Written as inline asm so that the compiler does not track
-// these LDS writes: it would otherwise wait for every outstanding one before
-// any LDS read, including the reads of the stage already complete; the
-// chunk pipeline below waits for them itself (wait_vm_barrier).
-__device__ __forceinline__ void load_lds16(const void *src, const char *lds_dst) {
-    const uint32_t a = (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) char *)lds_dst;
-    asm volatile("global_load_lds_dwordx4 %0, off" ::"v"(src), "{m0}"(__builtin_amdgcn_readfirstlane(a))
-                 : "memory");
-}
-
-// Segment descriptor through a scalar (constant address space) load: it
-// counts against the scalar counter, so the compiler's wait for it never
-// covers the chunk loads in flight.  The descriptors are read-only during a
-// launch and the address is uniform.
-__device__ __forceinline__ Seg load_seg_scalar(const Seg *p) {
-    const __attribute__((address_space(4))) Seg *g = (const __attribute__((address_space(4))) Seg *)p;
-    Seg s;
-    s.a_off = g->a_off;
-    s.b_row = g->b_row;
-    s.lda = g->lda;
-    s.K = g->K;
-    s.b_buf = g->b_buf;
-    s.Kpad = g->Kpad;
-    s.a_off16 = g->a_off16;
-    s.b_row16 = g->b_row16;
-    return s;
-}
-
-// Waits until at most N of this wave's vector memory operations are
-// outstanding, then joins the workgroup barrier.  No fence: the barrier of
-// __syncthreads() also waits for every outstanding load, which would drain
-// the loads that are meant to stay in flight across it.  The direct
-// global-to-LDS writes of a chunk are complete once the counter covers them.
-template <int N>
-__device__ __forceinline__ void wait_vm_barrier() {
-    static_assert(N >= 0 && N < 64, "vmcnt out of range");
-    asm volatile("s_waitcnt vmcnt(%0)\n\ts_barrier" ::"n"(N) : "memory");
-}
-
 // Accumulates rows [m0, m0 + BM) x columns [n0, n0 + BN) of the split-BF16
 // products of segments [sb, se) into FP32 accumulators (FP32 register
 // layout, frag_row<true>).
@@ -512,7 +680,7 @@ __device__ __forceinline__ void product_loop_bf16x3(
     int tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
     const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const bool computes = wave < WAVES_M * WAVES_N;
+    const bool computes = WAVES_M * WAVES_N == NT / 64 || wave < WAVES_M * WAVES_N;  // all waves: known at compile time
     const int wm = wave / WAVES_N, wn = wave % WAVES_N;
     // the split workspace of a segment's B operand (by its FP64 buffer id)
     auto b16p = [&](int b) { return b == BUF_WT ? w16 : b == BUF_WHAT ? what16 : yhat16; };
@@ -665,7 +833,7 @@ __device__ __forceinline__ void block_product_split_then_f64(const TileJob &task
     float *stage = reinterpret_cast<float *>(lds);
     int tid = threadIdx.x;  // opaque: the LDS addresses are not hoisted out of the task loop
     asm volatile("" : "+v"(tid));
-    const bool computes = __builtin_amdgcn_readfirstlane(tid >> 6) < WAVES_M * WAVES_N;
+    const bool computes = WAVES_M * WAVES_N == NT / 64 || __builtin_amdgcn_readfirstlane(tid >> 6) < WAVES_M * WAVES_N;
     if (computes) {
 #pragma unroll
         for (int i = 0; i < TL::FM; i++)
@@ -685,10 +853,8 @@ __device__ __forceinline__ void block_product_split_then_f64(const TileJob &task
                 acc[i][j][r] = computes ? (double)stage[((i * TL::FN + j) * 4 + r) * NT + tid] : 0.0;
     static_assert(kVals * NT * 4 <= split_f64_lds_bytes<BM, BN>(), "LDS hand-over does not fit");
     __syncthreads();
-    double *As = reinterpret_cast<double *>(lds);
-    double *Bs = As + 2 * kBK * (BM + lds_pad<double>());
-    product_loop<double, BM, BN, WAVES_M, WAVES_N, NT, true>(segs, task.seg_end - 1, task.seg_end, task.m0, store,
-                                                             buf0, buf1, buf2, buf3, ldq, n0, As, Bs, acc);
+    product_loop_f64_dma<BM, BN, WAVES_M, WAVES_N, NT, true>(segs, task.seg_end - 1, task.seg_end, task.m0, store,
+                                                             buf0, buf1, buf2, buf3, ldq, n0, lds, acc);
     store_tile<double, d4_t, BM, BN, WAVES_M, WAVES_N, true>(task, buf0, buf1, buf2, buf3, ldq, n0, lds, acc);
 }
 
@@ -756,7 +922,8 @@ __global__ __launch_bounds__(kPersistThreads, BN <= 128 ? 4 : 1) void k_persiste
     const PTask *__restrict__ tasks, int n_tasks, const int32_t *__restrict__ succ,
     int32_t *counters, int32_t *head, int32_t *err, const MatDesc *__restrict__ mats, void *Y, int64_t ldy,
     int64_t Q, const int64_t *__restrict__ perm) {
-    constexpr int kNative = (2 * kBK * (128 + lds_pad<T>()) + 2 * kBK * (BN + lds_pad<T>())) * (int)sizeof(T);
+    constexpr int kRegs = (2 * kBK * (128 + lds_pad<T>()) + 2 * kBK * (BN + lds_pad<T>())) * (int)sizeof(T);
+    constexpr int kNative = sizeof(T) == 8 ? f64_lds_bytes<128, BN, SPLIT>() : kRegs;
     constexpr int kSplit = (SPLIT && sizeof(T) == 8) ? split_f64_lds_bytes<128, BN>() : 0;
     __shared__ __attribute__((aligned(16))) char lds[kNative > kSplit ? kNative : kSplit];
     T *As = reinterpret_cast<T *>(lds);
@@ -824,21 +991,23 @@ __global__ __launch_bounds__(kPersistThreads, BN <= 128 ? 4 : 1) void k_persiste
             }
         } else if (pt.bm == 128) {
             block_product<T, 128, BN, PLayout<128, BN>::WMv, PLayout<128, BN>::WN, kPersistThreads,
-                          SPLIT && sizeof(T) == 8>(job, segs, store, (T *)md.buf[0], (T *)md.buf[1],
+                          SPLIT && sizeof(T) == 8, sizeof(T) == 8>(job, segs, store, (T *)md.buf[0], (T *)md.buf[1],
                                                    (T *)md.buf[2], (T *)md.buf[3], md.ldq, n0, As, Bs);
         } else if (!fine_tiles(sizeof(T), BN, SPLIT) || pt.bm == 64) {
             block_product<T, 64, BN, PLayout<64, BN>::WMv, PLayout<64, BN>::WN, kPersistThreads,
-                          SPLIT && sizeof(T) == 8>(job, segs, store, (T *)md.buf[0], (T *)md.buf[1],
+                          SPLIT && sizeof(T) == 8, sizeof(T) == 8>(job, segs, store, (T *)md.buf[0], (T *)md.buf[1],
                                                    (T *)md.buf[2], (T *)md.buf[3], md.ldq, n0, As, Bs);
         } else if constexpr (fine_tiles(sizeof(T), BN, SPLIT)) {
             // 32- and 96-row tiles, for output blocks whose row count would
             // waste most of a 64- or 128-row tile
             if (pt.bm == 96)
-                block_product<T, 96, BN, PLayout<96, BN>::WMv, PLayout<96, BN>::WN, kPersistThreads>(
+                block_product<T, 96, BN, PLayout<96, BN>::WMv, PLayout<96, BN>::WN, kPersistThreads, false,
+                              sizeof(T) == 8>(
                     job, segs, store, (T *)md.buf[0], (T *)md.buf[1], (T *)md.buf[2], (T *)md.buf[3],
                     md.ldq, n0, As, Bs);
             else
-                block_product<T, 32, BN, PLayout<32, BN>::WMv, PLayout<32, BN>::WN, kPersistThreads>(
+                block_product<T, 32, BN, PLayout<32, BN>::WMv, PLayout<32, BN>::WN, kPersistThreads, false,
+                              sizeof(T) == 8>(
                     job, segs, store, (T *)md.buf[0], (T *)md.buf[1], (T *)md.buf[2], (T *)md.buf[3],
                     md.ldq, n0, As, Bs);
         }

@@ -165,7 +165,8 @@ class Matrix:
         self.handle = handle
 
     def __del__(self):
-        if getattr(self, "handle", None):
+        # (lib is None only during interpreter shutdown; the process frees all then)
+        if getattr(self, "handle", None) and lib is not None:
             lib.hm_free(self.handle)
             self.handle = None
 
@@ -242,7 +243,8 @@ class Repr:
             setattr(self, k, arr(getattr(v, k), dt, cnt))
 
     def __del__(self):
-        if getattr(self, "handle", None):
+        # (lib is None only during interpreter shutdown; the process frees all then)
+        if getattr(self, "handle", None) and lib is not None:
             lib.hm_repr_free(self.handle)
             self.handle = None
 
@@ -343,7 +345,8 @@ class Batch:
         self.handle, self.mats, self.Q = handle, list(mats), list(Q)
 
     def __del__(self):
-        if getattr(self, "handle", None):
+        # (lib is None only during interpreter shutdown; the process frees all then)
+        if getattr(self, "handle", None) and lib is not None:
             lib.hm_batch_free(self.handle)
             self.handle = None
 
@@ -423,7 +426,8 @@ class Server:
         self.handle, self.dtype, self.mats = handle, dtype, []
 
     def __del__(self):
-        if getattr(self, "handle", None):
+        # (lib is None only during interpreter shutdown; the process frees all then)
+        if getattr(self, "handle", None) and lib is not None:
             lib.hm_server_destroy(self.handle)
             self.handle = None
 
