@@ -85,11 +85,17 @@ def cpu_baseline(w, budget_s: float = 15.0):
     from oracle import oracle as orc
     H = orc.OracleH2.from_workload(w, wl.gen_points(w))
     st = H.stats()
-    probe_q = 4
-    t = time.perf_counter()
-    H.eval(np.ascontiguousarray(wl.gen_w(w, Q=probe_q)))
-    per_col = (time.perf_counter() - t) / probe_q
-    qs = int(max(probe_q, min(w.Q, budget_s / max(per_col, 1e-9))))
+    # two probes fit time = fixed + per_col * columns (the tree walk's fixed
+    # part is large next to a few columns, so one probe overestimates)
+    probe = []
+    for q in (4, 16):
+        Wp = np.ascontiguousarray(wl.gen_w(w, Q=q))
+        t = time.perf_counter()
+        H.eval(Wp)
+        probe.append(time.perf_counter() - t)
+    per_col = max((probe[1] - probe[0]) / 12, 1e-9)
+    fixed = max(probe[0] - 4 * per_col, 0.0)
+    qs = int(max(4, min(w.Q, (budget_s - fixed) / per_col)))
     Ws = np.ascontiguousarray(wl.gen_w(w, Q=qs))
     t = time.perf_counter()
     H.eval(Ws)
