@@ -4,21 +4,25 @@
 // loop, the reduction over the far blocks B, the top-down U loop and the
 // reduction over the near blocks D) is a set of small dense products
 //     out_block (M x Q) = sum_s A_s (M x K_s) * B_s (K_s x Q)
-// with A_s a stored block and B_s a row range of a workspace.  One kernel,
-// k_block_products, runs a whole phase of them: one workgroup per (output
-// block, column tile) accumulates all of its segments in registers and writes
-// its block once (a single writer per output row block, as in the paper's
-// blocking, Section 3.2, so no atomics are needed and results are
+// with A_s a stored block and B_s a row range of a workspace.  The persistent
+// task-graph kernel k_persistent runs all of them in one launch (per-level
+// launches of k_block_products remain as an alternative): one workgroup per
+// (output block, column tile) accumulates all of its segments in registers
+// and writes its block once (a single writer per output row block, as in the
+// paper's blocking, Section 3.2, so no atomics are needed and results are
 // deterministic).
 //
 // Tiling: a BM x BN output tile per workgroup, split over WAVES_M x WAVES_N
 // wave64s, each wave owning (BM/WAVES_M) x (BN/WAVES_N) = FM x FN MFMA
-// 16x16 fragments.  The contraction runs in chunks of BK = 16: A and B chunks
-// are loaded with 16-byte vector loads into registers, written to one of two
-// LDS buffers while the other is consumed by the MFMAs (one barrier per
-// chunk).  Lane mapping of the 16x16x4 MFMAs (checked on the device): lane l
-// supplies A[l%16][l/16] and B[l/16][l%16]; accumulator register r of lane l
-// holds D[4r + l/16][l%16] for FP64 and D[4(l/16) + r][l%16] for FP32.
+// 16x16 fragments.  The contraction runs in chunks of BK = 16 rows (32 for
+// split BF16).  FP64 and split-BF16 tiles of the persistent kernel load their
+// chunks straight into LDS (global_load_lds_dwordx4) with up to three stages
+// (product_loop_f64_dma, product_loop_bf16x3); FP32 tiles and the per-level
+// kernel stage 16-byte loads through registers into one of two LDS buffers
+// (product_loop).  One barrier per chunk.  Lane mapping of the 16x16x4
+// MFMAs (checked on the device): lane l supplies A[l%16][l/16] and
+// B[l/16][l%16]; accumulator register r of lane l holds D[4r + l/16][l%16]
+// for FP64 and D[4(l/16) + r][l%16] for FP32.
 #include <algorithm>
 #include <cstdlib>
 
