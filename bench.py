@@ -378,7 +378,7 @@ def main() -> int:
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
-              "(the path shards by columns of W with no exchange, see the design notes)",
+              "(on several GPUs the path would shard by columns of W, with no exchange between them)",
               file=sys.stderr)
         return 2
 

@@ -3,7 +3,8 @@ oracle's tree walk on the same compressed representation and the same seeded
 W.  Bar: relative Frobenius error <= 1e-10 for the FP64 path (the stated
 target), elementwise within 1e-12 of max|Y| (summation order is the only
 difference); FP32 path within 5e-6 relative (single-precision rounding of
-K~ and W accumulated over the block sums, bounded in the design notes)."""
+K~ and W, 2^-24 each, accumulated in FP32 over contraction lengths up to
+65 536: about sqrt(K) 2^-24 per product, a few 1e-6 at most)."""
 import os
 import sys
 
