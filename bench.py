@@ -57,18 +57,18 @@ def measured_counters(name: str):
             "source": f"profiles/{name}.json (rocprofv3 SQ_VALU_MFMA_BUSY_CYCLES, SQ_INSTS_VALU_MFMA_MOPS_F64)"}
 
 
-def time_variant(hmx, torch, M, w, dtype, steps, warmup):
+def time_variant(hmx, torch, M, w, dtype, steps, warmup, flags=0):
     W = torch.from_numpy(__import__("workloads").gen_w(w)).to("cuda", dtype)
     Y = torch.empty_like(W)
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
-        hmx.hm_eval(M, W, Y, stream=stream)
+        hmx.hm_eval(M, W, Y, flags=flags, stream=stream)
     torch.cuda.synchronize()
     hmx.hm_profile_reset(M)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        hmx.hm_eval(M, W, Y, flags=hmx.HM_PROFILE, stream=stream)
+        hmx.hm_eval(M, W, Y, flags=flags | hmx.HM_PROFILE, stream=stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms, n = hmx.hm_profile_read(M)
@@ -364,6 +364,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-near-from-points", dest="near_from_points", action="store_false",
+                    help="skip the matrix-free near-field variant of the FP64 step")
     ap.add_argument("--mixed-c4-only", dest="mixed_both", action="store_false",
                     help="mixed form: skip the N=65536 workload reported beside the main one")
     ap.add_argument("--form", choices=("plain", "batched", "serving", "mixed"), default="plain",
@@ -450,6 +452,23 @@ def main() -> int:
         ms32, ph32, n32 = time_variant(hmx, torch, M, w, torch.float32, args.steps, args.warmup)
         out["fp32"] = {"ms_per_step": ms32, "value": flops / (ms32 * 1e-3) / 1e9, "unit": "GFLOP/s",
                        "frac_of_fp32_peak": flops / (ms32 * 1e-3) / 1e12 / PEAK_FP32_TFLOPS}
+    if args.near_from_points:
+        # matrix-free near field: the same FP64 step with every near block
+        # computed from the points in the product tiles (stored blocks unread)
+        hmx.hm_set_points(M, X, w.kernel, w.h)
+        msp, php, npp = time_variant(hmx, torch, M, w, torch.float64, args.steps, args.warmup,
+                                     flags=hmx.HM_NEAR_FROM_POINTS)
+        Wd = torch.from_numpy(wl.gen_w(w)).to("cuda", torch.float64)
+        Ys, Yp = torch.empty_like(Wd), torch.empty_like(Wd)
+        hmx.hm_eval(M, Wd, Ys)
+        hmx.hm_eval(M, Wd, Yp, flags=hmx.HM_NEAR_FROM_POINTS)
+        torch.cuda.synchronize()
+        out["near_from_points"] = {
+            "ms_per_step": msp, "value": flops / (msp * 1e-3) / 1e9, "unit": "GFLOP/s",
+            "launch_ms": php[3] / max(npp[3], 1),
+            "near_block_bytes_not_read": info["E_D"] * 8,
+            "rel_diff_vs_stored": float(torch.linalg.norm(Yp - Ys) / torch.linalg.norm(Ys))}
+        del Wd, Ys, Yp
     del M
     if args.calib_copy_mib:
         src = torch.ones(args.calib_copy_mib << 17, dtype=torch.float64, device="cuda")

@@ -1,5 +1,6 @@
 // hm_api.hip -- the extern "C" entry points declared in include/hm.h.
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -179,6 +180,7 @@ hm_status hm_free(hm_matrix h) {
     if (h->d_head) (void)hipFree(h->d_head);
     if (h->d_tasks) (void)hipFree(h->d_tasks);
     if (h->d_segs) (void)hipFree(h->d_segs);
+    if (h->d_pts) (void)hipFree(h->d_pts);
     for (int g = 0; g < 5; g++)
         for (auto &pr : h->prof.pending[g]) {
             (void)hipEventDestroy(pr.first);
@@ -195,7 +197,8 @@ hm_status hm_eval(hm_matrix h, const void *W, int64_t ldw, void *Y, int64_t ldy,
     if (Q == 0) return HM_OK;
     if (!W || !Y) return fail(HM_ERR_INVALID, "hm_eval: W or Y is NULL");
     if (ldw < Q || ldy < Q) return fail(HM_ERR_INVALID, "hm_eval: leading dimension < Q");
-    if (flags & ~(HM_TREE_ORDER | HM_PROFILE)) return fail(HM_ERR_INVALID, "hm_eval: unknown flags");
+    if (flags & ~(HM_TREE_ORDER | HM_PROFILE | HM_NEAR_FROM_POINTS))
+        return fail(HM_ERR_INVALID, "hm_eval: unknown flags");
     if (!((dtype == HM_F64 && prec == HM_PREC_FP64) || (dtype == HM_F32 && prec == HM_PREC_FP32) ||
           (dtype == HM_F64 && prec == HM_PREC_BF16X3)))
         return fail(HM_ERR_INVALID, "hm_eval: dtype and precision do not match");
@@ -209,8 +212,13 @@ hm_status hm_eval(hm_matrix h, const void *W, int64_t ldw, void *Y, int64_t ldy,
     const int es = dtype == HM_F64 ? 8 : 4, slot = dtype == HM_F64 ? 0 : 1;
     const char *sched = std::getenv("HM_SCHED");
     const bool level_sched = sched && std::string(sched) == "level" && !mixed;
+    const bool from_points = (flags & HM_NEAR_FROM_POINTS) != 0;
+    if (from_points && (prec != HM_PREC_FP64 || !h->d_pts || level_sched))
+        return fail(HM_ERR_INVALID, "hm_eval: HM_NEAR_FROM_POINTS needs HM_PREC_FP64, points set with "
+                                    "hm_set_points and the task-graph launch");
     int bn_kind[4] = {0, pick_bn(Q, 1), pick_bn(Q, 2), pick_bn(Q, 3)};
     if (!level_sched) bn_kind[1] = bn_kind[2] = bn_kind[3] = graph_bn(Q, es, mixed, h->task_k);  // one tile for the graph
+    if (from_points && bn_kind[3] == 64) bn_kind[1] = bn_kind[2] = bn_kind[3] = 128;  // see k_persistent
     const int bn_max = std::max({bn_kind[1], bn_kind[2], bn_kind[3]});
     const int64_t Qp = (Q + bn_max - 1) / bn_max * bn_max;  // workspace leading dimension
     {
@@ -236,7 +244,8 @@ hm_status hm_eval(hm_matrix h, const void *W, int64_t ldw, void *Y, int64_t ldy,
         MatDesc md{h->prec[mixed ? HM_PREC_FP64 : prec].blocks, {bufs[0], bufs[1], bufs[2], bufs[3]},
                    Qp, h->d_segs, mixed ? h->store16 : nullptr,
                    {mixed ? h->ws16[BUF_WT] : nullptr, nullptr, mixed ? h->ws16[BUF_WHAT] : nullptr,
-                    mixed ? h->ws16[BUF_YHAT] : nullptr}};
+                    mixed ? h->ws16[BUF_YHAT] : nullptr},
+                   from_points ? h->d_pts : nullptr, h->pts_d, h->pts_kern, h->pts_scale};
         MatDesc &cache = h->mat_cache[slot];
         if (std::memcmp(&md, &cache, sizeof(MatDesc)) != 0 || h->mat_slot != slot) {
             HM_HIP(hipStreamSynchronize(s));
@@ -271,7 +280,7 @@ hm_status hm_eval(hm_matrix h, const void *W, int64_t ldw, void *Y, int64_t ldy,
         // reported as the leaf-pass group; the leaf rows are written straight
         // into Y in the caller's order, so no permute-out follows
         if ((st = mark(3, true)) != HM_OK) return st;
-        HM_HIP(launch_persistent(*plan, es, h->d_mat, h->d_head, grid, s, OutScatter{Y, ldy, Q, perm}));
+        HM_HIP(launch_persistent(*plan, es, h->d_mat, h->d_head, grid, s, OutScatter{Y, ldy, Q, perm, from_points}));
         if ((st = mark(3, false)) != HM_OK) return st;
         return HM_OK;
     } else {
@@ -290,6 +299,37 @@ hm_status hm_eval(hm_matrix h, const void *W, int64_t ldw, void *Y, int64_t ldy,
     if ((st = mark(4, true)) != HM_OK) return st;
     HM_HIP(launch_permute_out(bufs[BUF_YT], Qp, Y, ldy, perm, h->N, Q, es, s));
     if ((st = mark(4, false)) != HM_OK) return st;
+    return HM_OK;
+}
+
+hm_status hm_set_points(hm_matrix h, const double *X, int64_t ldx, int64_t d, int kernel, double h_param) {
+    if (!h || !X) return fail(HM_ERR_INVALID, "hm_set_points: NULL argument");
+    if (d < 1 || d > kMaxPointDim) return fail(HM_ERR_INVALID, "hm_set_points: d must be in [1, 15]");
+    if (ldx < d) return fail(HM_ERR_INVALID, "hm_set_points: ldx < d");
+    if (kernel != 0 && kernel != 1) return fail(HM_ERR_INVALID, "hm_set_points: unknown kernel");
+    if (!(h_param > 0.0) || !std::isfinite(h_param)) return fail(HM_ERR_INVALID, "hm_set_points: h must be > 0");
+    DeviceScope ds(h->device);
+    if (ds.err != hipSuccess) return fail(HM_ERR_DEVICE, "hm_set_points: cannot select the device");
+    // tree order: row t holds the point perm[t]
+    std::vector<int64_t> perm((size_t)h->N);
+    HM_HIP(hipMemcpy(perm.data(), h->d_perm, sizeof(int64_t) * (size_t)h->N, hipMemcpyDeviceToHost));
+    std::vector<double> xt((size_t)h->N * (size_t)d);
+    for (int64_t t = 0; t < h->N; t++)
+        for (int64_t c = 0; c < d; c++) xt[(size_t)(t * d + c)] = X[perm[(size_t)t] * ldx + c];
+    HM_HIP(hipDeviceSynchronize());  // no evaluation may still read the old points
+    if (h->d_pts) {
+        (void)hipFree(h->d_pts);
+        h->d_pts = nullptr;
+    }
+    const hipError_t e = hipMalloc(&h->d_pts, sizeof(double) * xt.size());
+    if (e != hipSuccess) {
+        h->d_pts = nullptr;
+        return fail(e == hipErrorOutOfMemory ? HM_ERR_NOMEM : HM_ERR_DEVICE, "hm_set_points: device allocation");
+    }
+    HM_HIP(hipMemcpy(h->d_pts, xt.data(), sizeof(double) * xt.size(), hipMemcpyHostToDevice));
+    h->pts_d = (int32_t)d;
+    h->pts_kern = kernel;
+    h->pts_scale = kernel == 0 ? 1.0 / (2.0 * h_param * h_param) : 1.0 / h_param;
     return HM_OK;
 }
 

@@ -27,7 +27,7 @@ int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
 // b_row16: the B operand node's first row in its split-BF16 workspace
 Seg seg(int64_t a_off, int64_t b_row, int32_t lda, int32_t K, int32_t buf, int64_t b_row16) {
-    return Seg{a_off, b_row, lda, K, buf, (int32_t)round_up(K, 16), 0, b_row16};
+    return Seg{a_off, b_row, lda, K, buf, (int32_t)round_up(K, 16), 0, b_row16, 0, 0};
 }
 
 struct Block {            // one output block of a phase before tiling
@@ -263,6 +263,7 @@ hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_mat
                 int64_t off = P.alloc(mb, map);
                 P.jobs[2].push_back({r.near_off[e], off, ma, mb, 0, 0, mb, map});
                 b.segs.push_back(seg(off, r.start[bn], map, mb, BUF_WT, w16row[bn]));
+                b.segs.back().near = 1;
                 E_D += (int64_t)ma * mb;
             }
             const int32_t k = r.rank[a];

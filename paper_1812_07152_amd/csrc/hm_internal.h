@@ -35,7 +35,14 @@ struct Seg {
     int32_t Kpad;   // stored contraction rows (multiple of 16)
     int64_t a_off16; // element offset of the block in the split-BF16 store (see k_make_bf16x3)
     int64_t b_row16; // first row of the B operand's node in its split-BF16 workspace (see Split16)
+    int32_t near;    // 1: the A block is the near block K(x_a, x_b) of the job's leaf a and the
+                     //    leaf b whose W rows start at b_row (it can be computed from the points)
+    int32_t pad_;
 };
+
+// Largest point dimension of the near field computed from points (the tile's
+// points sit in LDS beside the pipeline stages).
+constexpr int kMaxPointDim = 15;
 
 // Split-BF16 workspaces of the mixed-precision evaluation: W (tree order),
 // Ŵ and the leaves' Ŷ, each value v stored as hi = bf16(v), lo = bf16(v - hi)
@@ -130,6 +137,11 @@ struct MatDesc {
     const Seg *segs;
     const void *store16;  // split-BF16 store (mixed precision), or null
     void *buf16[4];       // split-BF16 workspaces (mixed precision): [BUF_WT] W, [BUF_WHAT] Ŵ, [BUF_YHAT] Ŷ
+    const double *pts;    // FP64 launch: points in tree order (N x pts_d) to compute the near
+                          // blocks from, or null to read them from the store
+    int32_t pts_d;
+    int32_t kern;         // 0: exp(-r^2 kscale), 1: exp(-r kscale)
+    double kscale;        // 1 / (2 h^2) or 1 / h
 };
 
 // One matrix's permutes in a batched launch.
@@ -220,6 +232,10 @@ struct hm_matrix_s {
     void *ws[2][hm::BUF_COUNT] = {{nullptr}};
     size_t ws_bytes[2][hm::BUF_COUNT] = {{0}};
     hm::ProfileAcc prof;
+    // points for the near field computed on the fly (hm_set_points)
+    double *d_pts = nullptr;               // N x pts_d, tree order
+    int32_t pts_d = 0, pts_kern = 0;
+    double pts_scale = 0;
 };
 
 namespace hm {
@@ -284,6 +300,7 @@ struct OutScatter {
     void *Y = nullptr;
     int64_t ldy = 0, Q = 0;
     const int64_t *perm = nullptr;
+    bool near_from_points = false;  // FP64: the launch that computes the near blocks from points
 };
 // Persistent launch of a plan (init + graph kernel) on stream s.
 hipError_t launch_persistent(const GraphPlan &plan, int elem_bytes, const MatDesc *d_mat,

@@ -115,6 +115,8 @@ __device__ __forceinline__ Seg load_seg_scalar(const Seg *p) {
     s.Kpad = g->Kpad;
     s.a_off16 = g->a_off16;
     s.b_row16 = g->b_row16;
+    s.near = g->near;
+    s.pad_ = 0;
     return s;
 }
 
@@ -320,11 +322,27 @@ constexpr int f64_lds_bytes() {
     return f64_stages<BN, ROWPERM>() * (BM + BN) * kBK * 8;
 }
 
+// Near blocks computed from the points (matrix-free near field): with pts
+// set, a segment flagged near has the A block K(x_a, x_b), a the tile's leaf
+// (points from a_row, m_valid rows in this tile) and b the leaf whose W rows
+// start at the segment's b_row.  xa: LDS for the tile's points (BM x d).
+struct NearGen {
+    const double *pts = nullptr;  // N x d, tree order
+    int d = 0;
+    int kern = 0;                 // 0: exp(-r^2 kscale), 1: exp(-r kscale)
+    double kscale = 0;
+    int64_t a_row = 0;
+    int m_valid = 0;
+    char *xa = nullptr;
+};
+constexpr int kPointLds = 128 * kMaxPointDim * 8;  // the tile's points, BM <= 128
+
 template <int BM, int BN, int WAVES_M, int WAVES_N, int NT, bool ROWPERM>
 __device__ __forceinline__ void product_loop_f64_dma(
     const Seg *__restrict__ segs, int sb, int se, int m0, const double *__restrict__ store, double *buf0,
     double *buf1, double *buf2, double *buf3, int64_t ldq, int64_t n0, char *lds,
-    d4_t (&acc)[Tile<BM, BN, WAVES_M, WAVES_N>::FM][Tile<BM, BN, WAVES_M, WAVES_N>::FN]) {
+    d4_t (&acc)[Tile<BM, BN, WAVES_M, WAVES_N>::FM][Tile<BM, BN, WAVES_M, WAVES_N>::FN],
+    NearGen ng = NearGen()) {
     constexpr int WM = Tile<BM, BN, WAVES_M, WAVES_N>::WM, WN = Tile<BM, BN, WAVES_M, WAVES_N>::WN;
     constexpr int FM = WM / 16, FN = WN / 16;
     constexpr int STAGES = f64_stages<BN, ROWPERM>();
@@ -352,13 +370,19 @@ __device__ __forceinline__ void product_loop_f64_dma(
     // Chunk at contraction row kk of segment sg into stage st.  Slot t =
     // 64 q + lane of block q is (row kr, value pair p) of A or of B; B rows
     // past K re-load row K - 1 (multiplied by zero rows of A).
+    const bool gen = ng.pts != nullptr;
     auto issue = [&](int st, const Seg &sg, int kk) {
         const double *A = store + sg.a_off + m0 + (int64_t)kk * sg.lda;
         const double *Bp = bufp(sg.b_buf) + sg.b_row * ldq + n0;
         char *stage = lds + st * kStage;
+        const bool make_a = gen && sg.near;  // wave-uniform
 #pragma unroll
         for (int u = 0; u < PER_WAVE; u++) {
-            const int q = min(u * 8 + wave, BLOCKS - 1);  // wave-uniform
+            int q = min(u * 8 + wave, BLOCKS - 1);  // wave-uniform
+            // an A block computed below: load a B block in its place (the
+            // bytes its own load writes, to the same place), so that every
+            // wave still issues PER_WAVE loads per chunk
+            if (make_a && q < A_BLOCKS) q = A_BLOCKS + q % (BLOCKS - A_BLOCKS);
             const double *src;
             if (q < A_BLOCKS) {
                 const int t = q * 64 + lane, kr = t / (BM / 2), pr = (t % (BM / 2)) ^ ((kr & 1) ? SWA : 0);
@@ -368,6 +392,42 @@ __device__ __forceinline__ void product_loop_f64_dma(
                 src = Bp + (int64_t)min(kk + kr, sg.K - 1) * ldq + 2 * pr;
             }
             load_lds16(src, stage + q * 1024);
+        }
+        if (make_a) {
+            // A[k][m] = K(x_a[m], x_b[kk + k]) for the 16 rows of the chunk:
+            // wave w takes rows w and w + 8 (x_b through scalar loads), lanes
+            // take m; zero past the segment's K rows and the tile's rows.
+            const __attribute__((address_space(4))) double *P =
+                (const __attribute__((address_space(4))) double *)ng.pts;
+            const double *xa = reinterpret_cast<const double *>(ng.xa);
+#pragma unroll
+            for (int kh = 0; kh < 2; kh++) {
+                const int k = wave + 8 * kh, kg = kk + k;
+                const bool kv = kg < sg.K;
+                double xb[kMaxPointDim];
+#pragma unroll
+                for (int t = 0; t < kMaxPointDim; t++) xb[t] = (kv && t < ng.d) ? P[(sg.b_row + kg) * ng.d + t] : 0.0;
+#pragma unroll
+                for (int j = 0; j < (BM + 63) / 64; j++) {
+                    const int m = lane + 64 * j;
+                    if (BM % 64 == 0 || m < BM) {
+                        double v = 0.0;
+                        if (kv && m < ng.m_valid) {
+                            double r2 = 0.0;
+#pragma unroll
+                            for (int t = 0; t < kMaxPointDim; t++)
+                                if (t < ng.d) {
+                                    const double df = xa[m * ng.d + t] - xb[t];
+                                    r2 += df * df;
+                                }
+                            v = ng.kern == 0 ? exp(-r2 * ng.kscale) : exp(-sqrt(r2) * ng.kscale);
+                        }
+                        *reinterpret_cast<double *>(stage + k * BM * 8 + ((((m >> 1) ^ ((k & 1) ? SWA : 0))) << 4) +
+                                                    ((m & 1) << 3)) = v;
+                    }
+                }
+            }
+            asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");  // written before the barrier that publishes it
         }
     };
     // A lane reads rows kr = ks + lane / 16 (ks % 4 == 0), so its row parity
@@ -421,6 +481,11 @@ __device__ __forceinline__ void product_loop_f64_dma(
     };
 
     if (sb < se) {
+        if (gen) {  // the tile's points (m_valid rows) into LDS before any chunk is made
+            double *xa = reinterpret_cast<double *>(ng.xa);
+            for (int e = tid; e < ng.m_valid * ng.d; e += NT) xa[e] = ng.pts[ng.a_row * ng.d + e];
+            __syncthreads();
+        }
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // only this loop's loads in flight
         Cursor cur;
         cur.s = sb;
@@ -587,17 +652,20 @@ template <typename T, int BM, int BN, int WAVES_M, int WAVES_N, int NT, bool ROW
 __device__ __forceinline__ void block_product(const TileJob &task, const Seg *__restrict__ segs,
                                               const T *__restrict__ store, T *buf0, T *buf1,
                                               T *buf2, T *buf3, int64_t ldq, int64_t n0, T *As_,
-                                              T *Bs_) {
+                                              T *Bs_, NearGen ng = NearGen()) {
     typedef Tile<BM, BN, WAVES_M, WAVES_N> TL;
     typename Mfma<T>::acc_t acc[TL::FM][TL::FN];
 #pragma unroll
     for (int i = 0; i < TL::FM; i++)
 #pragma unroll
         for (int j = 0; j < TL::FN; j++) acc[i][j] = typename Mfma<T>::acc_t{0, 0, 0, 0};
-    if constexpr (DMA && sizeof(T) == 8)
+    if constexpr (DMA && sizeof(T) == 8) {
+        ng.a_row = task.out_row + task.m0;
+        ng.m_valid = min(BM, task.M - task.m0);
         product_loop_f64_dma<BM, BN, WAVES_M, WAVES_N, NT, ROWPERM>(segs, task.seg_begin, task.seg_end, task.m0,
                                                                    store, buf0, buf1, buf2, buf3, ldq, n0,
-                                                                   reinterpret_cast<char *>(As_), acc);
+                                                                   reinterpret_cast<char *>(As_), acc, ng);
+    }
     else
         product_loop<T, BM, BN, WAVES_M, WAVES_N, NT, ROWPERM>(segs, task.seg_begin, task.seg_end, task.m0, store,
                                                                buf0, buf1, buf2, buf3, ldq, n0, As_, Bs_, acc);
@@ -921,7 +989,10 @@ constexpr int kWaitLimit = 1 << 20;  // polls (each followed by a sleep) before 
 // queue order is topological, so every awaited entry was taken earlier by a
 // running workgroup: the launch cannot deadlock and every workgroup exits
 // when the queue is drained.
-template <typename T, int BN, bool SPLIT>
+// GEN: the FP64 launch that computes the near blocks from the points (see
+// NearGen); a separate instantiation, so that the stored-block launch keeps
+// its registers and code.
+template <typename T, int BN, bool SPLIT, bool GEN = false>
 __global__ __launch_bounds__(kPersistThreads, BN <= 128 ? 4 : 1) void k_persistent(
     const PTask *__restrict__ tasks, int n_tasks, const int32_t *__restrict__ succ,
     int32_t *counters, int32_t *head, int32_t *err, const MatDesc *__restrict__ mats, void *Y, int64_t ldy,
@@ -929,7 +1000,12 @@ __global__ __launch_bounds__(kPersistThreads, BN <= 128 ? 4 : 1) void k_persiste
     constexpr int kRegs = (2 * kBK * (128 + lds_pad<T>()) + 2 * kBK * (BN + lds_pad<T>())) * (int)sizeof(T);
     constexpr int kNative = sizeof(T) == 8 ? f64_lds_bytes<128, BN, SPLIT>() : kRegs;
     constexpr int kSplit = (SPLIT && sizeof(T) == 8) ? split_f64_lds_bytes<128, BN>() : 0;
-    __shared__ __attribute__((aligned(16))) char lds[kNative > kSplit ? kNative : kSplit];
+    constexpr int kMain = kNative > kSplit ? kNative : kSplit;
+    // (not at 64 columns, where the points' LDS would cost the second
+    // workgroup per compute unit: hm_eval runs that mode at 128 columns)
+    constexpr bool kGen = GEN;
+    static_assert(!GEN || (sizeof(T) == 8 && !SPLIT && BN != 64), "near blocks from points: FP64 only");
+    __shared__ __attribute__((aligned(16))) char lds[kMain + (kGen ? kPointLds : 0)];
     T *As = reinterpret_cast<T *>(lds);
     T *Bs = As + 2 * kBK * (128 + lds_pad<T>());
     __shared__ int s_t;
@@ -969,6 +1045,16 @@ __global__ __launch_bounds__(kPersistThreads, BN <= 128 ? 4 : 1) void k_persiste
         const int64_t n0 = (int64_t)pt.qtile * BN;
         const T *store = (const T *)md.store;
         const Seg *segs = md.segs;
+        NearGen ng;
+        if constexpr (kGen) {
+            // leaf tiles only (rows of Y in tree order = point rows); null:
+            // the near blocks come from the store
+            ng.pts = pt.out_buf == BUF_YT ? md.pts : nullptr;
+            ng.d = md.pts_d;
+            ng.kern = md.kern;
+            ng.kscale = md.kscale;
+            ng.xa = lds + kMain;
+        }
         int mode = 0;
         if constexpr (SPLIT && sizeof(T) == 8) mode = pt.mode;
         if (mode != 0) {
@@ -996,11 +1082,11 @@ __global__ __launch_bounds__(kPersistThreads, BN <= 128 ? 4 : 1) void k_persiste
         } else if (pt.bm == 128) {
             block_product<T, 128, BN, PLayout<128, BN>::WMv, PLayout<128, BN>::WN, kPersistThreads,
                           SPLIT && sizeof(T) == 8, sizeof(T) == 8>(job, segs, store, (T *)md.buf[0], (T *)md.buf[1],
-                                                   (T *)md.buf[2], (T *)md.buf[3], md.ldq, n0, As, Bs);
+                                                   (T *)md.buf[2], (T *)md.buf[3], md.ldq, n0, As, Bs, ng);
         } else if (!fine_tiles(sizeof(T), BN, SPLIT) || pt.bm == 64) {
             block_product<T, 64, BN, PLayout<64, BN>::WMv, PLayout<64, BN>::WN, kPersistThreads,
                           SPLIT && sizeof(T) == 8, sizeof(T) == 8>(job, segs, store, (T *)md.buf[0], (T *)md.buf[1],
-                                                   (T *)md.buf[2], (T *)md.buf[3], md.ldq, n0, As, Bs);
+                                                   (T *)md.buf[2], (T *)md.buf[3], md.ldq, n0, As, Bs, ng);
         } else if constexpr (fine_tiles(sizeof(T), BN, SPLIT)) {
             // 32- and 96-row tiles, for output blocks whose row count would
             // waste most of a 64- or 128-row tile
@@ -1008,12 +1094,12 @@ __global__ __launch_bounds__(kPersistThreads, BN <= 128 ? 4 : 1) void k_persiste
                 block_product<T, 96, BN, PLayout<96, BN>::WMv, PLayout<96, BN>::WN, kPersistThreads, false,
                               sizeof(T) == 8>(
                     job, segs, store, (T *)md.buf[0], (T *)md.buf[1], (T *)md.buf[2], (T *)md.buf[3],
-                    md.ldq, n0, As, Bs);
+                    md.ldq, n0, As, Bs, ng);
             else
                 block_product<T, 32, BN, PLayout<32, BN>::WMv, PLayout<32, BN>::WN, kPersistThreads, false,
                               sizeof(T) == 8>(
                     job, segs, store, (T *)md.buf[0], (T *)md.buf[1], (T *)md.buf[2], (T *)md.buf[3],
-                    md.ldq, n0, As, Bs);
+                    md.ldq, n0, As, Bs, ng);
         }
         __syncthreads();  // every wave's stores of this task are done
         if (threadIdx.x == 0 && pt.succ_end > pt.succ_begin) {
@@ -1244,6 +1330,15 @@ hipError_t run_persistent(const GraphPlan &plan, const MatDesc *mats, int32_t *h
     const int nt = plan.n_tasks;
     hipLaunchKernelGGL(k_persistent_init, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s,
                        plan.d_tasks, nt, plan.d_counters, head);
+    if constexpr (sizeof(T) == 8 && BN != 64) {
+        if (out.near_from_points) {
+            hipLaunchKernelGGL((k_persistent<T, BN, false, true>), dim3((unsigned)grid), dim3(kPersistThreads), 0,
+                               s, plan.d_tasks, nt, plan.d_succ, plan.d_counters, head, head + 1, mats, out.Y,
+                               out.ldy, out.Q, out.perm);
+            return hipGetLastError();
+        }
+    }
+    if (out.near_from_points) return hipErrorInvalidValue;
     if (sizeof(T) == 8 && plan.mode == 1)
         hipLaunchKernelGGL((k_persistent<T, BN, true>), dim3((unsigned)grid), dim3(kPersistThreads), 0,
                            s, plan.d_tasks, nt, plan.d_succ, plan.d_counters, head, head + 1, mats, out.Y,

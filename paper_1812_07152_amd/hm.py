@@ -18,7 +18,7 @@ HM_OK, HM_ERR_INVALID, HM_ERR_FORMAT, HM_ERR_NOMEM = 0, -1, -2, -3
 HM_ERR_DEVICE, HM_ERR_BUSY, HM_ERR_PENDING, HM_ERR_INTERNAL = -4, -5, -6, -7
 HM_F64, HM_F32 = 0, 1
 HM_PREC_FP64, HM_PREC_FP32, HM_PREC_BF16X3 = 0, 1, 2
-HM_TREE_ORDER, HM_PROFILE = 1, 2
+HM_TREE_ORDER, HM_PROFILE, HM_NEAR_FROM_POINTS = 1, 2, 4
 HM_BATCH_AUTOTUNE, HM_BATCH_NO_GRAPH = 1, 2
 STATUS_NAMES = {0: "HM_OK", -1: "HM_ERR_INVALID", -2: "HM_ERR_FORMAT", -3: "HM_ERR_NOMEM",
                 -4: "HM_ERR_DEVICE", -5: "HM_ERR_BUSY", -6: "HM_ERR_PENDING", -7: "HM_ERR_INTERNAL"}
@@ -103,6 +103,8 @@ def _load():
     L.hm_profile_reset.restype = st
     L.hm_profile_reset.argtypes = [_P]
     L.hm_check.restype = st
+    L.hm_set_points.argtypes = [_P, _P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.c_double]
+    L.hm_set_points.restype = ctypes.c_int
     L.hm_check.argtypes = [_P]
     _PP = ctypes.POINTER(_P)
     _I64P = ctypes.POINTER(ctypes.c_int64)
@@ -331,6 +333,16 @@ def hm_eval(h: Matrix, W, Y, Q: int | None = None, prec: int | None = None, flag
         raise ValueError("hm_eval: tensors narrower than Q")
     _check(lib.hm_eval(h, W.data_ptr(), W.stride(0), Y.data_ptr(), Y.stride(0), Q, dtype, prec,
                        flags, _stream_ptr(stream)))
+
+
+def hm_set_points(h: Matrix, X: np.ndarray, kernel: int, h_param: float) -> None:
+    """Points (N x d, FP64, original order) and kernel (0 Gaussian, 1
+    Laplace-type) for evaluations with HM_NEAR_FROM_POINTS, which compute
+    the near blocks from the points instead of reading them."""
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    if X.ndim != 2 or X.shape[0] != hm_info(h)["N"]:
+        raise ValueError("hm_set_points: X must be N x d")
+    _check(lib.hm_set_points(h, X.ctypes.data, X.shape[1], X.shape[1], int(kernel), float(h_param)))
 
 
 def hm_check(h: Matrix) -> None:
