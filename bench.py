@@ -410,7 +410,8 @@ def main() -> int:
     M = hmx.hm_load_compressed_mem(R, 0, precs)
     t_load = time.perf_counter() - t
     info = hmx.hm_info(M)
-    del R
+    if not args.near_from_points:
+        del R
     flops = info["flops_per_col"] * w.Q
 
     ms64, ph64, n64 = time_variant(hmx, torch, M, w, torch.float64, args.steps, args.warmup)
@@ -468,7 +469,21 @@ def main() -> int:
             "launch_ms": php[3] / max(npp[3], 1),
             "near_block_bytes_not_read": info["E_D"] * 8,
             "rel_diff_vs_stored": float(torch.linalg.norm(Yp - Ys) / torch.linalg.norm(Ys))}
-        del Wd, Ys, Yp
+        # the same matrix loaded without its near blocks: the store's HBM
+        M2 = hmx.hm_load_compressed_mem(R, 0, hmx.precbit(hmx.HM_PREC_FP64) | hmx.HM_LOAD_NO_NEAR_BLOCKS)
+        del R
+        hmx.hm_set_points(M2, X, w.kernel, w.h)
+        ms2, _, _ = time_variant(hmx, torch, M2, w, torch.float64, args.steps, args.warmup,
+                                 flags=hmx.HM_NEAR_FROM_POINTS)
+        Y2 = torch.empty_like(Wd)
+        hmx.hm_eval(M2, Wd, Y2, flags=hmx.HM_NEAR_FROM_POINTS)
+        torch.cuda.synchronize()
+        out["near_from_points"].update({
+            "store_gb_with_near_blocks": info["bytes_fp64"] / 1e9,
+            "store_gb_without_near_blocks": hmx.hm_info(M2)["bytes_fp64"] / 1e9,
+            "ms_per_step_without_near_blocks": ms2,
+            "rel_diff_without_near_blocks": float(torch.linalg.norm(Y2 - Ys) / torch.linalg.norm(Ys))})
+        del M2, Y2, Wd, Ys, Yp
     del M
     if args.calib_copy_mib:
         src = torch.ones(args.calib_copy_mib << 17, dtype=torch.float64, device="cuda")

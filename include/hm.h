@@ -66,6 +66,11 @@ typedef enum { HM_PREC_FP64 = 0, HM_PREC_FP32 = 1, HM_PREC_BF16X3 = 2 } hm_prec;
 
 /* Bit for hm_load_*'s prec_mask: which precisions to keep on the device. */
 #define HM_PRECBIT(p) (1u << (unsigned)(p))
+/* prec_mask bit: leave the near blocks out of the device store (their HBM is
+ * not allocated).  FP64 only (HM_ERR_INVALID with the FP32 or BF16X3 bits);
+ * every hm_eval on the matrix must then pass HM_NEAR_FROM_POINTS (points set
+ * with hm_set_points), and hm_batch_create / hm_server_add reject it. */
+#define HM_LOAD_NO_NEAR_BLOCKS (1u << 8)
 
 /* hm_eval flags */
 #define HM_TREE_ORDER 1u  /* W and Y are already in tree order: skip both permutes */

@@ -115,6 +115,10 @@ hm_status hm_load_compressed(const char *path, int device, unsigned prec_mask, h
     *out = nullptr;
     if (!(prec_mask & (HM_PRECBIT(HM_PREC_FP64) | HM_PRECBIT(HM_PREC_FP32) | HM_PRECBIT(HM_PREC_BF16X3))))
         return fail(HM_ERR_INVALID, "hm_load_compressed: prec_mask selects no precision");
+    if ((prec_mask & HM_LOAD_NO_NEAR_BLOCKS) &&
+        (!(prec_mask & HM_PRECBIT(HM_PREC_FP64)) ||
+         (prec_mask & (HM_PRECBIT(HM_PREC_FP32) | HM_PRECBIT(HM_PREC_BF16X3)))))
+        return fail(HM_ERR_INVALID, "hm_load_compressed: HM_LOAD_NO_NEAR_BLOCKS is for the FP64 store alone");
     HostRepr r;
     hm_status st = read_file(path, r);
     if (st != HM_OK) return st;
@@ -131,6 +135,10 @@ hm_status hm_load_compressed_mem(const hm_host_repr *repr, int device, unsigned 
     if (!repr) return fail(HM_ERR_INVALID, "hm_load_compressed_mem: repr is NULL");
     if (!(prec_mask & (HM_PRECBIT(HM_PREC_FP64) | HM_PRECBIT(HM_PREC_FP32) | HM_PRECBIT(HM_PREC_BF16X3))))
         return fail(HM_ERR_INVALID, "hm_load_compressed_mem: prec_mask selects no precision");
+    if ((prec_mask & HM_LOAD_NO_NEAR_BLOCKS) &&
+        (!(prec_mask & HM_PRECBIT(HM_PREC_FP64)) ||
+         (prec_mask & (HM_PRECBIT(HM_PREC_FP32) | HM_PRECBIT(HM_PREC_BF16X3)))))
+        return fail(HM_ERR_INVALID, "hm_load_compressed_mem: HM_LOAD_NO_NEAR_BLOCKS is for the FP64 store alone");
     HostRepr r;
     hm_status st = from_view(*repr, r);
     if (st != HM_OK) return st;
@@ -213,6 +221,8 @@ hm_status hm_eval(hm_matrix h, const void *W, int64_t ldw, void *Y, int64_t ldy,
     const char *sched = std::getenv("HM_SCHED");
     const bool level_sched = sched && std::string(sched) == "level" && !mixed;
     const bool from_points = (flags & HM_NEAR_FROM_POINTS) != 0;
+    if (!from_points && !h->near_stored)
+        return fail(HM_ERR_INVALID, "hm_eval: the near blocks were not loaded (use HM_NEAR_FROM_POINTS)");
     if (from_points && (prec != HM_PREC_FP64 || !h->d_pts || level_sched))
         return fail(HM_ERR_INVALID, "hm_eval: HM_NEAR_FROM_POINTS needs HM_PREC_FP64, points set with "
                                     "hm_set_points and the task-graph launch");

@@ -164,6 +164,7 @@ hm_status repack_source(const double *host, std::vector<RepackJob> &jobs, double
 
 hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_matrix *out) {
     const int32_t n = r.n_nodes;
+    const bool no_near = (prec_mask & HM_LOAD_NO_NEAR_BLOCKS) != 0;
     auto leaf = [&](int a) { return r.left[a] < 0; };
     std::vector<int64_t> wrow((size_t)n + 1, 0);
     for (int a = 0; a < n; a++) wrow[a + 1] = wrow[a] + r.rank[a];
@@ -260,8 +261,13 @@ hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_mat
             for (int64_t e = r.near_ptr[a]; e < r.near_ptr[a + 1]; e++) {
                 const int32_t bn = r.near_col[e];
                 const int32_t mb = (int32_t)r.size[bn];
-                int64_t off = P.alloc(mb, map);
-                P.jobs[2].push_back({r.near_off[e], off, ma, mb, 0, 0, mb, map});
+                // left out of the store: the segment's A offset is never read
+                // (its evaluations compute the block from the points)
+                int64_t off = 0;
+                if (!no_near) {
+                    off = P.alloc(mb, map);
+                    P.jobs[2].push_back({r.near_off[e], off, ma, mb, 0, 0, mb, map});
+                }
                 b.segs.push_back(seg(off, r.start[bn], map, mb, BUF_WT, w16row[bn]));
                 b.segs.back().near = 1;
                 E_D += (int64_t)ma * mb;
@@ -447,6 +453,7 @@ hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_mat
         }
     } guard{h};
     h->device = device;
+    h->near_stored = !no_near;
     h->N = r.N;
     h->n_nodes = n;
     h->depth = r.depth;

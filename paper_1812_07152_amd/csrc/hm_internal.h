@@ -232,6 +232,7 @@ struct hm_matrix_s {
     void *ws[2][hm::BUF_COUNT] = {{nullptr}};
     size_t ws_bytes[2][hm::BUF_COUNT] = {{0}};
     hm::ProfileAcc prof;
+    bool near_stored = true;               // false: loaded with HM_LOAD_NO_NEAR_BLOCKS
     // points for the near field computed on the fly (hm_set_points)
     double *d_pts = nullptr;               // N x pts_d, tree order
     int32_t pts_d = 0, pts_kern = 0;

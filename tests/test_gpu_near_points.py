@@ -112,3 +112,28 @@ def test_near_from_points_rejects_bad_use(hmx):
     W32 = torch.from_numpy(W).to("cuda", torch.float32)
     with pytest.raises(hmx.HMError):  # FP64 only
         hmx.hm_eval(M, W32, torch.empty_like(W32), flags=hmx.HM_NEAR_FROM_POINTS)
+
+
+def test_load_without_near_blocks(hmx):
+    w, X, H = built("mix8")
+    full = hmx.hm_load_compressed_mem(H, 0)
+    bits = hmx.precbit(hmx.HM_PREC_FP64) | hmx.HM_LOAD_NO_NEAR_BLOCKS
+    M = hmx.hm_load_compressed_mem(H, 0, bits)
+    # the near blocks' device memory is not allocated (each block is stored
+    # padded, so at least 8 E_D bytes are saved)
+    saved = hmx.hm_info(full)["bytes_fp64"] - hmx.hm_info(M)["bytes_fp64"]
+    assert saved >= 8 * H.stats()["E_D"]
+    W = wl.gen_w(w, Q=48, seed=11)
+    with pytest.raises(hmx.HMError):  # the stored near blocks are not there
+        run(hmx, M, W, 0)
+    with pytest.raises(hmx.HMError):  # nor the points yet
+        run(hmx, M, W, hmx.HM_NEAR_FROM_POINTS)
+    hmx.hm_set_points(M, X, w.kernel, w.h)
+    Y = run(hmx, M, W, hmx.HM_NEAR_FROM_POINTS)
+    Yref = H.eval(W)
+    assert rel(Y, Yref) <= 1e-10
+    np.testing.assert_allclose(Y, run(hmx, full, W, 0), rtol=0, atol=1e-13 * np.abs(Yref).max())
+    with pytest.raises(hmx.HMError):  # FP64 store only
+        hmx.hm_load_compressed_mem(H, 0, bits | hmx.precbit(hmx.HM_PREC_FP32))
+    with pytest.raises(hmx.HMError):  # the batched form reads stored blocks
+        hmx.hm_batch_create([M], [16])
