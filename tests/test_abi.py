@@ -78,6 +78,10 @@ def test_missing_file_and_null_arguments():
     out = ctypes.c_void_p()
     assert hm.lib.hm_load_compressed_mem(None, 0, 1, ctypes.byref(out)) == hm.HM_ERR_INVALID
     assert hm.lib.hm_load_compressed(b"x", 0, 0, ctypes.byref(out)) == hm.HM_ERR_INVALID
+    assert hm.lib.hm_set_points(None, None, 3, 3, 0, 1.0) == hm.HM_ERR_INVALID
+    # the near blocks may be left out of the FP64 store only
+    no_near_fp32 = hm.HM_LOAD_NO_NEAR_BLOCKS | hm.precbit(hm.HM_PREC_FP64) | hm.precbit(hm.HM_PREC_FP32)
+    assert hm.lib.hm_load_compressed(b"x", 0, no_near_fp32, ctypes.byref(out)) == hm.HM_ERR_INVALID
 
 
 def test_inconsistent_host_arrays_are_format_errors():
