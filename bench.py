@@ -345,8 +345,11 @@ def bench_mixed(args) -> dict:
     workload beside it.  Split BF16 against the plain FP64 and FP32 paths on
     the same matrix, with its error against the FP64 result."""
     import workloads as wl
-    main_run = _mixed_one(args, wl.C4, "HSS", "exp(-r/h)")
-    also = _mixed_one(args, wl.C2, f"distance tau={wl.C2.tau}", "gaussian") if args.mixed_both else None
+    if args.mixed_c2_only:  # the N = 65536 workload alone (for the profiles of its launch)
+        main_run, also = _mixed_one(args, wl.C2, f"distance tau={wl.C2.tau}", "gaussian"), None
+    else:
+        main_run = _mixed_one(args, wl.C4, "HSS", "exp(-r/h)")
+        also = _mixed_one(args, wl.C2, f"distance tau={wl.C2.tau}", "gaussian") if args.mixed_both else None
     m = main_run["paths"]["bf16x3"]
     return {
         "metric": "mixed-precision K~W GFLOP/s (algorithmic) vs the plain FP64 path",
@@ -368,6 +371,8 @@ def main() -> int:
                     help="skip the matrix-free near-field variant of the FP64 step")
     ap.add_argument("--mixed-c4-only", dest="mixed_both", action="store_false",
                     help="mixed form: skip the N=65536 workload reported beside the main one")
+    ap.add_argument("--mixed-c2-only", action="store_true",
+                    help="mixed form: run the N=65536 workload alone")
     ap.add_argument("--form", choices=("plain", "batched", "serving", "mixed"), default="plain",
                     help="plain: the headline workload; batched: 64 uneven matrices in one launch; "
                          "serving: 8 resident matrices under a request stream")
