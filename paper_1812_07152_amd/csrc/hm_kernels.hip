@@ -393,42 +393,41 @@ __device__ __forceinline__ void product_loop_f64_dma(
             }
             load_lds16(src, stage + q * 1024);
         }
-        if (make_a) {
-            // A[k][m] = K(x_a[m], x_b[kk + k]) for the 16 rows of the chunk:
-            // wave w takes rows w and w + 8 (x_b through scalar loads), lanes
-            // take m; zero past the segment's K rows and the tile's rows.
-            const __attribute__((address_space(4))) double *P =
-                (const __attribute__((address_space(4))) double *)ng.pts;
-            const double *xa = reinterpret_cast<const double *>(ng.xa);
+    };
+    // The A block of a near segment's chunk from the points: A[k][m] =
+    // K(x_a[m], x_b[kk + k]), zero past the segment's K rows and the tile's
+    // rows.  Wave w takes rows w and w + 8 (x_b through scalar loads), lanes
+    // take m: NV values a lane, value v is row kh = v / NJ, column block
+    // j = v % NJ.
+    constexpr int NJ = (BM + 63) / 64, NV = 2 * NJ;
+    auto make_value = [&](int st, const Seg &sg, int kk, int v) {
+        const __attribute__((address_space(4))) double *P =
+            (const __attribute__((address_space(4))) double *)ng.pts;
+        const double *xa = reinterpret_cast<const double *>(ng.xa);
+        const int kh = v / NJ, jb = v % NJ;
+        const int k = wave + 8 * kh, kg = kk + k;
+        const bool kv = kg < sg.K;
+        const int m = lane + 64 * jb;
+        if (BM % 64 == 0 || m < BM) {
+            double val = 0.0;
+            if (kv && m < ng.m_valid) {
+                double r2 = 0.0;
 #pragma unroll
-            for (int kh = 0; kh < 2; kh++) {
-                const int k = wave + 8 * kh, kg = kk + k;
-                const bool kv = kg < sg.K;
-                double xb[kMaxPointDim];
-#pragma unroll
-                for (int t = 0; t < kMaxPointDim; t++) xb[t] = (kv && t < ng.d) ? P[(sg.b_row + kg) * ng.d + t] : 0.0;
-#pragma unroll
-                for (int j = 0; j < (BM + 63) / 64; j++) {
-                    const int m = lane + 64 * j;
-                    if (BM % 64 == 0 || m < BM) {
-                        double v = 0.0;
-                        if (kv && m < ng.m_valid) {
-                            double r2 = 0.0;
-#pragma unroll
-                            for (int t = 0; t < kMaxPointDim; t++)
-                                if (t < ng.d) {
-                                    const double df = xa[m * ng.d + t] - xb[t];
-                                    r2 += df * df;
-                                }
-                            v = ng.kern == 0 ? exp(-r2 * ng.kscale) : exp(-sqrt(r2) * ng.kscale);
-                        }
-                        *reinterpret_cast<double *>(stage + k * BM * 8 + ((((m >> 1) ^ ((k & 1) ? SWA : 0))) << 4) +
-                                                    ((m & 1) << 3)) = v;
+                for (int t = 0; t < kMaxPointDim; t++)
+                    if (t < ng.d) {
+                        const double df = xa[m * ng.d + t] - P[(sg.b_row + kg) * ng.d + t];
+                        r2 += df * df;
                     }
-                }
+                val = ng.kern == 0 ? exp(-r2 * ng.kscale) : exp(-sqrt(r2) * ng.kscale);
             }
-            asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");  // written before the barrier that publishes it
+            *reinterpret_cast<double *>(lds + st * kStage + k * BM * 8 +
+                                        ((((m >> 1) ^ ((k & 1) ? SWA : 0))) << 4) + ((m & 1) << 3)) = val;
         }
+    };
+    auto make_all = [&](int st, const Seg &sg, int kk) {
+#pragma unroll
+        for (int v = 0; v < NV; v++) make_value(st, sg, kk, v);
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");  // written before the barrier that publishes it
     };
     // A lane reads rows kr = ks + lane / 16 (ks % 4 == 0), so its row parity
     // is fixed.  Fragment i of the wave sits at byte (wm WM + i 16 + arow) 8 of
@@ -439,7 +438,10 @@ __device__ __forceinline__ void product_loop_f64_dma(
     const int a_lane = (lane >> 4) * BM * 8 + (wm * WM + arow) * 8, a_sw = (SWA && odd) ? 128 : 0;
     const int b_lane = (lane >> 4) * BN * 8 + (wn * WN + (lane & 15)) * 8, b_sw = (SWB && odd) ? 128 : 0;
     const int a_even = a_lane + a_sw, a_odd = a_lane - a_sw, b_even = b_lane + b_sw, b_odd = b_lane - b_sw;
-    auto compute = [&](int st) {
+    // g: also make the A block of the chunk in stage gst (segment gsg, row
+    // gkk), one value after each MFMA step, so that its VALU work runs while
+    // the other wave of the SIMD keeps the MFMA pipe busy
+    auto compute = [&](int st, bool g, int gst, const Seg &gsg, int gkk) {
         const char *sa = lds + st * kStage;
         const char *sb_ = sa + BM * kBK * 8;
 #pragma unroll
@@ -455,7 +457,19 @@ __device__ __forceinline__ void product_loop_f64_dma(
             for (int i = 0; i < FM; i++)
 #pragma unroll
                 for (int j = 0; j < FN; j++) acc[i][j] = Mfma<double>::mma(af[i], bf[j], acc[i][j]);
+            if (g) {
+#pragma unroll
+                for (int v = 0; v < NV; v++)
+                    if (v % 4 == ks / 4) make_value(gst, gsg, gkk, v);
+            }
         }
+        if (g) asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");  // written before the next barrier
+    };
+    auto compute_and_make = [&](int st, bool g, int gst, const Seg &gsg, int gkk) {
+        if (computes)
+            compute(st, g, gst, gsg, gkk);
+        else if (g)
+            make_all(gst, gsg, gkk);
     };
 
     // next chunk to load (see product_loop_bf16x3): chunks of 16 rows over Kpad
@@ -493,6 +507,7 @@ __device__ __forceinline__ void product_loop_f64_dma(
         cur.sg = load_seg_scalar(segs + sb);
         cur.nsg = sb + 1 < se ? load_seg_scalar(segs + sb + 1) : cur.sg;
         issue(0, cur.sg, 0);  // chunk 0
+        if (gen && cur.sg.near) make_all(0, cur.sg, 0);
         cur = advance(cur);   // chunk 1
         int st = 0;           // stage of chunk c
         // (the loop test sits at the bottom, after the accumulators' only
@@ -501,13 +516,15 @@ __device__ __forceinline__ void product_loop_f64_dma(
         if constexpr (STAGES == 3) {
             bool next_valid = cur.s < se;
             issue(1, cur.sg, cur.kk);
+            if (gen && cur.sg.near) make_all(1, cur.sg, cur.kk);
             cur = advance(cur);  // chunk c + 2
             bool more = true;
             do {
                 wait_vm_barrier<PER_WAVE>();  // chunk c landed; stage of c + 2 free
                 const bool after_valid = cur.s < se;
-                issue(st == 0 ? 2 : st - 1, cur.sg, cur.kk);
-                if (computes) compute(st);
+                const int gst = st == 0 ? 2 : st - 1;
+                issue(gst, cur.sg, cur.kk);
+                compute_and_make(st, gen && cur.sg.near, gst, cur.sg, cur.kk);
                 more = next_valid;
                 next_valid = after_valid;
                 cur = advance(cur);
@@ -519,7 +536,7 @@ __device__ __forceinline__ void product_loop_f64_dma(
                 wait_vm_barrier<0>();  // chunk c landed; the other stage is free
                 more = cur.s < se;     // chunk c + 1 exists
                 issue(st ^ 1, cur.sg, cur.kk);  // chunk c + 1 (or a repeat)
-                if (computes) compute(st);
+                compute_and_make(st, gen && cur.sg.near, st ^ 1, cur.sg, cur.kk);
                 cur = advance(cur);
                 st = __builtin_amdgcn_readfirstlane(st ^ 1);
             } while (more);
