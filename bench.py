@@ -476,6 +476,10 @@ def main() -> int:
             "rel_diff_vs_stored": float(torch.linalg.norm(Yp - Ys) / torch.linalg.norm(Ys))}
         # the same matrix loaded without its near blocks: the store's HBM
         M2 = hmx.hm_load_compressed_mem(R, 0, hmx.precbit(hmx.HM_PREC_FP64) | hmx.HM_LOAD_NO_NEAR_BLOCKS)
+        # and without its near and far blocks (both computed from the points
+        # and the skeletons)
+        M3 = hmx.hm_load_compressed_mem(R, 0, hmx.precbit(hmx.HM_PREC_FP64) | hmx.HM_LOAD_NO_NEAR_BLOCKS
+                                        | hmx.HM_LOAD_NO_FAR_BLOCKS)
         del R
         hmx.hm_set_points(M2, X, w.kernel, w.h)
         ms2, _, _ = time_variant(hmx, torch, M2, w, torch.float64, args.steps, args.warmup,
@@ -488,7 +492,18 @@ def main() -> int:
             "store_gb_without_near_blocks": hmx.hm_info(M2)["bytes_fp64"] / 1e9,
             "ms_per_step_without_near_blocks": ms2,
             "rel_diff_without_near_blocks": float(torch.linalg.norm(Y2 - Ys) / torch.linalg.norm(Ys))})
-        del M2, Y2, Wd, Ys, Yp
+        both = hmx.HM_NEAR_FROM_POINTS | hmx.HM_FAR_FROM_POINTS
+        hmx.hm_set_points(M3, X, w.kernel, w.h)
+        ms3, ph3, n3 = time_variant(hmx, torch, M3, w, torch.float64, args.steps, args.warmup, flags=both)
+        hmx.hm_eval(M3, Wd, Y2, flags=both)
+        torch.cuda.synchronize()
+        out["near_from_points"]["far_too"] = {
+            "ms_per_step": ms3, "value": flops / (ms3 * 1e-3) / 1e9, "unit": "GFLOP/s",
+            "launch_ms": ph3[3] / max(n3[3], 1),
+            "far_block_bytes_not_read": info["E_B"] * 8,
+            "store_gb_without_near_and_far_blocks": hmx.hm_info(M3)["bytes_fp64"] / 1e9,
+            "rel_diff_vs_stored": float(torch.linalg.norm(Y2 - Ys) / torch.linalg.norm(Ys))}
+        del M2, M3, Y2, Wd, Ys, Yp
     del M
     if args.calib_copy_mib:
         src = torch.ones(args.calib_copy_mib << 17, dtype=torch.float64, device="cuda")

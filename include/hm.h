@@ -71,12 +71,19 @@ typedef enum { HM_PREC_FP64 = 0, HM_PREC_FP32 = 1, HM_PREC_BF16X3 = 2 } hm_prec;
  * every hm_eval on the matrix must then pass HM_NEAR_FROM_POINTS (points set
  * with hm_set_points), and hm_batch_create / hm_server_add reject it. */
 #define HM_LOAD_NO_NEAR_BLOCKS (1u << 8)
+/* prec_mask bit: leave the far (coupling) blocks B_ab out of the device store.
+ * FP64 only, as HM_LOAD_NO_NEAR_BLOCKS, and the representation must carry its
+ * skeletons (skel_ptr/skel; HM_ERR_INVALID otherwise); every hm_eval on the
+ * matrix must then pass HM_FAR_FROM_POINTS. */
+#define HM_LOAD_NO_FAR_BLOCKS (1u << 9)
 
 /* hm_eval flags */
 #define HM_TREE_ORDER 1u  /* W and Y are already in tree order: skip both permutes */
 #define HM_PROFILE 2u     /* record HIP events around each phase (see hm_profile_read) */
 #define HM_NEAR_FROM_POINTS 4u /* FP64 only: compute the near blocks from the points set with
                                   hm_set_points instead of reading them from the device store */
+#define HM_FAR_FROM_POINTS 8u  /* FP64 only: compute the far blocks B_ab = K(X[skel_a], X[skel_b])
+                                  from the points and the skeletons instead of reading them */
 
 typedef struct hm_matrix_s *hm_matrix;
 
@@ -153,21 +160,26 @@ hm_status hm_free(hm_matrix h);
 /* Y = K~ W for Q columns on `stream` (a hipStream_t, NULL = null stream).
  * dtype must be HM_F64 with HM_PREC_FP64 or HM_PREC_BF16X3, HM_F32 with HM_PREC_FP32; the
  * precision must have been loaded.  flags: HM_TREE_ORDER, HM_PROFILE, and
- * HM_NEAR_FROM_POINTS (HM_PREC_FP64 with points set by hm_set_points, in the
- * task-graph launch; HM_ERR_INVALID otherwise).  Q = 0 is a valid no-op.  Workspaces grow
+ * HM_NEAR_FROM_POINTS and HM_FAR_FROM_POINTS (HM_PREC_FP64 with points set by
+ * hm_set_points, in the task-graph launch; the far flag also needs the
+ * skeletons loaded with the representation; HM_ERR_INVALID otherwise).  Q = 0 is a valid no-op.  Workspaces grow
  * on demand (the first call at a larger Q allocates).  Calls on the same h
  * must be serialized by the caller (they share workspaces). */
 hm_status hm_eval(hm_matrix h, const void *W, int64_t ldw, void *Y, int64_t ldy, int64_t Q,
                   hm_dtype dtype, hm_prec prec, unsigned flags, void *stream);
 
-/* Matrix-free near field (Section 2.1: a near block is the kernel matrix of
+/* Matrix-free blocks (Section 2.1: a near block is the kernel matrix of
  * two leaves, K(X[I_a], X[I_b])).  Copies the N points (row i at X + i*ldx,
  * d coordinates, FP64, the caller's original point order, host memory) to the
  * device in tree order, with the kernel that the representation was
  * compressed with: kernel 0 is exp(-|x-y|^2 / (2 h^2)), kernel 1 is
  * exp(-|x-y| / h).  An hm_eval with HM_NEAR_FROM_POINTS then evaluates every
  * near block from the points inside its product tiles instead of reading it
- * from the device store; the far field is unchanged.  Requires 1 <= d <= 15,
+ * from the device store.  When the representation was loaded with its
+ * skeletons, the skeleton points are copied too (in the order of the
+ * skeleton rows), and HM_FAR_FROM_POINTS computes every far block B_ab =
+ * K(X[skel_a], X[skel_b]) (Section 2.1: the coupling block of an ID-based H2
+ * matrix is the kernel matrix of the two skeletons) the same way.  Requires 1 <= d <= 15,
  * ldx >= d, h > 0 (HM_ERR_INVALID otherwise).  Calling it again replaces the
  * points; they are freed with the matrix.  The caller may free X on return.
  * The points and kernel are not checked against the compressed blocks: other

@@ -115,13 +115,16 @@ hm_status hm_load_compressed(const char *path, int device, unsigned prec_mask, h
     *out = nullptr;
     if (!(prec_mask & (HM_PRECBIT(HM_PREC_FP64) | HM_PRECBIT(HM_PREC_FP32) | HM_PRECBIT(HM_PREC_BF16X3))))
         return fail(HM_ERR_INVALID, "hm_load_compressed: prec_mask selects no precision");
-    if ((prec_mask & HM_LOAD_NO_NEAR_BLOCKS) &&
+    if ((prec_mask & (HM_LOAD_NO_NEAR_BLOCKS | HM_LOAD_NO_FAR_BLOCKS)) &&
         (!(prec_mask & HM_PRECBIT(HM_PREC_FP64)) ||
          (prec_mask & (HM_PRECBIT(HM_PREC_FP32) | HM_PRECBIT(HM_PREC_BF16X3)))))
-        return fail(HM_ERR_INVALID, "hm_load_compressed: HM_LOAD_NO_NEAR_BLOCKS is for the FP64 store alone");
+        return fail(HM_ERR_INVALID, "hm_load_compressed: HM_LOAD_NO_NEAR_BLOCKS and HM_LOAD_NO_FAR_BLOCKS are for "
+                                    "the FP64 store alone");
     HostRepr r;
     hm_status st = read_file(path, r);
     if (st != HM_OK) return st;
+    if ((prec_mask & HM_LOAD_NO_FAR_BLOCKS) && r.skel_ptr.empty())
+        return fail(HM_ERR_INVALID, "hm_load_compressed: HM_LOAD_NO_FAR_BLOCKS needs the skeletons");
     int count = 0;
     if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count)
         return fail(HM_ERR_INVALID, "hm_load_compressed: no such HIP device");
@@ -135,13 +138,16 @@ hm_status hm_load_compressed_mem(const hm_host_repr *repr, int device, unsigned 
     if (!repr) return fail(HM_ERR_INVALID, "hm_load_compressed_mem: repr is NULL");
     if (!(prec_mask & (HM_PRECBIT(HM_PREC_FP64) | HM_PRECBIT(HM_PREC_FP32) | HM_PRECBIT(HM_PREC_BF16X3))))
         return fail(HM_ERR_INVALID, "hm_load_compressed_mem: prec_mask selects no precision");
-    if ((prec_mask & HM_LOAD_NO_NEAR_BLOCKS) &&
+    if ((prec_mask & (HM_LOAD_NO_NEAR_BLOCKS | HM_LOAD_NO_FAR_BLOCKS)) &&
         (!(prec_mask & HM_PRECBIT(HM_PREC_FP64)) ||
          (prec_mask & (HM_PRECBIT(HM_PREC_FP32) | HM_PRECBIT(HM_PREC_BF16X3)))))
-        return fail(HM_ERR_INVALID, "hm_load_compressed_mem: HM_LOAD_NO_NEAR_BLOCKS is for the FP64 store alone");
+        return fail(HM_ERR_INVALID, "hm_load_compressed_mem: HM_LOAD_NO_NEAR_BLOCKS and HM_LOAD_NO_FAR_BLOCKS are for "
+                                    "the FP64 store alone");
     HostRepr r;
     hm_status st = from_view(*repr, r);
     if (st != HM_OK) return st;
+    if ((prec_mask & HM_LOAD_NO_FAR_BLOCKS) && r.skel_ptr.empty())
+        return fail(HM_ERR_INVALID, "hm_load_compressed_mem: HM_LOAD_NO_FAR_BLOCKS needs the skeletons");
     int count = 0;
     if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count)
         return fail(HM_ERR_INVALID, "hm_load_compressed_mem: no such HIP device");
@@ -189,6 +195,7 @@ hm_status hm_free(hm_matrix h) {
     if (h->d_tasks) (void)hipFree(h->d_tasks);
     if (h->d_segs) (void)hipFree(h->d_segs);
     if (h->d_pts) (void)hipFree(h->d_pts);
+    if (h->d_skel_pts) (void)hipFree(h->d_skel_pts);
     for (int g = 0; g < 5; g++)
         for (auto &pr : h->prof.pending[g]) {
             (void)hipEventDestroy(pr.first);
@@ -205,7 +212,7 @@ hm_status hm_eval(hm_matrix h, const void *W, int64_t ldw, void *Y, int64_t ldy,
     if (Q == 0) return HM_OK;
     if (!W || !Y) return fail(HM_ERR_INVALID, "hm_eval: W or Y is NULL");
     if (ldw < Q || ldy < Q) return fail(HM_ERR_INVALID, "hm_eval: leading dimension < Q");
-    if (flags & ~(HM_TREE_ORDER | HM_PROFILE | HM_NEAR_FROM_POINTS))
+    if (flags & ~(HM_TREE_ORDER | HM_PROFILE | HM_NEAR_FROM_POINTS | HM_FAR_FROM_POINTS))
         return fail(HM_ERR_INVALID, "hm_eval: unknown flags");
     if (!((dtype == HM_F64 && prec == HM_PREC_FP64) || (dtype == HM_F32 && prec == HM_PREC_FP32) ||
           (dtype == HM_F64 && prec == HM_PREC_BF16X3)))
@@ -220,12 +227,18 @@ hm_status hm_eval(hm_matrix h, const void *W, int64_t ldw, void *Y, int64_t ldy,
     const int es = dtype == HM_F64 ? 8 : 4, slot = dtype == HM_F64 ? 0 : 1;
     const char *sched = std::getenv("HM_SCHED");
     const bool level_sched = sched && std::string(sched) == "level" && !mixed;
-    const bool from_points = (flags & HM_NEAR_FROM_POINTS) != 0;
-    if (!from_points && !h->near_stored)
+    const bool near_pts = (flags & HM_NEAR_FROM_POINTS) != 0, far_pts = (flags & HM_FAR_FROM_POINTS) != 0;
+    const bool from_points = near_pts || far_pts;
+    if (!near_pts && !h->near_stored)
         return fail(HM_ERR_INVALID, "hm_eval: the near blocks were not loaded (use HM_NEAR_FROM_POINTS)");
+    if (!far_pts && !h->far_stored)
+        return fail(HM_ERR_INVALID, "hm_eval: the far blocks were not loaded (use HM_FAR_FROM_POINTS)");
     if (from_points && (prec != HM_PREC_FP64 || !h->d_pts || level_sched))
-        return fail(HM_ERR_INVALID, "hm_eval: HM_NEAR_FROM_POINTS needs HM_PREC_FP64, points set with "
-                                    "hm_set_points and the task-graph launch");
+        return fail(HM_ERR_INVALID, "hm_eval: HM_NEAR_FROM_POINTS and HM_FAR_FROM_POINTS need HM_PREC_FP64, "
+                                    "points set with hm_set_points and the task-graph launch");
+    if (far_pts && !h->d_skel_pts)
+        return fail(HM_ERR_INVALID, "hm_eval: HM_FAR_FROM_POINTS needs a representation loaded with its "
+                                    "skeletons");
     int bn_kind[4] = {0, pick_bn(Q, 1), pick_bn(Q, 2), pick_bn(Q, 3)};
     if (!level_sched) bn_kind[1] = bn_kind[2] = bn_kind[3] = graph_bn(Q, es, mixed, h->task_k);  // one tile for the graph
     if (from_points && bn_kind[3] == 64) bn_kind[1] = bn_kind[2] = bn_kind[3] = 128;  // see k_persistent
@@ -255,7 +268,8 @@ hm_status hm_eval(hm_matrix h, const void *W, int64_t ldw, void *Y, int64_t ldy,
                    Qp, h->d_segs, mixed ? h->store16 : nullptr,
                    {mixed ? h->ws16[BUF_WT] : nullptr, nullptr, mixed ? h->ws16[BUF_WHAT] : nullptr,
                     mixed ? h->ws16[BUF_YHAT] : nullptr},
-                   from_points ? h->d_pts : nullptr, h->pts_d, h->pts_kern, h->pts_scale};
+                   near_pts ? h->d_pts : nullptr, far_pts ? h->d_skel_pts : nullptr, h->pts_d, h->pts_kern,
+                   h->pts_scale};
         MatDesc &cache = h->mat_cache[slot];
         if (std::memcmp(&md, &cache, sizeof(MatDesc)) != 0 || h->mat_slot != slot) {
             HM_HIP(hipStreamSynchronize(s));
@@ -337,6 +351,21 @@ hm_status hm_set_points(hm_matrix h, const double *X, int64_t ldx, int64_t d, in
         return fail(e == hipErrorOutOfMemory ? HM_ERR_NOMEM : HM_ERR_DEVICE, "hm_set_points: device allocation");
     }
     HM_HIP(hipMemcpy(h->d_pts, xt.data(), sizeof(double) * xt.size(), hipMemcpyHostToDevice));
+    if (h->d_skel_pts) {
+        (void)hipFree(h->d_skel_pts);
+        h->d_skel_pts = nullptr;
+    }
+    if (!h->skel_row_pt.empty()) {  // skeleton points in Ŵ row order (for HM_FAR_FROM_POINTS)
+        std::vector<double> xs(h->skel_row_pt.size() * (size_t)d);
+        for (size_t t = 0; t < h->skel_row_pt.size(); t++)
+            for (int64_t c = 0; c < d; c++) xs[t * (size_t)d + (size_t)c] = X[h->skel_row_pt[t] * ldx + c];
+        const hipError_t es = hipMalloc(&h->d_skel_pts, sizeof(double) * xs.size());
+        if (es != hipSuccess) {
+            h->d_skel_pts = nullptr;
+            return fail(es == hipErrorOutOfMemory ? HM_ERR_NOMEM : HM_ERR_DEVICE, "hm_set_points: device allocation");
+        }
+        HM_HIP(hipMemcpy(h->d_skel_pts, xs.data(), sizeof(double) * xs.size(), hipMemcpyHostToDevice));
+    }
     h->pts_d = (int32_t)d;
     h->pts_kern = kernel;
     h->pts_scale = kernel == 0 ? 1.0 / (2.0 * h_param * h_param) : 1.0 / h_param;

@@ -181,7 +181,8 @@ hm_status hm_batch_create(int n, const hm_matrix *hs, const int64_t *Q, hm_dtype
         if (!hs[i]) return fail(HM_ERR_INVALID, "hm_batch_create: NULL matrix");
         if (hs[i]->device != hs[0]->device) return fail(HM_ERR_INVALID, "hm_batch_create: matrices on different devices");
         if (!hs[i]->prec[prec].blocks) return fail(HM_ERR_INVALID, "hm_batch_create: precision not loaded for a matrix");
-        if (!hs[i]->near_stored) return fail(HM_ERR_INVALID, "hm_batch_create: a matrix was loaded without its near blocks");
+        if (!hs[i]->near_stored || !hs[i]->far_stored)
+            return fail(HM_ERR_INVALID, "hm_batch_create: a matrix was loaded without its near or far blocks");
         if (Q[i] < 1 || Q[i] > ((int64_t)1 << 24)) return fail(HM_ERR_INVALID, "hm_batch_create: each Q must be in [1, 2^24]");
         maxq = std::max(maxq, Q[i]);
     }

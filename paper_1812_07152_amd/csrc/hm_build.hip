@@ -165,6 +165,9 @@ hm_status repack_source(const double *host, std::vector<RepackJob> &jobs, double
 hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_matrix *out) {
     const int32_t n = r.n_nodes;
     const bool no_near = (prec_mask & HM_LOAD_NO_NEAR_BLOCKS) != 0;
+    const bool no_far = (prec_mask & HM_LOAD_NO_FAR_BLOCKS) != 0;
+    if (no_far && r.skel_ptr.empty())
+        return fail(HM_ERR_INVALID, "HM_LOAD_NO_FAR_BLOCKS needs the skeletons in the representation");
     auto leaf = [&](int a) { return r.left[a] < 0; };
     std::vector<int64_t> wrow((size_t)n + 1, 0);
     for (int a = 0; a < n; a++) wrow[a + 1] = wrow[a] + r.rank[a];
@@ -233,9 +236,14 @@ hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_mat
             for (int64_t e = r.far_ptr[a]; e < r.far_ptr[a + 1]; e++) {
                 const int32_t bn = r.far_col[e], kb = r.rank[bn];
                 if (kb == 0) continue;
-                int64_t off = P.alloc(kb, kap);
-                P.jobs[1].push_back({r.far_off[e], off, ka, kb, 0, 0, kb, kap});
+                // left out of the store as the near blocks are (below)
+                int64_t off = 0;
+                if (!no_far) {
+                    off = P.alloc(kb, kap);
+                    P.jobs[1].push_back({r.far_off[e], off, ka, kb, 0, 0, kb, kap});
+                }
                 b.segs.push_back(seg(off, wrow[bn], kap, kb, BUF_WHAT, h16row[bn]));
+                b.segs.back().from_pts = 2;
                 E_B += (int64_t)ka * kb;
             }
             const int32_t p = r.parent[a];
@@ -269,7 +277,7 @@ hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_mat
                     P.jobs[2].push_back({r.near_off[e], off, ma, mb, 0, 0, mb, map});
                 }
                 b.segs.push_back(seg(off, r.start[bn], map, mb, BUF_WT, w16row[bn]));
-                b.segs.back().near = 1;
+                b.segs.back().from_pts = 1;
                 E_D += (int64_t)ma * mb;
             }
             const int32_t k = r.rank[a];
@@ -454,6 +462,13 @@ hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_mat
     } guard{h};
     h->device = device;
     h->near_stored = !no_near;
+    h->far_stored = !no_far;
+    if (!r.skel_ptr.empty()) {  // original point of each Ŵ row (node a's rows follow its skeleton)
+        h->skel_row_pt.assign((size_t)wrow[n], 0);
+        for (int a = 0; a < n; a++)
+            for (int32_t i = 0; i < r.rank[a]; i++)
+                h->skel_row_pt[(size_t)(wrow[a] + i)] = r.skel[(size_t)(r.skel_ptr[a] + i)];
+    }
     h->N = r.N;
     h->n_nodes = n;
     h->depth = r.depth;

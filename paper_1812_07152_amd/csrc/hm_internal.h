@@ -35,8 +35,12 @@ struct Seg {
     int32_t Kpad;   // stored contraction rows (multiple of 16)
     int64_t a_off16; // element offset of the block in the split-BF16 store (see k_make_bf16x3)
     int64_t b_row16; // first row of the B operand's node in its split-BF16 workspace (see Split16)
-    int32_t near;    // 1: the A block is the near block K(x_a, x_b) of the job's leaf a and the
-                     //    leaf b whose W rows start at b_row (it can be computed from the points)
+    int32_t from_pts; // the A block can be computed from points, A[k][m] = K(x_m, y_k):
+                      //   1: near block of the job's leaf a and the leaf b whose W rows start
+                      //      at b_row (x: a's points, y: b's points, both tree order)
+                      //   2: far block B_ab of the job's node a and node b whose Ŵ rows start
+                      //      at b_row (x: a's skeleton points, y: b's, both in Ŵ row order)
+                      //   0: stored only
     int32_t pad_;
 };
 
@@ -92,6 +96,7 @@ struct HostRepr {
     std::vector<int64_t> perm, start, size, basis_off, far_ptr, far_off, near_ptr, near_off;
     std::vector<int32_t> parent, left, right, level, rank, far_col, near_col;
     std::vector<double> basis, B, D;          // owned values (file loads)
+    std::vector<int64_t> skel_ptr, skel;       // skeleton point indices per node (empty: not given)
     const double *basis_ext = nullptr;         // borrowed values (host-array loads)
     const double *B_ext = nullptr;
     const double *D_ext = nullptr;
@@ -139,6 +144,8 @@ struct MatDesc {
     void *buf16[4];       // split-BF16 workspaces (mixed precision): [BUF_WT] W, [BUF_WHAT] Ŵ, [BUF_YHAT] Ŷ
     const double *pts;    // FP64 launch: points in tree order (N x pts_d) to compute the near
                           // blocks from, or null to read them from the store
+    const double *skel_pts;  // FP64 launch: skeleton points in Ŵ row order (skel_rows x pts_d) to
+                             // compute the far blocks from, or null to read them from the store
     int32_t pts_d;
     int32_t kern;         // 0: exp(-r^2 kscale), 1: exp(-r kscale)
     double kscale;        // 1 / (2 h^2) or 1 / h
@@ -233,8 +240,11 @@ struct hm_matrix_s {
     size_t ws_bytes[2][hm::BUF_COUNT] = {{0}};
     hm::ProfileAcc prof;
     bool near_stored = true;               // false: loaded with HM_LOAD_NO_NEAR_BLOCKS
-    // points for the near field computed on the fly (hm_set_points)
+    bool far_stored = true;                // false: loaded with HM_LOAD_NO_FAR_BLOCKS
+    std::vector<int64_t> skel_row_pt;      // original point index of each Ŵ row (empty: no skeletons)
+    // points for the blocks computed on the fly (hm_set_points)
     double *d_pts = nullptr;               // N x pts_d, tree order
+    double *d_skel_pts = nullptr;          // skel_rows x pts_d, Ŵ row order (with skeletons)
     int32_t pts_d = 0, pts_kern = 0;
     double pts_scale = 0;
 };
@@ -301,7 +311,7 @@ struct OutScatter {
     void *Y = nullptr;
     int64_t ldy = 0, Q = 0;
     const int64_t *perm = nullptr;
-    bool near_from_points = false;  // FP64: the launch that computes the near blocks from points
+    bool from_points = false;  // FP64: the launch that computes near and/or far blocks from points
 };
 // Persistent launch of a plan (init + graph kernel) on stream s.
 hipError_t launch_persistent(const GraphPlan &plan, int elem_bytes, const MatDesc *d_mat,

@@ -115,7 +115,7 @@ __device__ __forceinline__ Seg load_seg_scalar(const Seg *p) {
     s.Kpad = g->Kpad;
     s.a_off16 = g->a_off16;
     s.b_row16 = g->b_row16;
-    s.near = g->near;
+    s.from_pts = g->from_pts;
     s.pad_ = 0;
     return s;
 }
@@ -322,12 +322,16 @@ constexpr int f64_lds_bytes() {
     return f64_stages<BN, ROWPERM>() * (BM + BN) * kBK * 8;
 }
 
-// Near blocks computed from the points (matrix-free near field): with pts
-// set, a segment flagged near has the A block K(x_a, x_b), a the tile's leaf
-// (points from a_row, m_valid rows in this tile) and b the leaf whose W rows
-// start at the segment's b_row.  xa: LDS for the tile's points (BM x d).
+// Blocks computed from points (matrix-free near and far field): with pts
+// set, a segment whose from_pts equals kind has the A block K(x_a, x_b): x_a
+// the points of the tile's rows (pts rows a_row.., m_valid rows in this
+// tile), x_b those of the B operand's rows (pts rows b_row..).  kind 1: a
+// leaf tile's near blocks, pts the points in tree order; kind 2: a down-pass
+// tile's far blocks, pts the skeleton points in Ŵ row order.  xa: LDS for
+// the tile's points (BM x d).
 struct NearGen {
-    const double *pts = nullptr;  // N x d, tree order
+    const double *pts = nullptr;  // rows x d
+    int kind = 0;
     int d = 0;
     int kern = 0;                 // 0: exp(-r^2 kscale), 1: exp(-r kscale)
     double kscale = 0;
@@ -375,7 +379,7 @@ __device__ __forceinline__ void product_loop_f64_dma(
         const double *A = store + sg.a_off + m0 + (int64_t)kk * sg.lda;
         const double *Bp = bufp(sg.b_buf) + sg.b_row * ldq + n0;
         char *stage = lds + st * kStage;
-        const bool make_a = gen && sg.near;  // wave-uniform
+        const bool make_a = gen && sg.from_pts == ng.kind;  // wave-uniform
 #pragma unroll
         for (int u = 0; u < PER_WAVE; u++) {
             int q = min(u * 8 + wave, BLOCKS - 1);  // wave-uniform
@@ -507,7 +511,7 @@ __device__ __forceinline__ void product_loop_f64_dma(
         cur.sg = load_seg_scalar(segs + sb);
         cur.nsg = sb + 1 < se ? load_seg_scalar(segs + sb + 1) : cur.sg;
         issue(0, cur.sg, 0);  // chunk 0
-        if (gen && cur.sg.near) make_all(0, cur.sg, 0);
+        if (gen && cur.sg.from_pts == ng.kind) make_all(0, cur.sg, 0);
         cur = advance(cur);   // chunk 1
         int st = 0;           // stage of chunk c
         // (the loop test sits at the bottom, after the accumulators' only
@@ -516,7 +520,7 @@ __device__ __forceinline__ void product_loop_f64_dma(
         if constexpr (STAGES == 3) {
             bool next_valid = cur.s < se;
             issue(1, cur.sg, cur.kk);
-            if (gen && cur.sg.near) make_all(1, cur.sg, cur.kk);
+            if (gen && cur.sg.from_pts == ng.kind) make_all(1, cur.sg, cur.kk);
             cur = advance(cur);  // chunk c + 2
             bool more = true;
             do {
@@ -524,7 +528,7 @@ __device__ __forceinline__ void product_loop_f64_dma(
                 const bool after_valid = cur.s < se;
                 const int gst = st == 0 ? 2 : st - 1;
                 issue(gst, cur.sg, cur.kk);
-                compute_and_make(st, gen && cur.sg.near, gst, cur.sg, cur.kk);
+                compute_and_make(st, gen && cur.sg.from_pts == ng.kind, gst, cur.sg, cur.kk);
                 more = next_valid;
                 next_valid = after_valid;
                 cur = advance(cur);
@@ -536,7 +540,7 @@ __device__ __forceinline__ void product_loop_f64_dma(
                 wait_vm_barrier<0>();  // chunk c landed; the other stage is free
                 more = cur.s < se;     // chunk c + 1 exists
                 issue(st ^ 1, cur.sg, cur.kk);  // chunk c + 1 (or a repeat)
-                compute_and_make(st, gen && cur.sg.near, st ^ 1, cur.sg, cur.kk);
+                compute_and_make(st, gen && cur.sg.from_pts == ng.kind, st ^ 1, cur.sg, cur.kk);
                 cur = advance(cur);
                 st = __builtin_amdgcn_readfirstlane(st ^ 1);
             } while (more);
@@ -1064,9 +1068,16 @@ __global__ __launch_bounds__(kPersistThreads, BN <= 128 ? 4 : 1) void k_persiste
         const Seg *segs = md.segs;
         NearGen ng;
         if constexpr (kGen) {
-            // leaf tiles only (rows of Y in tree order = point rows); null:
-            // the near blocks come from the store
-            ng.pts = pt.out_buf == BUF_YT ? md.pts : nullptr;
+            // leaf tiles: near blocks (rows of Y in tree order = point rows);
+            // down-pass tiles: far blocks (rows of Ŷ = skeleton point rows);
+            // null: the blocks come from the store
+            if (pt.out_buf == BUF_YT && md.pts) {
+                ng.pts = md.pts;
+                ng.kind = 1;
+            } else if (pt.out_buf == BUF_YHAT && md.skel_pts) {
+                ng.pts = md.skel_pts;
+                ng.kind = 2;
+            }
             ng.d = md.pts_d;
             ng.kern = md.kern;
             ng.kscale = md.kscale;
@@ -1348,14 +1359,14 @@ hipError_t run_persistent(const GraphPlan &plan, const MatDesc *mats, int32_t *h
     hipLaunchKernelGGL(k_persistent_init, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s,
                        plan.d_tasks, nt, plan.d_counters, head);
     if constexpr (sizeof(T) == 8 && BN != 64) {
-        if (out.near_from_points) {
+        if (out.from_points) {
             hipLaunchKernelGGL((k_persistent<T, BN, false, true>), dim3((unsigned)grid), dim3(kPersistThreads), 0,
                                s, plan.d_tasks, nt, plan.d_succ, plan.d_counters, head, head + 1, mats, out.Y,
                                out.ldy, out.Q, out.perm);
             return hipGetLastError();
         }
     }
-    if (out.near_from_points) return hipErrorInvalidValue;
+    if (out.from_points) return hipErrorInvalidValue;
     if (sizeof(T) == 8 && plan.mode == 1)
         hipLaunchKernelGGL((k_persistent<T, BN, true>), dim3((unsigned)grid), dim3(kPersistThreads), 0,
                            s, plan.d_tasks, nt, plan.d_succ, plan.d_counters, head, head + 1, mats, out.Y,

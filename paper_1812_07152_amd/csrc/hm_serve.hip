@@ -287,7 +287,8 @@ hm_status hm_server_add(hm_server S, hm_matrix h, int *mat_id) {
     if (!S || !h || !mat_id) return fail(HM_ERR_INVALID, "hm_server_add: NULL argument");
     if (h->device != S->device) return fail(HM_ERR_INVALID, "hm_server_add: matrix on another device");
     if (!h->prec[S->prec].blocks) return fail(HM_ERR_INVALID, "hm_server_add: precision not loaded");
-    if (!h->near_stored) return fail(HM_ERR_INVALID, "hm_server_add: matrix loaded without its near blocks");
+    if (!h->near_stored || !h->far_stored)
+        return fail(HM_ERR_INVALID, "hm_server_add: matrix loaded without its near or far blocks");
     std::lock_guard<std::mutex> g(S->mu);
     if (!S->inflight.empty()) return fail(HM_ERR_BUSY, "hm_server_add: add matrices before submitting work");
     int prev = 0;

@@ -105,6 +105,10 @@ hm_status read_file(const char *path, HostRepr &r) {
     r.basis_len = basis_len;
     r.B_len = B_len;
     r.D_len = D_len;
+    if (skel_len > 0) {  // a file without skeletons stores skel_len 0
+        r.skel_ptr = std::move(skel_ptr);
+        r.skel = std::move(skel);
+    }
     return validate(r);
 }
 
@@ -141,6 +145,10 @@ hm_status from_view(const hm_host_repr &v, HostRepr &r) {
     r.basis_ext = v.basis; r.basis_len = v.basis_len;
     r.B_ext = v.B; r.B_len = v.B_len;
     r.D_ext = v.D; r.D_len = v.D_len;
+    if (v.skel_ptr && v.skel && v.skel_len > 0) {  // optional
+        r.skel_ptr.assign(v.skel_ptr, v.skel_ptr + n + 1);
+        r.skel.assign(v.skel, v.skel + v.skel_len);
+    }
     return validate(r);
 }
 
@@ -223,6 +231,16 @@ hm_status validate(const HostRepr &r) {
             if (r.near_off[e] < 0 || r.near_off[e] > r.D_len - len)
                 return fail(HM_ERR_FORMAT, "D offset out of range");
         }
+    }
+    if (!r.skel_ptr.empty()) {  // optional skeletons: k_a original point indices per node
+        if ((int64_t)r.skel_ptr.size() != n + 1 || r.skel_ptr[0] != 0 ||
+            r.skel_ptr[n] != (int64_t)r.skel.size())
+            return fail(HM_ERR_FORMAT, "skeleton pointers are inconsistent");
+        for (int64_t a = 0; a < n; a++)
+            if (r.skel_ptr[a + 1] - r.skel_ptr[a] != r.rank[a])
+                return fail(HM_ERR_FORMAT, "a node's skeleton size differs from its rank");
+        for (int64_t p : r.skel)
+            if (p < 0 || p >= N) return fail(HM_ERR_FORMAT, "skeleton index out of range");
     }
     return HM_OK;
 }

@@ -18,8 +18,8 @@ HM_OK, HM_ERR_INVALID, HM_ERR_FORMAT, HM_ERR_NOMEM = 0, -1, -2, -3
 HM_ERR_DEVICE, HM_ERR_BUSY, HM_ERR_PENDING, HM_ERR_INTERNAL = -4, -5, -6, -7
 HM_F64, HM_F32 = 0, 1
 HM_PREC_FP64, HM_PREC_FP32, HM_PREC_BF16X3 = 0, 1, 2
-HM_TREE_ORDER, HM_PROFILE, HM_NEAR_FROM_POINTS = 1, 2, 4
-HM_LOAD_NO_NEAR_BLOCKS = 1 << 8
+HM_TREE_ORDER, HM_PROFILE, HM_NEAR_FROM_POINTS, HM_FAR_FROM_POINTS = 1, 2, 4, 8
+HM_LOAD_NO_NEAR_BLOCKS, HM_LOAD_NO_FAR_BLOCKS = 1 << 8, 1 << 9
 HM_BATCH_AUTOTUNE, HM_BATCH_NO_GRAPH = 1, 2
 STATUS_NAMES = {0: "HM_OK", -1: "HM_ERR_INVALID", -2: "HM_ERR_FORMAT", -3: "HM_ERR_NOMEM",
                 -4: "HM_ERR_DEVICE", -5: "HM_ERR_BUSY", -6: "HM_ERR_PENDING", -7: "HM_ERR_INTERNAL"}
@@ -190,10 +190,11 @@ _I32 = ("parent", "left", "right", "level", "rank", "far_col", "near_col")
 _F64 = ("basis", "B", "D")
 
 
-def host_repr(src) -> tuple[hm_host_repr, list]:
+def host_repr(src, skeletons: bool = True) -> tuple[hm_host_repr, list]:
     """Build an hm_host_repr view of an object carrying the representation's
     arrays as attributes (numpy).  Returns the struct and the arrays it points
-    to (keep them alive until the call returns)."""
+    to (keep them alive until the call returns).  The skeletons (skel_ptr,
+    skel) are passed when the object has them and skeletons is true."""
     keep = []
     r = hm_host_repr()
 
@@ -214,8 +215,12 @@ def host_repr(src) -> tuple[hm_host_repr, list]:
     r.depth = int(np.max(src.level))
     r.n_far, r.n_near = len(src.far_col), len(src.near_col)
     r.basis_len, r.B_len, r.D_len = len(src.basis), len(src.B), len(src.D)
-    r.skel_len = 0
-    r.skel_ptr = r.skel = None
+    if skeletons and getattr(src, "skel", None) is not None and len(src.skel) > 0:
+        r.skel_ptr, r.skel = arr("skel_ptr", np.int64), arr("skel", np.int64)
+        r.skel_len = len(src.skel)
+    else:
+        r.skel_len = 0
+        r.skel_ptr = r.skel = None
     return r, keep
 
 
@@ -276,12 +281,15 @@ def hm_repr_free(r: Repr) -> None:
         r.handle = None
 
 
-def hm_load_compressed_mem(src, device: int = 0, prec_mask: int = precbit(HM_PREC_FP64)) -> Matrix:
+def hm_load_compressed_mem(src, device: int = 0, prec_mask: int = precbit(HM_PREC_FP64),
+                           skeletons: bool = True) -> Matrix:
+    """Load a representation (an hm_compress result, or an object with its
+    arrays); skeletons=False leaves an object's skeletons out of the view."""
     if isinstance(src, Repr):
         out = _P()
         _check(lib.hm_load_compressed_mem(ctypes.byref(src._view), device, prec_mask, ctypes.byref(out)))
         return Matrix(out.value)
-    r, keep = host_repr(src)
+    r, keep = host_repr(src, skeletons)
     out = _P()
     _check(lib.hm_load_compressed_mem(ctypes.byref(r), device, prec_mask, ctypes.byref(out)))
     del keep
@@ -338,8 +346,9 @@ def hm_eval(h: Matrix, W, Y, Q: int | None = None, prec: int | None = None, flag
 
 def hm_set_points(h: Matrix, X: np.ndarray, kernel: int, h_param: float) -> None:
     """Points (N x d, FP64, original order) and kernel (0 Gaussian, 1
-    Laplace-type) for evaluations with HM_NEAR_FROM_POINTS, which compute
-    the near blocks from the points instead of reading them."""
+    Laplace-type) for evaluations with HM_NEAR_FROM_POINTS or
+    HM_FAR_FROM_POINTS, which compute the near or far blocks from the points
+    instead of reading them."""
     X = np.ascontiguousarray(X, dtype=np.float64)
     if X.ndim != 2 or X.shape[0] != hm_info(h)["N"]:
         raise ValueError("hm_set_points: X must be N x d")

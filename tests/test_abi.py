@@ -82,6 +82,9 @@ def test_missing_file_and_null_arguments():
     # the near blocks may be left out of the FP64 store only
     no_near_fp32 = hm.HM_LOAD_NO_NEAR_BLOCKS | hm.precbit(hm.HM_PREC_FP64) | hm.precbit(hm.HM_PREC_FP32)
     assert hm.lib.hm_load_compressed(b"x", 0, no_near_fp32, ctypes.byref(out)) == hm.HM_ERR_INVALID
+    # so may the far blocks
+    no_far_fp32 = hm.HM_LOAD_NO_FAR_BLOCKS | hm.precbit(hm.HM_PREC_FP64) | hm.precbit(hm.HM_PREC_FP32)
+    assert hm.lib.hm_load_compressed(b"x", 0, no_far_fp32, ctypes.byref(out)) == hm.HM_ERR_INVALID
 
 
 def test_inconsistent_host_arrays_are_format_errors():
@@ -116,4 +119,49 @@ def test_inconsistent_host_arrays_are_format_errors():
         rep, keep = hm.host_repr(r)
         out = ctypes.c_void_p()
         st = hm.lib.hm_load_compressed_mem(ctypes.byref(rep), 0, 1, ctypes.byref(out))
+        assert st == hm.HM_ERR_FORMAT, (name, st, hm.hm_last_error())
+
+
+def test_skeletons_are_validated():
+    """Optional skeletons in hm_load_compressed_mem: checked against the ranks
+    and N (format errors), and required by HM_LOAD_NO_FAR_BLOCKS."""
+    from paper_1812_07152_amd import hm
+    w = wl.small("abi3", N=600, d=3, m=40)
+    H = OracleH2.from_workload(w, wl.gen_points(w))
+    assert len(H.skel) > 0
+    fp64 = hm.precbit(hm.HM_PREC_FP64)
+
+    def load(obj, mask, skeletons=True):
+        rep, keep = hm.host_repr(obj, skeletons)
+        out = ctypes.c_void_p()
+        st = hm.lib.hm_load_compressed_mem(ctypes.byref(rep), 0, mask, ctypes.byref(out))
+        del keep
+        return st
+
+    # without the skeletons the far blocks cannot be left out
+    assert load(H, fp64 | hm.HM_LOAD_NO_FAR_BLOCKS, skeletons=False) == hm.HM_ERR_INVALID
+    assert "skeletons" in hm.hm_last_error()
+
+    class R:
+        pass
+
+    def clone():
+        r = R()
+        for k in ("N", "d", "n_nodes", "perm", "start", "size", "parent", "left", "right", "level",
+                  "rank", "basis_off", "basis", "far_ptr", "far_col", "far_off", "B", "near_ptr",
+                  "near_col", "near_off", "D", "skel_ptr", "skel"):
+            v = getattr(H, k)
+            setattr(r, k, v.copy() if isinstance(v, np.ndarray) else v)
+        return r
+
+    a = int(np.argmax(H.rank > 0))
+    mutations = {
+        "skel_oob": lambda r: r.skel.__setitem__(0, r.N),
+        "skel_negative": lambda r: r.skel.__setitem__(len(r.skel) - 1, -1),
+        "skel_size": lambda r: r.skel_ptr.__setitem__(a + 1, r.skel_ptr[a + 1] - 1),
+    }
+    for name, mut in mutations.items():
+        r = clone()
+        mut(r)
+        st = load(r, fp64)
         assert st == hm.HM_ERR_FORMAT, (name, st, hm.hm_last_error())
