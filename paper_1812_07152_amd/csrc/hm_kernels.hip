@@ -328,7 +328,7 @@ constexpr int f64_lds_bytes() {
 // tile), x_b those of the B operand's rows (pts rows b_row..).  kind 1: a
 // leaf tile's near blocks, pts the points in tree order; kind 2: a down-pass
 // tile's far blocks, pts the skeleton points in Ŵ row order.  xa: LDS for
-// the tile's points (BM x d).
+// the tile's points (d x 128, coordinate-major).
 struct NearGen {
     const double *pts = nullptr;  // rows x d
     int kind = 0;
@@ -398,39 +398,58 @@ __device__ __forceinline__ void product_loop_f64_dma(
             load_lds16(src, stage + q * 1024);
         }
     };
-    // The A block of a near segment's chunk from the points: A[k][m] =
+    // The A block of a chunk of a segment made from points: A[k][m] =
     // K(x_a[m], x_b[kk + k]), zero past the segment's K rows and the tile's
     // rows.  Wave w takes rows w and w + 8 (x_b through scalar loads), lanes
     // take m: NV values a lane, value v is row kh = v / NJ, column block
-    // j = v % NJ.
+    // j = v % NJ.  All NV values at once, coordinate by coordinate: the NV
+    // distance sums, then the NV exponentials, are independent chains in one
+    // basic block, so their latencies overlap (one value at a time, with a
+    // branch per coordinate, ran about 20% slower).
     constexpr int NJ = (BM + 63) / 64, NV = 2 * NJ;
-    auto make_value = [&](int st, const Seg &sg, int kk, int v) {
+    auto make_dist = [&](const Seg &sg, int kk, double (&r2)[NV]) {
         const __attribute__((address_space(4))) double *P =
             (const __attribute__((address_space(4))) double *)ng.pts;
         const double *xa = reinterpret_cast<const double *>(ng.xa);
-        const int kh = v / NJ, jb = v % NJ;
-        const int k = wave + 8 * kh, kg = kk + k;
-        const bool kv = kg < sg.K;
-        const int m = lane + 64 * jb;
-        if (BM % 64 == 0 || m < BM) {
-            double val = 0.0;
-            if (kv && m < ng.m_valid) {
-                double r2 = 0.0;
+        const int kg0 = kk + wave, kg1 = kg0 + 8;
+        const bool kv0 = kg0 < sg.K, kv1 = kg1 < sg.K;  // wave-uniform
+        const int64_t r0 = (sg.b_row + kg0) * ng.d, r1 = (sg.b_row + kg1) * ng.d;
 #pragma unroll
-                for (int t = 0; t < kMaxPointDim; t++)
-                    if (t < ng.d) {
-                        const double df = xa[m * ng.d + t] - P[(sg.b_row + kg) * ng.d + t];
-                        r2 += df * df;
-                    }
-                val = ng.kern == 0 ? exp(-r2 * ng.kscale) : exp(-sqrt(r2) * ng.kscale);
+        for (int v = 0; v < NV; v++) r2[v] = 0.0;
+#pragma unroll 4
+        for (int t = 0; t < ng.d; t++) {
+            const double xb0 = kv0 ? P[r0 + t] : 0.0, xb1 = kv1 ? P[r1 + t] : 0.0;
+#pragma unroll
+            for (int v = 0; v < NV; v++) {
+                const double df = xa[t * 128 + lane + 64 * (v % NJ)] - (v / NJ ? xb1 : xb0);
+                r2[v] = fma(df, df, r2[v]);
             }
-            *reinterpret_cast<double *>(lds + st * kStage + k * BM * 8 +
-                                        ((((m >> 1) ^ ((k & 1) ? SWA : 0))) << 4) + ((m & 1) << 3)) = val;
+        }
+    };
+    auto make_store = [&](int st, const Seg &sg, int kk, double (&r2)[NV]) {
+        const int kg0 = kk + wave, kg1 = kg0 + 8;
+        const bool kv0 = kg0 < sg.K, kv1 = kg1 < sg.K;  // wave-uniform
+        if (ng.kern != 0) {
+#pragma unroll
+            for (int v = 0; v < NV; v++) r2[v] = sqrt(r2[v]);
+        }
+#pragma unroll
+        for (int v = 0; v < NV; v++) r2[v] = exp(-r2[v] * ng.kscale);
+#pragma unroll
+        for (int v = 0; v < NV; v++) {
+            const int kh = v / NJ, k = wave + 8 * kh, m = lane + 64 * (v % NJ);
+            if (BM % 64 == 0 || m < BM) {
+                const bool ok = (kh ? kv1 : kv0) && m < ng.m_valid;
+                *reinterpret_cast<double *>(lds + st * kStage + k * BM * 8 +
+                                            ((((m >> 1) ^ ((k & 1) ? SWA : 0))) << 4) + ((m & 1) << 3)) =
+                    ok ? r2[v] : 0.0;
+            }
         }
     };
     auto make_all = [&](int st, const Seg &sg, int kk) {
-#pragma unroll
-        for (int v = 0; v < NV; v++) make_value(st, sg, kk, v);
+        double r2[NV];
+        make_dist(sg, kk, r2);
+        make_store(st, sg, kk, r2);
         asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");  // written before the barrier that publishes it
     };
     // A lane reads rows kr = ks + lane / 16 (ks % 4 == 0), so its row parity
@@ -443,11 +462,15 @@ __device__ __forceinline__ void product_loop_f64_dma(
     const int b_lane = (lane >> 4) * BN * 8 + (wn * WN + (lane & 15)) * 8, b_sw = (SWB && odd) ? 128 : 0;
     const int a_even = a_lane + a_sw, a_odd = a_lane - a_sw, b_even = b_lane + b_sw, b_odd = b_lane - b_sw;
     // g: also make the A block of the chunk in stage gst (segment gsg, row
-    // gkk), one value after each MFMA step, so that its VALU work runs while
-    // the other wave of the SIMD keeps the MFMA pipe busy
+    // gkk) between MFMA steps, so that its VALU work runs while the other
+    // wave of the SIMD keeps the MFMA pipe busy: the distances after the
+    // first step, the exponentials after the third (after the first, too,
+    // at BN < 256, where carrying the distances over two steps spills)
+    constexpr int kStoreStep = BN >= 256 ? 8 : 0;
     auto compute = [&](int st, bool g, int gst, const Seg &gsg, int gkk) {
         const char *sa = lds + st * kStage;
         const char *sb_ = sa + BM * kBK * 8;
+        double r2g[NV];
 #pragma unroll
         for (int ks = 0; ks < kBK; ks += 4) {
             double af[FM], bf[FN];
@@ -461,11 +484,8 @@ __device__ __forceinline__ void product_loop_f64_dma(
             for (int i = 0; i < FM; i++)
 #pragma unroll
                 for (int j = 0; j < FN; j++) acc[i][j] = Mfma<double>::mma(af[i], bf[j], acc[i][j]);
-            if (g) {
-#pragma unroll
-                for (int v = 0; v < NV; v++)
-                    if (v % 4 == ks / 4) make_value(gst, gsg, gkk, v);
-            }
+            if (g && ks == 0) make_dist(gsg, gkk, r2g);
+            if (g && ks == kStoreStep) make_store(gst, gsg, gkk, r2g);
         }
         if (g) asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");  // written before the next barrier
     };
@@ -499,9 +519,10 @@ __device__ __forceinline__ void product_loop_f64_dma(
     };
 
     if (sb < se) {
-        if (gen) {  // the tile's points (m_valid rows) into LDS before any chunk is made
+        if (gen) {  // the tile's points (m_valid rows) into LDS before any chunk is made,
+                    // coordinate-major (xa[t][m]: the lanes of a wave read consecutive m)
             double *xa = reinterpret_cast<double *>(ng.xa);
-            for (int e = tid; e < ng.m_valid * ng.d; e += NT) xa[e] = ng.pts[ng.a_row * ng.d + e];
+            for (int e = tid; e < ng.m_valid * ng.d; e += NT) xa[(e % ng.d) * 128 + e / ng.d] = ng.pts[ng.a_row * ng.d + e];
             __syncthreads();
         }
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // only this loop's loads in flight
