@@ -179,8 +179,9 @@ hm_status hm_eval(hm_matrix h, const void *W, int64_t ldw, void *Y, int64_t ldy,
  * skeletons, the skeleton points are copied too (in the order of the
  * skeleton rows), and HM_FAR_FROM_POINTS computes every far block B_ab =
  * K(X[skel_a], X[skel_b]) (Section 2.1: the coupling block of an ID-based H2
- * matrix is the kernel matrix of the two skeletons) the same way.  Requires 1 <= d <= 15,
- * ldx >= d, h > 0 (HM_ERR_INVALID otherwise).  Calling it again replaces the
+ * matrix is the kernel matrix of the two skeletons) the same way.  Requires 1 <= d <= 64
+ * (up to 15 the product tiles keep their points in LDS, above they read them
+ * from global memory), ldx >= d, h > 0 (HM_ERR_INVALID otherwise).  Calling it again replaces the
  * points; they are freed with the matrix.  The caller may free X on return.
  * The points and kernel are not checked against the compressed blocks: other
  * points give the near field of other points. */

@@ -328,7 +328,7 @@ hm_status hm_eval(hm_matrix h, const void *W, int64_t ldw, void *Y, int64_t ldy,
 
 hm_status hm_set_points(hm_matrix h, const double *X, int64_t ldx, int64_t d, int kernel, double h_param) {
     if (!h || !X) return fail(HM_ERR_INVALID, "hm_set_points: NULL argument");
-    if (d < 1 || d > kMaxPointDim) return fail(HM_ERR_INVALID, "hm_set_points: d must be in [1, 15]");
+    if (d < 1 || d > kMaxPointDimAny) return fail(HM_ERR_INVALID, "hm_set_points: d must be in [1, 64]");
     if (ldx < d) return fail(HM_ERR_INVALID, "hm_set_points: ldx < d");
     if (kernel != 0 && kernel != 1) return fail(HM_ERR_INVALID, "hm_set_points: unknown kernel");
     if (!(h_param > 0.0) || !std::isfinite(h_param)) return fail(HM_ERR_INVALID, "hm_set_points: h must be > 0");

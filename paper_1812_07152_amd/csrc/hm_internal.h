@@ -47,6 +47,9 @@ struct Seg {
 // Largest point dimension of the near field computed from points (the tile's
 // points sit in LDS beside the pipeline stages).
 constexpr int kMaxPointDim = 15;
+// Largest point dimension of blocks computed from points at all (above
+// kMaxPointDim the lanes read the tile's points from global memory).
+constexpr int kMaxPointDimAny = 64;
 
 // Split-BF16 workspaces of the mixed-precision evaluation: W (tree order),
 // Ŵ and the leaves' Ŷ, each value v stored as hi = bf16(v), lo = bf16(v - hi)

@@ -328,7 +328,7 @@ constexpr int f64_lds_bytes() {
 // tile), x_b those of the B operand's rows (pts rows b_row..).  kind 1: a
 // leaf tile's near blocks, pts the points in tree order; kind 2: a down-pass
 // tile's far blocks, pts the skeleton points in Ŵ row order.  xa: LDS for
-// the tile's points (d x 128, coordinate-major).
+// the tile's points (d x 128, coordinate-major), used when d <= kMaxPointDim.
 struct NearGen {
     const double *pts = nullptr;  // rows x d
     int kind = 0;
@@ -416,13 +416,29 @@ __device__ __forceinline__ void product_loop_f64_dma(
         const int64_t r0 = (sg.b_row + kg0) * ng.d, r1 = (sg.b_row + kg1) * ng.d;
 #pragma unroll
         for (int v = 0; v < NV; v++) r2[v] = 0.0;
+        if (ng.d <= kMaxPointDim) {
 #pragma unroll 4
-        for (int t = 0; t < ng.d; t++) {
-            const double xb0 = kv0 ? P[r0 + t] : 0.0, xb1 = kv1 ? P[r1 + t] : 0.0;
+            for (int t = 0; t < ng.d; t++) {
+                const double xb0 = kv0 ? P[r0 + t] : 0.0, xb1 = kv1 ? P[r1 + t] : 0.0;
 #pragma unroll
-            for (int v = 0; v < NV; v++) {
-                const double df = xa[t * 128 + lane + 64 * (v % NJ)] - (v / NJ ? xb1 : xb0);
-                r2[v] = fma(df, df, r2[v]);
+                for (int v = 0; v < NV; v++) {
+                    const double df = xa[t * 128 + lane + 64 * (v % NJ)] - (v / NJ ? xb1 : xb0);
+                    r2[v] = fma(df, df, r2[v]);
+                }
+            }
+        } else {  // the tile's points from global memory (rows past m_valid read the last one)
+            const double *xg = ng.pts + ng.a_row * ng.d;  // wave-uniform base
+            int xo[NJ];
+#pragma unroll
+            for (int j = 0; j < NJ; j++) xo[j] = min(lane + 64 * j, ng.m_valid - 1) * ng.d;
+#pragma unroll 1
+            for (int t = 0; t < ng.d; t++) {
+                const double xb0 = kv0 ? P[r0 + t] : 0.0, xb1 = kv1 ? P[r1 + t] : 0.0;
+#pragma unroll
+                for (int v = 0; v < NV; v++) {
+                    const double df = xg[xo[v % NJ] + t] - (v / NJ ? xb1 : xb0);
+                    r2[v] = fma(df, df, r2[v]);
+                }
             }
         }
     };
@@ -519,8 +535,9 @@ __device__ __forceinline__ void product_loop_f64_dma(
     };
 
     if (sb < se) {
-        if (gen) {  // the tile's points (m_valid rows) into LDS before any chunk is made,
-                    // coordinate-major (xa[t][m]: the lanes of a wave read consecutive m)
+        if (gen && ng.d <= kMaxPointDim) {  // the tile's points (m_valid rows) into LDS before any chunk
+                                           // is made, coordinate-major (xa[t][m]: the lanes of a wave
+                                           // read consecutive m)
             double *xa = reinterpret_cast<double *>(ng.xa);
             for (int e = tid; e < ng.m_valid * ng.d; e += NT) xa[(e % ng.d) * 128 + e / ng.d] = ng.pts[ng.a_row * ng.d + e];
             __syncthreads();

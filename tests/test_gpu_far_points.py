@@ -28,6 +28,9 @@ CASES = {
     "deep_small_leaves": wl.small("deep", N=2048, d=3, m=8, Q=4, rmax=8),
     "d15": wl.small("d15", N=1500, d=15, points="normal", m=100, adm=wl.ADM_HSS,
                     kernel=wl.KERNEL_LAPLACE, h=4.0, tol=1e-4, rmax=100, Q=9),
+    # above 15 dimensions the tiles read their points from global memory
+    "d28": wl.small("d28", N=1800, d=28, points="normal", m=100, adm=wl.ADM_HSS,
+                    kernel=wl.KERNEL_LAPLACE, h=4.0, tol=1e-4, rmax=100, Q=11),
 }
 _built = {}
 

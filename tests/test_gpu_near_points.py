@@ -28,6 +28,9 @@ CASES = {
     "deep_small_leaves": wl.small("deep", N=2048, d=3, m=8, Q=4, rmax=8),
     "d15": wl.small("d15", N=1500, d=15, points="normal", m=100, adm=wl.ADM_HSS,
                     kernel=wl.KERNEL_LAPLACE, h=4.0, tol=1e-4, rmax=100, Q=9),
+    # above 15 dimensions the tiles read their points from global memory
+    "d28": wl.small("d28", N=1800, d=28, points="normal", m=100, adm=wl.ADM_HSS,
+                    kernel=wl.KERNEL_LAPLACE, h=4.0, tol=1e-4, rmax=100, Q=11),
 }
 _built = {}
 
@@ -102,8 +105,8 @@ def test_near_from_points_rejects_bad_use(hmx):
     W = wl.gen_w(w)
     with pytest.raises(hmx.HMError):  # no points set
         run(hmx, M, W, hmx.HM_NEAR_FROM_POINTS)
-    with pytest.raises(hmx.HMError):  # d above 15
-        hmx.hm_set_points(M, np.zeros((w.N, 16)), w.kernel, w.h)
+    with pytest.raises(hmx.HMError):  # d above 64
+        hmx.hm_set_points(M, np.zeros((w.N, 65)), w.kernel, w.h)
     with pytest.raises(hmx.HMError):  # unknown kernel
         hmx.hm_set_points(M, X, 7, w.h)
     with pytest.raises(hmx.HMError):  # h <= 0
