@@ -719,8 +719,8 @@ __device__ __forceinline__ void block_product(const TileJob &task, const Seg *__
 #pragma unroll
         for (int j = 0; j < TL::FN; j++) acc[i][j] = typename Mfma<T>::acc_t{0, 0, 0, 0};
     if constexpr (DMA && sizeof(T) == 8) {
-        ng.a_row = task.out_row + task.m0;
-        ng.m_valid = min(BM, task.M - task.m0);
+        ng.a_row = task.out_row;        // the tile's first row (task.m0 is its offset in the block)
+        ng.m_valid = min(BM, task.M);   // the tile's rows
         product_loop_f64_dma<BM, BN, WAVES_M, WAVES_N, NT, ROWPERM>(segs, task.seg_begin, task.seg_end, task.m0,
                                                                    store, buf0, buf1, buf2, buf3, ldq, n0,
                                                                    reinterpret_cast<char *>(As_), acc, ng);

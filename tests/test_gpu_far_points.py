@@ -31,6 +31,12 @@ CASES = {
     # above 15 dimensions the tiles read their points from global memory
     "d28": wl.small("d28", N=1800, d=28, points="normal", m=100, adm=wl.ADM_HSS,
                     kernel=wl.KERNEL_LAPLACE, h=4.0, tol=1e-4, rmax=100, Q=11),
+    # leaves of up to 188 points and ranks up to 200: blocks taller than one
+    # 128-row tile, whose second tile starts at row 128 of the block
+    "tall_tiles": wl.small("tall", N=3000, d=3, m=256, adm=wl.ADM_HSS, kernel=wl.KERNEL_LAPLACE,
+                           h=1.0, tol=1e-10, rmax=200, Q=5),
+    "tall_tiles_d28": wl.small("tall28", N=3000, d=28, points="normal", m=256, adm=wl.ADM_HSS,
+                               kernel=wl.KERNEL_LAPLACE, h=4.0, tol=1e-8, rmax=200, Q=5),
 }
 _built = {}
 
