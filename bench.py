@@ -338,6 +338,57 @@ def _mixed_one(args, w, adm_name: str, kernel_name: str) -> dict:
     }
 
 
+def bench_points(args) -> dict:
+    """Blocks computed from the points (FP64): the N = 65536, d = 8, Q = 256
+    workload (reported) and the N = 262144, d = 28, Q = 1024 HSS one beside it,
+    each timed with stored blocks and with the near and far blocks computed
+    from the points and skeletons on a store loaded without them."""
+    import torch
+
+    import paper_1812_07152_amd as hmx
+    import workloads as wl
+
+    both = hmx.HM_NEAR_FROM_POINTS | hmx.HM_FAR_FROM_POINTS
+    fp64 = hmx.precbit(hmx.HM_PREC_FP64)
+    runs = {}
+    for w in (wl.C2, wl.C4):
+        X = wl.gen_points(w)
+        R = hmx.hm_compress(X, kernel=w.kernel, h=w.h, leaf_size=w.m, tol=w.tol, max_rank=w.rmax,
+                            admissibility=w.adm, tau=w.tau, sample_rows=w.sample_rows, seed=w.sample_seed)
+        M = hmx.hm_load_compressed_mem(R, 0, fp64)
+        Mp = hmx.hm_load_compressed_mem(R, 0, fp64 | hmx.HM_LOAD_NO_NEAR_BLOCKS | hmx.HM_LOAD_NO_FAR_BLOCKS)
+        del R
+        hmx.hm_set_points(Mp, X, w.kernel, w.h)
+        info = hmx.hm_info(M)
+        flops = info["flops_per_col"] * w.Q
+        ms0, _, _ = time_variant(hmx, torch, M, w, torch.float64, args.steps, args.warmup)
+        msp, php, npp = time_variant(hmx, torch, Mp, w, torch.float64, args.steps, args.warmup, flags=both)
+        Wd = torch.from_numpy(wl.gen_w(w)).to("cuda", torch.float64)
+        Ys, Yp = torch.empty_like(Wd), torch.empty_like(Wd)
+        hmx.hm_eval(M, Wd, Ys)
+        hmx.hm_eval(Mp, Wd, Yp, flags=both)
+        torch.cuda.synchronize()
+        runs[w.name] = {
+            "N": w.N, "d": w.d, "Q": w.Q, "ms_stored": ms0, "ms_from_points": msp,
+            "launch_ms_from_points": php[3] / max(npp[3], 1),
+            "gflops_from_points": flops / (msp * 1e-3) / 1e9,
+            "store_gb": info["bytes_fp64"] / 1e9, "store_gb_without_near_and_far": hmx.hm_info(Mp)["bytes_fp64"] / 1e9,
+            "rel_diff_vs_stored": float(torch.linalg.norm(Yp - Ys) / torch.linalg.norm(Ys))}
+        print(f"[points] {w.name}: stored {ms0:.2f} ms, from points {msp:.2f} ms", file=sys.stderr, flush=True)
+        del M, Mp, Wd, Ys, Yp
+    main = runs[wl.C2.name]
+    return {
+        "metric": "K~W GFLOP/s (algorithmic), near and far blocks computed from the points",
+        "value": main["gflops_from_points"], "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": main["ms_from_points"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded points and normal W; no dataset)",
+        "config": {"workload": wl.C2.name, "flags": "HM_NEAR_FROM_POINTS|HM_FAR_FROM_POINTS",
+                   "load": "HM_LOAD_NO_NEAR_BLOCKS|HM_LOAD_NO_FAR_BLOCKS"},
+        "runs": runs,
+    }
+
+
 def bench_mixed(args) -> dict:
     """Mixed-precision form: N = 262144 points in d = 28 (i.i.d. normal),
     kernel exp(-r/4), leaf 256, tol 1e-4, rank <= 256, HSS, W: N x 1024 FP64
@@ -373,9 +424,10 @@ def main() -> int:
                     help="mixed form: skip the N=65536 workload reported beside the main one")
     ap.add_argument("--mixed-c2-only", action="store_true",
                     help="mixed form: run the N=65536 workload alone")
-    ap.add_argument("--form", choices=("plain", "batched", "serving", "mixed"), default="plain",
+    ap.add_argument("--form", choices=("plain", "batched", "serving", "mixed", "points"), default="plain",
                     help="plain: the headline workload; batched: 64 uneven matrices in one launch; "
-                         "serving: 8 resident matrices under a request stream")
+                         "serving: 8 resident matrices under a request stream; mixed: split BF16; "
+                         "points: near and far blocks computed from the points")
     ap.add_argument("--burst", type=int, default=128, help="serving: requests in the saturation burst")
     ap.add_argument("--serving-seconds", type=float, default=3.0, help="serving: seconds per load level")
     ap.add_argument("--serving-seed", type=int, default=4)
@@ -397,6 +449,9 @@ def main() -> int:
         return 0
     if args.form == "mixed":
         print(json.dumps(bench_mixed(args)), flush=True)
+        return 0
+    if args.form == "points":
+        print(json.dumps(bench_points(args)), flush=True)
         return 0
 
     import torch
