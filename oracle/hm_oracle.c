@@ -297,8 +297,10 @@ static void orc_interactions(orc_h2 *H)
  * (0 when the cap or the full width ended the loop).  Returns 1 when the cap
  * decided the rank. */
 static int orc_pqr_id(double *A, int64_t mr, int nc, double tol, int rmax,
-                      int *k_out, int *piv, double *Tcoef, double *rdiag)
+                      int *k_out, int *piv, double *Tcoef, double *rdiag, int par)
 {
+    /* par: run the loops over columns on the OpenMP team (each column's
+     * arithmetic is the same either way) */
     int cap = rmax;
     if (cap > nc) cap = nc;
     if ((int64_t)cap > mr) cap = (int)mr;
@@ -311,15 +313,17 @@ static int orc_pqr_id(double *A, int64_t mr, int nc, double tol, int rmax,
     for (int j = 0;; j++) {
         if (j >= nc || (int64_t)j >= mr) { k = j; if (rdiag) rdiag[j] = 0.0; break; }
         /* exact remaining column norms */
-        int p = j;
-        double best = -1.0;
+#pragma omp parallel for if (par) schedule(static)
         for (int c = j; c < nc; c++) {
             double s = 0.0;
             const double *col = A + (size_t)c * mr;
             for (int64_t i = j; i < mr; i++) s += col[i] * col[i];
             nrm2[c] = s;
-            if (s > best) { best = s; p = c; }
         }
+        int p = j;
+        double best = -1.0;
+        for (int c = j; c < nc; c++)
+            if (nrm2[c] > best) { best = nrm2[c]; p = c; }
         double rjj = sqrt(best);
         if (j == 0) r11 = rjj;
         if (rjj == 0.0 || (j > 0 && rjj <= tol * r11)) { k = j; if (rdiag) rdiag[j] = rjj; break; }
@@ -341,6 +345,7 @@ static int orc_pqr_id(double *A, int64_t mr, int nc, double tol, int rmax,
         a[j] = alpha;
         for (int64_t i = j + 1; i < mr; i++) a[i] = 0.0;
         if (vtv > 0.0) {
+#pragma omp parallel for if (par) schedule(static)
             for (int c = j + 1; c < nc; c++) {
                 double *col = A + (size_t)c * mr;
                 double s = 0.0;
@@ -352,6 +357,7 @@ static int orc_pqr_id(double *A, int64_t mr, int nc, double tol, int rmax,
     }
     /* Tcoef = R11^{-1} R12, R stored in the upper triangle of A */
     int nr = nc - k;
+#pragma omp parallel for if (par) schedule(static)
     for (int c = 0; c < nr; c++) {
         for (int i = k - 1; i >= 0; i--) {
             double s = A[(size_t)(k + c) * mr + i];
@@ -479,9 +485,16 @@ static void orc_compress(orc_h2 *H)
     double **bas = calloc((size_t)n, sizeof(double *));
     int64_t **sk = calloc((size_t)n, sizeof(int64_t *));
     int *ncol = calloc((size_t)n, sizeof(int));
+    int nthreads = 1;
+#ifdef _OPENMP
+    nthreads = omp_get_max_threads();
+#endif
     for (int lev = H->L; lev >= 0; lev--) {
         int first = (1 << lev) - 1, last = (2 << lev) - 1;
-#pragma omp parallel for schedule(dynamic, 1)
+        /* a level with fewer nodes than threads runs its nodes one after the
+         * other, each with the column loops of its ID on all threads */
+        int inner = last - first < nthreads;
+#pragma omp parallel for schedule(dynamic, 1) if (!inner)
         for (int a = first; a < last; a++) {
             int leaf = H->left[a] < 0;
             int nc = leaf ? (int)H->size[a] : H->rank[H->left[a]] + H->rank[H->right[a]];
@@ -500,12 +513,13 @@ static void orc_compress(orc_h2 *H)
             double *P = NULL;
             if (mr > 0 && nc > 0) {
                 double *A = malloc(sizeof(double) * (size_t)mr * nc);
+#pragma omp parallel for if (inner) schedule(static)
                 for (int j = 0; j < nc; j++)
                     for (int64_t i = 0; i < mr; i++)
                         A[(size_t)j * mr + i] = orc_kernel_idx(H, H->perm[rows[i]], cand[j]);
                 int *piv = malloc(sizeof(int) * nc);
                 double *Tc = malloc(sizeof(double) * (size_t)nc * nc + 1);
-                H->cap_hit[a] = orc_pqr_id(A, mr, nc, H->tol, H->rmax, &k, piv, Tc, NULL);
+                H->cap_hit[a] = orc_pqr_id(A, mr, nc, H->tol, H->rmax, &k, piv, Tc, NULL, inner);
                 P = calloc((size_t)k * nc + 1, sizeof(double));
                 int nr = nc - k;
                 for (int i = 0; i < k; i++) {
@@ -850,11 +864,38 @@ void orc_exact_rows(const orc_h2 *H, const int64_t *rows, int64_t nrows, const d
     }
 }
 
+/* A point set with its kernel and nothing else (no tree, no compression),
+ * for orc_exact_rows on workloads whose compression the caller does not
+ * need.  Free with orc_free. */
+orc_h2 *orc_points(const double *X, int64_t N, int d, int kernel, double h)
+{
+    if (N < 1 || d < 1 || h <= 0.0) return NULL;
+    orc_h2 *H = calloc(1, sizeof(orc_h2));
+    H->N = N; H->d = d; H->kernel = kernel; H->h = h;
+    H->X = malloc(sizeof(double) * (size_t)N * d);
+    memcpy(H->X, X, sizeof(double) * (size_t)N * d);
+    return H;
+}
+
+/* Row sample R(a) of node a (tree positions, ascending) into out (room for
+ * cap entries); returns the sample's size, or -1 if a is out of range or the
+ * sample does not fit.  Exposed so that the tests can pin the sampling rule. */
+int64_t orc_row_sample_public(const orc_h2 *H, int a, int64_t *out, int64_t cap)
+{
+    if (a < 0 || a >= H->n_nodes) return -1;
+    int64_t *rows = NULL;
+    int64_t n = orc_row_sample(H, a, &rows);
+    if (n > cap) { free(rows); return -1; }
+    memcpy(out, rows, sizeof(int64_t) * (size_t)n);
+    free(rows);
+    return n;
+}
+
 /* Standalone pivoted-QR ID of a column-major mr x nc block, for pinning. */
 int orc_pqr_id_public(double *A, int64_t mr, int nc, double tol, int rmax, int *k, int *piv,
                       double *Tcoef, double *rdiag)
 {
-    return orc_pqr_id(A, mr, nc, tol, rmax, k, piv, Tcoef, rdiag);
+    return orc_pqr_id(A, mr, nc, tol, rmax, k, piv, Tcoef, rdiag, 0);
 }
 
 /* ------------------------------------------------------------------------ */

@@ -44,6 +44,10 @@ def lib():
         L.orc_pqr_id_public.restype = ctypes.c_int
         L.orc_pqr_id_public.argtypes = [_f64p, ctypes.c_int64, ctypes.c_int, ctypes.c_double,
                                         ctypes.c_int, _i32p, _i32p, _f64p, _f64p]
+        L.orc_points.restype = ctypes.c_void_p
+        L.orc_points.argtypes = [_f64p, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_double]
+        L.orc_row_sample_public.restype = ctypes.c_int64
+        L.orc_row_sample_public.argtypes = [ctypes.c_void_p, ctypes.c_int, _i64p, ctypes.c_int64]
         L.orc_write.restype = ctypes.c_int
         L.orc_write.argtypes = [ctypes.c_void_p, ctypes.c_char_p]
         L.orc_set_threads.argtypes = [ctypes.c_int]
@@ -78,6 +82,24 @@ def pqr_id(A: np.ndarray, tol: float, rmax: int):
                                      _p(T, _f64p), _p(rd, _f64p))
     kk = int(k[0])
     return kk, piv[:nc].copy(), T[: kk * (nc - kk)].reshape(kk, nc - kk).copy(), rd[: kk + 1].copy(), bool(capped)
+
+
+def exact_rows(X: np.ndarray, kernel: int, h: float, rows, W: np.ndarray) -> np.ndarray:
+    """(K W)[rows, :] from the kernel's definition, for points X (original
+    order), without compressing anything."""
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    H = lib().orc_points(_p(X, _f64p), X.shape[0], X.shape[1], int(kernel), float(h))
+    if not H:
+        raise ValueError("oracle rejected the points")
+    try:
+        rows = np.ascontiguousarray(rows, dtype=np.int64)
+        W = np.ascontiguousarray(W, dtype=np.float64)
+        out = np.zeros((len(rows), W.shape[1]), np.float64)
+        lib().orc_exact_rows(ctypes.c_void_p(H), _p(rows, _i64p), len(rows), _p(W, _f64p), W.shape[1],
+                             _p(out, _f64p))
+        return out
+    finally:
+        lib().orc_free(ctypes.c_void_p(H))
 
 
 class OracleH2:
@@ -220,6 +242,14 @@ class OracleH2:
         lib().orc_exact_rows(self._h, _p(rows, _i64p), len(rows), _p(W, _f64p), W.shape[1],
                              _p(out, _f64p))
         return out
+
+    def row_sample(self, a: int) -> np.ndarray:
+        """Rows (tree positions, ascending) of the ID of node a."""
+        out = np.zeros(max(self.N, 1), np.int64)
+        n = lib().orc_row_sample_public(self._h, int(a), _p(out, _i64p), len(out))
+        if n < 0:
+            raise ValueError("bad node")
+        return out[:n].copy()
 
     def write(self, path: str) -> None:
         rc = lib().orc_write(self._h, os.fsencode(path))
