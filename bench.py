@@ -25,8 +25,10 @@ PEAK_HBM_GBPS = 8000.0
 
 
 def kernel_source_hash() -> str:
+    """Hash of every source that decides what the timed launch executes: the
+    kernels, the store layout and segments, the queue order, and the types."""
     h = hashlib.sha256()
-    for f in ("hm_kernels.hip", "hm_build.hip"):
+    for f in ("hm_kernels.hip", "hm_build.hip", "hm_sched.hip", "hm_internal.h"):
         h.update(open(os.path.join(ROOT, "paper_1812_07152_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -57,54 +59,104 @@ def measured_counters(name: str):
             "source": f"profiles/{name}.json (rocprofv3 SQ_VALU_MFMA_BUSY_CYCLES, SQ_INSTS_VALU_MFMA_MOPS_F64)"}
 
 
-def time_variant(hmx, torch, M, w, dtype, steps, warmup, flags=0):
-    W = torch.from_numpy(__import__("workloads").gen_w(w)).to("cuda", dtype)
+def time_variant(hmx, torch, M, W, steps, warmup, flags=0, prec=None):
+    """Times `steps` evaluations Y = K~ W on torch's current stream after
+    `warmup` untimed ones; returns (ms per step by the host clock, per-phase
+    launch milliseconds and counts from HIP events, Y)."""
     Y = torch.empty_like(W)
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
-        hmx.hm_eval(M, W, Y, flags=flags, stream=stream)
+        hmx.hm_eval(M, W, Y, flags=flags, stream=stream, prec=prec)
     torch.cuda.synchronize()
     hmx.hm_profile_reset(M)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        hmx.hm_eval(M, W, Y, flags=flags | hmx.HM_PROFILE, stream=stream)
+        hmx.hm_eval(M, W, Y, flags=flags | hmx.HM_PROFILE, stream=stream, prec=prec)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms, n = hmx.hm_profile_read(M)
-    return (t1 - t0) * 1e3 / steps, ms, n
+    hmx.hm_check(M)  # raises if a bounded dependency wait expired (the results would be invalid)
+    return (t1 - t0) * 1e3 / steps, ms, n, Y
 
 
-def cpu_baseline(w, budget_s: float = 15.0):
+def host_description() -> dict:
+    """The host the CPU baseline ran on: model name and usable cores."""
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"cpu_model": model, "affinity_cores": len(os.sched_getaffinity(0))}
+
+
+def cpu_baseline(w, X, W, budget_s: float = 15.0, eps_rows: int = 256):
     """The oracle (plain C, FP64, OpenMP over nodes) on a bounded column sample
     of the same workload: its own compression (untimed), then the timed tree
-    walk on Qs of the Q columns, Qs chosen for roughly budget_s seconds."""
+    walk, as the paper times (median of 5 runs), on all usable host cores and
+    on one core.  The sample's width is chosen so that the five runs take about
+    budget_s.  Also returns the oracle's Y on the sampled columns (the first
+    qs columns of W) and the exact rows (K W)[rows, :qs] of eps_rows seeded rows
+    (the direct definition), for the accuracy figures."""
     import numpy as np
 
-    import workloads as wl
     from oracle import oracle as orc
-    H = orc.OracleH2.from_workload(w, wl.gen_points(w))
+    H = orc.OracleH2.from_workload(w, X)
     st = H.stats()
+    cores = orc.max_threads()
     # two probes fit time = fixed + per_col * columns (the tree walk's fixed
     # part is large next to a few columns, so one probe overestimates)
     probe = []
     for q in (4, 16):
-        Wp = np.ascontiguousarray(wl.gen_w(w, Q=q))
+        Wp = np.ascontiguousarray(W[:, :q])
         t = time.perf_counter()
         H.eval(Wp)
         probe.append(time.perf_counter() - t)
     per_col = max((probe[1] - probe[0]) / 12, 1e-9)
     fixed = max(probe[0] - 4 * per_col, 0.0)
-    qs = int(max(4, min(w.Q, (budget_s - fixed) / per_col)))
-    Ws = np.ascontiguousarray(wl.gen_w(w, Q=qs))
-    t = time.perf_counter()
-    H.eval(Ws)
-    dt = time.perf_counter() - t
-    return {"value": st["flops_per_col"] * qs / dt / 1e9, "unit": "GFLOP/s",
-            "cores": orc.max_threads(), "kind": "oracle",
-            "sample": f"same compressed workload, {qs} of the {w.Q} columns of W "
-                      f"({dt:.1f} s timed tree walk)",
-            "seconds": dt}
+    qs = int(max(4, min(w.Q, (budget_s / 5 - fixed) / per_col)))
+    Ws = np.ascontiguousarray(W[:, :qs])
+    times = []
+    for _ in range(5):
+        t = time.perf_counter()
+        Yo = H.eval(Ws)
+        times.append(time.perf_counter() - t)
+    dt = float(np.median(times))
+    # one core, on a narrower sample (the fixed part grows with it too)
+    q1 = 4
+    orc.set_threads(1)
+    try:
+        W1 = np.ascontiguousarray(W[:, :q1])
+        t = time.perf_counter()
+        H.eval(W1)
+        dt1 = time.perf_counter() - t
+    finally:
+        orc.set_threads(cores)
+    rows = np.random.default_rng(12345).choice(w.N, eps_rows, replace=False)
+    exact = H.exact_rows(rows, Ws)
+    eps_f = float(np.linalg.norm(Yo[rows] - exact) / np.linalg.norm(exact))
+    base = {"value": st["flops_per_col"] * qs / dt / 1e9, "unit": "GFLOP/s",
+            "cores": cores, "kind": "oracle",
+            "sample": f"same compressed workload, {qs} of the {w.Q} columns of W; median of 5 timed "
+                      f"tree walks ({dt:.2f} s each)",
+            "seconds_median": dt, "seconds_all": times, **host_description(),
+            "one_core": {"value": st["flops_per_col"] * q1 / dt1 / 1e9, "unit": "GFLOP/s", "columns": q1,
+                         "seconds": dt1},
+            "eps_f_sampled_oracle": eps_f}
+    return base, {"cols": qs, "Y": Yo, "rows": rows, "exact": exact}
+
+
+def errors_vs_oracle(Ygpu, ref) -> dict:
+    """A GPU result against the oracle on the oracle's sampled columns: the
+    relative Frobenius difference to the oracle's own evaluation (same
+    compression) and the sampled-row eps_f against the exact (K W) rows."""
+    import numpy as np
+    Y = np.asarray(Ygpu, dtype=np.float64)[:, :ref["cols"]]
+    return {"rel_err_vs_oracle": float(np.linalg.norm(Y - ref["Y"]) / np.linalg.norm(ref["Y"])),
+            "eps_f_sampled": float(np.linalg.norm(Y[ref["rows"]] - ref["exact"]) / np.linalg.norm(ref["exact"]))}
 
 
 def bench_batched(args) -> dict:
@@ -154,6 +206,10 @@ def bench_batched(args) -> dict:
     hmx.hm_batch_check(B)
     err = max(float((a - b).norm() / b.norm()) for a, b in zip(Yb, Ys))
     info = hmx.hm_batch_info(B)
+    # the oracle beside it: the three smallest matrices, their first columns
+    small = sorted(range(len(specs)), key=lambda i: specs[i].N)[:3]
+    cpu = cpu_baseline_batched([specs[i] for i in small], [Ws[i][:, :8].double().cpu().numpy() for i in small],
+                               [Yb[i][:, :8].double().cpu().numpy() for i in small])
     return {
         "metric": "batched K~W GFLOP/s (algorithmic), 64 matrices, one persistent launch",
         "value": flops / (ms_batch * 1e-3) / 1e9, "unit": "GFLOP/s", "n_gpus": 1,
@@ -168,7 +224,31 @@ def bench_batched(args) -> dict:
         "frac_of_fp32_peak": flops / (ms_batch * 1e-3) / 1e12 / PEAK_FP32_TFLOPS,
         "autotune": {"column_tile": info["column_tile"], "tuned_ms": info["tuned_ms"], "seconds": t_tune},
         "tasks": info["n_tasks"], "workgroups": info["workgroups"], "setup_s": {"compress_and_load": t_build},
+        "cpu_baseline": cpu,
     }
+
+
+def cpu_baseline_batched(specs, Ws, Ys) -> dict:
+    """The oracle on a few of the batched matrices (its own compression,
+    untimed; the tree walk timed): GFLOP/s over them, and the batched FP32
+    results' largest relative error against it (the bar of the plain FP32
+    path is 5e-6: FP32 rounding of the blocks and W)."""
+    import numpy as np
+
+    import workloads as wl
+    from oracle import oracle as orc
+    flops, secs, errs = 0.0, 0.0, []
+    for w, W, Y in zip(specs, Ws, Ys):
+        H = orc.OracleH2.from_workload(w, wl.gen_points(w))
+        Wr = np.ascontiguousarray(W.astype(np.float32).astype(np.float64))
+        t = time.perf_counter()
+        ref = H.eval(Wr)
+        secs += time.perf_counter() - t
+        flops += H.stats()["flops_per_col"] * W.shape[1]
+        errs.append(float(np.linalg.norm(Y - ref) / np.linalg.norm(ref)))
+    return {"value": flops / secs / 1e9, "unit": "GFLOP/s", "cores": orc.max_threads(), "kind": "oracle",
+            "sample": f"{len(specs)} smallest matrices (N {[w.N for w in specs]}), 8 columns each",
+            "max_rel_err_batched_fp32_vs_oracle": max(errs)}
 
 
 def bench_serving(args) -> dict:
@@ -269,8 +349,17 @@ def bench_serving(args) -> dict:
         levels.append({"offered_rps": rate, "fraction_of_saturation": frac, "requests": n,
                        "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
                        "achieved_rps": n / wall, "gflops": flops(reqs) / wall / 1e9})
+    # one more served request on the smallest matrix, checked against the oracle
+    Wc = Wsrc[0][:, :16].contiguous()
+    Yc = torch.full_like(Wc, float("nan"))
+    tk = hmx.hm_submit(S, ids[0], Wc, Yc)
+    t_end = time.perf_counter() + 60
+    while not hmx.hm_poll(S, tk)[0]:
+        assert time.perf_counter() < t_end, "check request did not complete"
+        time.sleep(0.0005)
     st = hmx.hm_server_stats(S)
     hmx.hm_server_destroy(S)
+    cpu = cpu_baseline_served(specs[0], Wc.double().cpu().numpy(), Yc.double().cpu().numpy())
     return {
         "metric": "served K~W throughput (GFLOP/s, algorithmic) and p50/p99 latency",
         "value": flops(burst) / (len(burst) / sat_rps) / 1e9, "unit": "GFLOP/s", "n_gpus": 1,
@@ -283,14 +372,35 @@ def bench_serving(args) -> dict:
         "levels": levels,
         "server": {"sweeps": st["sweeps"], "completed": st["completed"], "failed": st["failed"],
                    "requests_per_sweep": st["completed"] / max(st["sweeps"], 1),
-                   "peak_inflight_sweeps": st["peak_inflight"], "peak_pack_gib": st["peak_bytes"] / 2**30},
+                   "peak_inflight_sweeps": st["peak_inflight"], "peak_working_set_gib": st["peak_bytes"] / 2**30},
         "setup_s": {"compress_and_load": t_build},
+        "cpu_baseline": cpu,
     }
 
 
-def _mixed_one(args, w, adm_name: str, kernel_name: str) -> dict:
+def cpu_baseline_served(w, W, Y) -> dict:
+    """The oracle on one served request (the smallest resident matrix, its
+    own compression untimed, the tree walk timed); the served FP32 result's
+    relative error against it (FP32 bar 5e-6, as the plain FP32 path)."""
+    import numpy as np
+
+    import workloads as wl
+    from oracle import oracle as orc
+    H = orc.OracleH2.from_workload(w, wl.gen_points(w))
+    Wr = np.ascontiguousarray(W.astype(np.float32).astype(np.float64))
+    t = time.perf_counter()
+    ref = H.eval(Wr)
+    dt = time.perf_counter() - t
+    return {"value": H.stats()["flops_per_col"] * W.shape[1] / dt / 1e9, "unit": "GFLOP/s",
+            "cores": orc.max_threads(), "kind": "oracle",
+            "sample": f"one request of {W.shape[1]} columns on {w.name}",
+            "rel_err_served_fp32_vs_oracle": float(np.linalg.norm(Y - ref) / np.linalg.norm(ref))}
+
+
+def _mixed_one(args, w, adm_name: str, kernel_name: str, keep_cols: int = 0) -> dict:
     """Times one workload in FP64, split BF16 and FP32 on the same compressed
-    matrix; errors are relative Frobenius norms against the FP64 result."""
+    matrix; errors are relative Frobenius norms against the FP64 result.
+    keep_cols: also return W's and each result's first columns (host)."""
     import torch
 
     import paper_1812_07152_amd as hmx
@@ -326,7 +436,13 @@ def _mixed_one(args, w, adm_name: str, kernel_name: str) -> dict:
     ref = results["fp64"]
     for name in ("bf16x3", "fp32"):
         out[name]["rel_err_vs_fp64"] = float((results[name] - ref).norm() / ref.norm())
+    kept = None
+    if keep_cols:
+        kept = {"W": W[:, :keep_cols].cpu().numpy(),
+                **{k: v[:, :keep_cols].cpu().numpy() for k, v in results.items()}}
+    del results, ref, W, M
     return {
+        "_cols": kept,
         "config": {"workload": w.name, "N": w.N, "d": w.d, "Q": w.Q, "kernel": kernel_name, "h": w.h,
                    "leaf": w.m, "tol": w.tol, "max_rank": w.rmax, "admissibility": adm_name,
                    "gflop_per_step": flops / 1e9, "E_V": info["E_V"], "E_T": info["E_T"],
@@ -336,6 +452,43 @@ def _mixed_one(args, w, adm_name: str, kernel_name: str) -> dict:
         "speedup_vs_fp64": out["fp64"]["ms_per_step"] / out["bf16x3"]["ms_per_step"],
         "setup_s": {"compress": t_compress},
     }
+
+
+def bench_mixed_c4(args) -> dict:
+    """The mixed-precision form on its own workload: N = 262144 points in
+    d = 28 (i.i.d. normal), kernel exp(-r/4), leaf 256, tol 1e-4, rank <= 256,
+    HSS, W: N x 1024; split BF16 against the plain FP64 and FP32 paths on the
+    same matrix.  Accuracy: against the GPU FP64 result (which the parity
+    tests hold to the oracle's tree walk at this size), and against the exact
+    (K W) rows of 256 seeded rows on 16 columns (the oracle's direct
+    definition), for FP64 and split BF16."""
+    import workloads as wl
+    r = _mixed_one(args, wl.C4, "HSS", "exp(-r/h)", keep_cols=16)
+    cols = r.pop("_cols")
+    cpu = cpu_baseline_exact_rows(wl.C4, wl.gen_points(wl.C4), cols)
+    m = r["paths"]["bf16x3"]
+    return {"metric": "mixed-precision K~W GFLOP/s (algorithmic) vs the plain FP64 path",
+            "value": m["gflops"], "unit": "GFLOP/s", "ms_per_step": m["ms_per_step"], "dtype": "bf16x3+f64",
+            **r, "cpu_baseline": cpu}
+
+
+def cpu_baseline_exact_rows(w, X, cols, n_rows: int = 256) -> dict:
+    """Exact rows (K W)[rows, :q] from the oracle's direct definition (no
+    compression), timed, and the sampled-row eps_f of each GPU result."""
+    import numpy as np
+
+    from oracle import oracle as orc
+    rows = np.random.default_rng(54321).choice(w.N, n_rows, replace=False)
+    Wq = np.ascontiguousarray(cols["W"])
+    t = time.perf_counter()
+    exact = orc.exact_rows(X, w.kernel, w.h, rows, Wq)
+    dt = time.perf_counter() - t
+    out = {"kind": "oracle", "cores": orc.max_threads(), "sample": f"exact rows: {n_rows} rows x {Wq.shape[1]} columns",
+           "seconds": dt, "value": 2.0 * n_rows * w.N * Wq.shape[1] / dt / 1e9, "unit": "GFLOP/s (direct K W rows)"}
+    for k, Y in cols.items():
+        if k != "W":
+            out[f"eps_f_sampled_{k}"] = float(np.linalg.norm(Y[rows] - exact) / np.linalg.norm(exact))
+    return out
 
 
 def bench_points(args) -> dict:
@@ -361,13 +514,9 @@ def bench_points(args) -> dict:
         hmx.hm_set_points(Mp, X, w.kernel, w.h)
         info = hmx.hm_info(M)
         flops = info["flops_per_col"] * w.Q
-        ms0, _, _ = time_variant(hmx, torch, M, w, torch.float64, args.steps, args.warmup)
-        msp, php, npp = time_variant(hmx, torch, Mp, w, torch.float64, args.steps, args.warmup, flags=both)
         Wd = torch.from_numpy(wl.gen_w(w)).to("cuda", torch.float64)
-        Ys, Yp = torch.empty_like(Wd), torch.empty_like(Wd)
-        hmx.hm_eval(M, Wd, Ys)
-        hmx.hm_eval(Mp, Wd, Yp, flags=both)
-        torch.cuda.synchronize()
+        ms0, _, _, Ys = time_variant(hmx, torch, M, Wd, args.steps, args.warmup)
+        msp, php, npp, Yp = time_variant(hmx, torch, Mp, Wd, args.steps, args.warmup, flags=both)
         runs[w.name] = {
             "N": w.N, "d": w.d, "Q": w.Q, "ms_stored": ms0, "ms_from_points": msp,
             "launch_ms_from_points": php[3] / max(npp[3], 1),
@@ -401,6 +550,9 @@ def bench_mixed(args) -> dict:
     else:
         main_run = _mixed_one(args, wl.C4, "HSS", "exp(-r/h)")
         also = _mixed_one(args, wl.C2, f"distance tau={wl.C2.tau}", "gaussian") if args.mixed_both else None
+    main_run.pop("_cols", None)
+    if also:
+        also.pop("_cols", None)
     m = main_run["paths"]["bf16x3"]
     return {
         "metric": "mixed-precision K~W GFLOP/s (algorithmic) vs the plain FP64 path",
@@ -418,6 +570,10 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the split-BF16 step on the headline workload")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the batched, served and N=262144 mixed-precision forms after the headline")
+    ap.add_argument("--no-c4", action="store_true", help="skip the N=262144 mixed-precision form")
     ap.add_argument("--no-near-from-points", dest="near_from_points", action="store_false",
                     help="skip the matrix-free near-field variant of the FP64 step")
     ap.add_argument("--mixed-c4-only", dest="mixed_both", action="store_false",
@@ -454,6 +610,7 @@ def main() -> int:
         print(json.dumps(bench_points(args)), flush=True)
         return 0
 
+    import numpy as np
     import torch
 
     import paper_1812_07152_amd as hmx
@@ -461,11 +618,13 @@ def main() -> int:
 
     w = wl.C2
     X = wl.gen_points(w)
+    Wn = wl.gen_w(w)
     t = time.perf_counter()
     R = hmx.hm_compress(X, kernel=w.kernel, h=w.h, leaf_size=w.m, tol=w.tol, max_rank=w.rmax,
                         admissibility=w.adm, tau=w.tau, sample_rows=w.sample_rows, seed=w.sample_seed)
     t_compress = time.perf_counter() - t
-    precs = hmx.precbit(hmx.HM_PREC_FP64) | (0 if args.no_fp32 else hmx.precbit(hmx.HM_PREC_FP32))
+    precs = (hmx.precbit(hmx.HM_PREC_FP64) | (0 if args.no_fp32 else hmx.precbit(hmx.HM_PREC_FP32))
+             | (0 if args.no_mixed else hmx.precbit(hmx.HM_PREC_BF16X3)))
     t = time.perf_counter()
     M = hmx.hm_load_compressed_mem(R, 0, precs)
     t_load = time.perf_counter() - t
@@ -473,8 +632,11 @@ def main() -> int:
     if not args.near_from_points:
         del R
     flops = info["flops_per_col"] * w.Q
+    W64 = torch.from_numpy(Wn).to("cuda", torch.float64)
+    results = {}  # GPU results on the host, compared with the oracle at the end
 
-    ms64, ph64, n64 = time_variant(hmx, torch, M, w, torch.float64, args.steps, args.warmup)
+    ms64, ph64, n64, Y = time_variant(hmx, torch, M, W64, args.steps, args.warmup)
+    results["fp64"] = Y.cpu().numpy()
     # the dominant kernel: the persistent task-graph launch, which runs every
     # block product of the step (everything but the two permutes)
     graph_ms = ph64[3] / max(n64[3], 1)
@@ -508,58 +670,59 @@ def main() -> int:
         "phase_ms": {k: ph64[i] / max(n64[i], 1) for i, k in
                      enumerate(("permute_in", "up", "down", "graph", "permute_out")) if n64[i]},
         "setup_s": {"compress": t_compress, "load": t_load},
+        "store_gb_fp64": info["bytes_fp64"] / 1e9,
     }
     if not args.no_fp32:
-        ms32, ph32, n32 = time_variant(hmx, torch, M, w, torch.float32, args.steps, args.warmup)
+        ms32, ph32, n32, Y = time_variant(hmx, torch, M, W64.float(), args.steps, args.warmup)
+        results["fp32"] = Y.double().cpu().numpy()
         out["fp32"] = {"ms_per_step": ms32, "value": flops / (ms32 * 1e-3) / 1e9, "unit": "GFLOP/s",
                        "frac_of_fp32_peak": flops / (ms32 * 1e-3) / 1e12 / PEAK_FP32_TFLOPS}
+    if not args.no_mixed:
+        # the mixed-precision form on the same matrix: split-BF16 near, far
+        # and leaf-basis products, FP64 transfers and final sum
+        msm, phm, nm, Y = time_variant(hmx, torch, M, W64, args.steps, args.warmup, prec=hmx.HM_PREC_BF16X3)
+        results["mixed_bf16x3"] = Y.cpu().numpy()
+        out["mixed_bf16x3"] = {
+            "ms_per_step": msm, "value": flops / (msm * 1e-3) / 1e9, "unit": "GFLOP/s",
+            "launch_ms": phm[3] / max(nm[3], 1), "speedup_vs_fp64": ms64 / msm,
+            "rel_err_vs_gpu_fp64": float(np.linalg.norm(results["mixed_bf16x3"] - results["fp64"])
+                                         / np.linalg.norm(results["fp64"]))}
     if args.near_from_points:
         # matrix-free near field: the same FP64 step with every near block
         # computed from the points in the product tiles (stored blocks unread)
         hmx.hm_set_points(M, X, w.kernel, w.h)
-        msp, php, npp = time_variant(hmx, torch, M, w, torch.float64, args.steps, args.warmup,
-                                     flags=hmx.HM_NEAR_FROM_POINTS)
-        Wd = torch.from_numpy(wl.gen_w(w)).to("cuda", torch.float64)
-        Ys, Yp = torch.empty_like(Wd), torch.empty_like(Wd)
-        hmx.hm_eval(M, Wd, Ys)
-        hmx.hm_eval(M, Wd, Yp, flags=hmx.HM_NEAR_FROM_POINTS)
-        torch.cuda.synchronize()
+        msp, php, npp, Yp = time_variant(hmx, torch, M, W64, args.steps, args.warmup,
+                                         flags=hmx.HM_NEAR_FROM_POINTS)
+        results["near_from_points"] = Yp.cpu().numpy()
         out["near_from_points"] = {
             "ms_per_step": msp, "value": flops / (msp * 1e-3) / 1e9, "unit": "GFLOP/s",
             "launch_ms": php[3] / max(npp[3], 1),
             "near_block_bytes_not_read": info["E_D"] * 8,
-            "rel_diff_vs_stored": float(torch.linalg.norm(Yp - Ys) / torch.linalg.norm(Ys))}
-        # the same matrix loaded without its near blocks: the store's HBM
-        M2 = hmx.hm_load_compressed_mem(R, 0, hmx.precbit(hmx.HM_PREC_FP64) | hmx.HM_LOAD_NO_NEAR_BLOCKS)
-        # and without its near and far blocks (both computed from the points
-        # and the skeletons)
+            "rel_diff_vs_stored": float(np.linalg.norm(results["near_from_points"] - results["fp64"])
+                                        / np.linalg.norm(results["fp64"]))}
+        del M
+        # the same matrix loaded without its near and far blocks (both
+        # computed from the points and the skeletons): the store's HBM
         M3 = hmx.hm_load_compressed_mem(R, 0, hmx.precbit(hmx.HM_PREC_FP64) | hmx.HM_LOAD_NO_NEAR_BLOCKS
                                         | hmx.HM_LOAD_NO_FAR_BLOCKS)
         del R
-        hmx.hm_set_points(M2, X, w.kernel, w.h)
-        ms2, _, _ = time_variant(hmx, torch, M2, w, torch.float64, args.steps, args.warmup,
-                                 flags=hmx.HM_NEAR_FROM_POINTS)
-        Y2 = torch.empty_like(Wd)
-        hmx.hm_eval(M2, Wd, Y2, flags=hmx.HM_NEAR_FROM_POINTS)
-        torch.cuda.synchronize()
-        out["near_from_points"].update({
-            "store_gb_with_near_blocks": info["bytes_fp64"] / 1e9,
-            "store_gb_without_near_blocks": hmx.hm_info(M2)["bytes_fp64"] / 1e9,
-            "ms_per_step_without_near_blocks": ms2,
-            "rel_diff_without_near_blocks": float(torch.linalg.norm(Y2 - Ys) / torch.linalg.norm(Ys))})
         both = hmx.HM_NEAR_FROM_POINTS | hmx.HM_FAR_FROM_POINTS
         hmx.hm_set_points(M3, X, w.kernel, w.h)
-        ms3, ph3, n3 = time_variant(hmx, torch, M3, w, torch.float64, args.steps, args.warmup, flags=both)
-        hmx.hm_eval(M3, Wd, Y2, flags=both)
-        torch.cuda.synchronize()
+        ms3, ph3, n3, Y3 = time_variant(hmx, torch, M3, W64, args.steps, args.warmup, flags=both)
+        results["near_and_far_from_points"] = Y3.cpu().numpy()
         out["near_from_points"]["far_too"] = {
             "ms_per_step": ms3, "value": flops / (ms3 * 1e-3) / 1e9, "unit": "GFLOP/s",
             "launch_ms": ph3[3] / max(n3[3], 1),
             "far_block_bytes_not_read": info["E_B"] * 8,
             "store_gb_without_near_and_far_blocks": hmx.hm_info(M3)["bytes_fp64"] / 1e9,
-            "rel_diff_vs_stored": float(torch.linalg.norm(Y2 - Ys) / torch.linalg.norm(Ys))}
-        del M2, M3, Y2, Wd, Ys, Yp
-    del M
+            "rel_diff_vs_stored": float(np.linalg.norm(results["near_and_far_from_points"] - results["fp64"])
+                                        / np.linalg.norm(results["fp64"]))}
+        del M3, Y3, Yp
+    else:
+        del M
+    del Y, W64
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
     if args.calib_copy_mib:
         src = torch.ones(args.calib_copy_mib << 17, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
@@ -569,9 +732,36 @@ def main() -> int:
         out["calib_copy_bytes"] = {"read": src.numel() * 8, "write": dst.numel() * 8}
         del src, dst
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w)
+        base, ref = cpu_baseline(w, X, Wn)
+        out["cpu_baseline"] = base
+        # every GPU result of this workload against the oracle, on the
+        # oracle's sampled columns and rows
+        out["accuracy_vs_oracle"] = {"columns": ref["cols"], "rows_for_eps_f": len(ref["rows"]),
+                                     "eps_f_sampled_oracle": base["eps_f_sampled_oracle"],
+                                     **{k: errors_vs_oracle(v, ref) for k, v in results.items()}}
+        out["eps_f_sampled"] = out["accuracy_vs_oracle"]["fp64"]["eps_f_sampled"]
+    del results
+    if not args.no_forms:
+        # the three forms beside the plain kernel, each on its own workload
+        out["forms"] = {}
+        t = time.perf_counter()
+        out["forms"]["batched"] = compact(bench_batched(args))
+        print(f"[bench] batched form done ({time.perf_counter() - t:.0f} s)", file=sys.stderr, flush=True)
+        t = time.perf_counter()
+        out["forms"]["served"] = compact(bench_serving(args))
+        print(f"[bench] served form done ({time.perf_counter() - t:.0f} s)", file=sys.stderr, flush=True)
+        if not args.no_c4:
+            t = time.perf_counter()
+            out["forms"]["mixed_c4"] = compact(bench_mixed_c4(args))
+            print(f"[bench] mixed C4 form done ({time.perf_counter() - t:.0f} s)", file=sys.stderr, flush=True)
     print(json.dumps(out), flush=True)
     return 0
+
+
+def compact(d: dict) -> dict:
+    """A form's JSON line without the keys the headline line already has."""
+    drop = ("n_gpus", "steps", "warmup", "higher_is_better", "data", "scaling", "vs_baseline")
+    return {k: v for k, v in d.items() if k not in drop}
 
 
 if __name__ == "__main__":

@@ -84,6 +84,9 @@ typedef enum { HM_PREC_FP64 = 0, HM_PREC_FP32 = 1, HM_PREC_BF16X3 = 2 } hm_prec;
                                   hm_set_points instead of reading them from the device store */
 #define HM_FAR_FROM_POINTS 8u  /* FP64 only: compute the far blocks B_ab = K(X[skel_a], X[skel_b])
                                   from the points and the skeletons instead of reading them */
+#define HM_LEVEL_LAUNCHES 16u  /* FP64 / FP32 only: one launch per tree level (up levels, down
+                                  levels, leaf pass, permute-out) instead of the persistent
+                                  task-graph launch; same results to rounding */
 
 typedef struct hm_matrix_s *hm_matrix;
 
@@ -183,8 +186,12 @@ hm_status hm_eval(hm_matrix h, const void *W, int64_t ldw, void *Y, int64_t ldy,
  * (up to 15 the product tiles keep their points in LDS, above they read them
  * from global memory), ldx >= d, h > 0 (HM_ERR_INVALID otherwise).  Calling it again replaces the
  * points; they are freed with the matrix.  The caller may free X on return.
- * The points and kernel are not checked against the compressed blocks: other
- * points give the near field of other points. */
+ * d, kernel and h must equal the representation's metadata (d, kernel, h of
+ * hm_host_repr or the HMC1 header) when it states them (d > 0, h > 0):
+ * HM_ERR_INVALID otherwise, and the points are not replaced.  The point
+ * coordinates themselves cannot be checked: other points of that shape give
+ * the near field of other points.  On any error the previous points stay in
+ * place. */
 hm_status hm_set_points(hm_matrix h, const double *X, int64_t ldx, int64_t d, int kernel, double h_param);
 
 /* Synchronize the device and report whether any evaluation on h since the
@@ -242,42 +249,58 @@ hm_status hm_eval_batched(int n, const hm_matrix *hs, const void *const *W, cons
                           hm_prec prec, void *stream);
 
 /* ---------------------------------------------------------------------------
- * Serving: several compressed matrices resident in HBM, requests of any width
- * Q in [1, 1024] submitted without blocking and served by continuous
- * batching.  A server thread coalesces the pending requests of a matrix
- * column-wise into one sweep (one evaluation of up to 1024 columns) whenever
- * the matrix has no sweep in flight, a slot (stream) is free and the HBM
- * budget (packed W and Y of the sweeps in flight) allows it; requests that
- * arrive while a sweep of their matrix runs join the next one, and sweeps of
- * different matrices run on different streams and overlap on the device.  A
+ * Serving (no section of the paper: the served form of the evaluation of
+ * Section 2.1): several compressed matrices resident in HBM, requests of any
+ * width Q in [1, 1024] submitted without blocking and served by continuous
+ * batching.  A server thread owns max_slots slots; a slot is a stream with
+ * its own workspaces, sized when matrices are added for the largest of them
+ * at 1024 columns.  Whenever a slot is free and the HBM budget allows it, the
+ * pending requests of the next matrix (round robin) are coalesced
+ * column-wise into one sweep of up to 1024 columns: gathered from each
+ * request's W, evaluated by one persistent task-graph launch, scattered into
+ * each request's Y.  Requests that arrive while sweeps run join the next
+ * sweep a free slot takes, also for a matrix that already has a sweep in
+ * flight, so sweeps of one or several matrices overlap on the device.  A
  * result is bitwise the same alone and in the mix (column j of Y depends only
  * on column j of W).  Add every matrix before submitting work; the matrices
- * must outlive the server, and hm_eval must not be called on them while the
- * server runs (they share workspaces). */
+ * must outlive the server.  The server never touches a matrix's own
+ * workspaces, but it shares its store: do not free it while the server runs.
+ * Calls are thread-safe. */
 typedef struct hm_server_s *hm_server;
 typedef uint64_t hm_ticket;
 
 typedef struct {
     int64_t completed, failed, sweeps, columns, pending;
-    int32_t inflight, peak_inflight;
-    double peak_bytes;        /* largest HBM the packed sweeps held at once */
+    int32_t inflight, peak_inflight;   /* sweeps on the device now / at most at once */
+    double peak_bytes;        /* largest sum of 2 N Q x element size over the sweeps in flight */
 } hm_server_stats_t;
 
-/* max_slots: sweeps in flight at once (1..16); hbm_budget: bytes for packed
- * W/Y of sweeps in flight; dtype/prec as for hm_eval. */
+/* max_slots: sweeps in flight at once (1..16); hbm_budget: bound on the
+ * working set of the sweeps in flight, counted as 2 N Q x element size per
+ * sweep (its columns of W and Y); a sweep waits until it fits.  dtype/prec as
+ * for hm_eval (FP64 or FP32).  Creates the slots' streams and a server
+ * thread. */
 hm_status hm_server_create(int device, size_t hbm_budget, int max_slots, hm_dtype dtype,
                            hm_prec prec, hm_server *out);
-/* Make h resident (reserves its workspaces and launch plans for every sweep
- * width, so that sweeps never allocate); *mat_id names it in hm_submit. */
+/* Make h resident: builds its launch plans for every sweep width and grows
+ * the slots' workspaces and counters to fit it (so that sweeps never plan,
+ * allocate or upload); *mat_id names it in hm_submit.  HM_ERR_BUSY while
+ * sweeps are running. */
 hm_status hm_server_add(hm_server s, hm_matrix h, int *mat_id);
-/* Queue Y = K~ W for matrix mat_id (device pointers, N x Q row-major; they
- * must stay valid until hm_poll reports done).  Never blocks; HM_ERR_BUSY when
- * the request can never fit the budget or too many requests are queued. */
+/* Queue Y = K~ W for matrix mat_id (device pointers, N x Q row-major in the
+ * caller's point order; they must stay valid until hm_poll reports done).
+ * The request is ordered after the work enqueued on `stream` (a hipStream_t;
+ * NULL = the null stream) before this call: an event recorded there is
+ * waited for before the sweep reads W or writes Y.  Never blocks on the GPU;
+ * HM_ERR_BUSY when the request alone exceeds the budget or too many requests
+ * are queued. */
 hm_status hm_submit(hm_server s, int mat_id, const void *W, int64_t ldw, void *Y, int64_t ldy,
-                    int64_t Q, hm_ticket *out);
+                    int64_t Q, void *stream, hm_ticket *out);
 /* *done = 1 once Y is written (then *latency_us = submit-to-completion time
  * and the ticket is retired); *done = 0 while pending.  HM_ERR_INVALID for an
- * unknown or retired ticket. */
+ * unknown or retired ticket; HM_ERR_INTERNAL (ticket retired) when the
+ * sweep's launch hit its bounded dependency wait, so Y is invalid;
+ * HM_ERR_DEVICE when a HIP call of the sweep failed. */
 hm_status hm_poll(hm_server s, hm_ticket t, int *done, double *latency_us);
 hm_status hm_server_stats(hm_server s, hm_server_stats_t *out);
 /* Stop the server thread and wait for the sweeps in flight; queued requests

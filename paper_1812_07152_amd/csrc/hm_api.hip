@@ -212,7 +212,7 @@ hm_status hm_eval(hm_matrix h, const void *W, int64_t ldw, void *Y, int64_t ldy,
     if (Q == 0) return HM_OK;
     if (!W || !Y) return fail(HM_ERR_INVALID, "hm_eval: W or Y is NULL");
     if (ldw < Q || ldy < Q) return fail(HM_ERR_INVALID, "hm_eval: leading dimension < Q");
-    if (flags & ~(HM_TREE_ORDER | HM_PROFILE | HM_NEAR_FROM_POINTS | HM_FAR_FROM_POINTS))
+    if (flags & ~(HM_TREE_ORDER | HM_PROFILE | HM_NEAR_FROM_POINTS | HM_FAR_FROM_POINTS | HM_LEVEL_LAUNCHES))
         return fail(HM_ERR_INVALID, "hm_eval: unknown flags");
     if (!((dtype == HM_F64 && prec == HM_PREC_FP64) || (dtype == HM_F32 && prec == HM_PREC_FP32) ||
           (dtype == HM_F64 && prec == HM_PREC_BF16X3)))
@@ -225,8 +225,9 @@ hm_status hm_eval(hm_matrix h, const void *W, int64_t ldw, void *Y, int64_t ldy,
     if (ds.err != hipSuccess) return fail(HM_ERR_DEVICE, "hm_eval: cannot select the device");
     hipStream_t s = (hipStream_t)stream;
     const int es = dtype == HM_F64 ? 8 : 4, slot = dtype == HM_F64 ? 0 : 1;
-    const char *sched = std::getenv("HM_SCHED");
-    const bool level_sched = sched && std::string(sched) == "level" && !mixed;
+    if (mixed && (flags & HM_LEVEL_LAUNCHES))
+        return fail(HM_ERR_INVALID, "hm_eval: HM_PREC_BF16X3 runs on the task-graph launch only");
+    const bool level_sched = (flags & HM_LEVEL_LAUNCHES) != 0;
     const bool near_pts = (flags & HM_NEAR_FROM_POINTS) != 0, far_pts = (flags & HM_FAR_FROM_POINTS) != 0;
     const bool from_points = near_pts || far_pts;
     if (!near_pts && !h->near_stored)
@@ -332,6 +333,13 @@ hm_status hm_set_points(hm_matrix h, const double *X, int64_t ldx, int64_t d, in
     if (ldx < d) return fail(HM_ERR_INVALID, "hm_set_points: ldx < d");
     if (kernel != 0 && kernel != 1) return fail(HM_ERR_INVALID, "hm_set_points: unknown kernel");
     if (!(h_param > 0.0) || !std::isfinite(h_param)) return fail(HM_ERR_INVALID, "hm_set_points: h must be > 0");
+    // the points must be those the representation was compressed from: its
+    // metadata names d, the kernel and h (a representation that states none
+    // cannot be checked)
+    if (h->repr_d > 0 && d != h->repr_d)
+        return fail(HM_ERR_INVALID, "hm_set_points: d differs from the representation's");
+    if (h->repr_h > 0 && (kernel != h->repr_kernel || std::fabs(h_param - h->repr_h) > 1e-12 * h->repr_h))
+        return fail(HM_ERR_INVALID, "hm_set_points: kernel or h differs from the representation's");
     DeviceScope ds(h->device);
     if (ds.err != hipSuccess) return fail(HM_ERR_DEVICE, "hm_set_points: cannot select the device");
     // tree order: row t holds the point perm[t]
@@ -340,32 +348,29 @@ hm_status hm_set_points(hm_matrix h, const double *X, int64_t ldx, int64_t d, in
     std::vector<double> xt((size_t)h->N * (size_t)d);
     for (int64_t t = 0; t < h->N; t++)
         for (int64_t c = 0; c < d; c++) xt[(size_t)(t * d + c)] = X[perm[(size_t)t] * ldx + c];
-    HM_HIP(hipDeviceSynchronize());  // no evaluation may still read the old points
-    if (h->d_pts) {
-        (void)hipFree(h->d_pts);
-        h->d_pts = nullptr;
-    }
-    const hipError_t e = hipMalloc(&h->d_pts, sizeof(double) * xt.size());
-    if (e != hipSuccess) {
-        h->d_pts = nullptr;
-        return fail(e == hipErrorOutOfMemory ? HM_ERR_NOMEM : HM_ERR_DEVICE, "hm_set_points: device allocation");
-    }
-    HM_HIP(hipMemcpy(h->d_pts, xt.data(), sizeof(double) * xt.size(), hipMemcpyHostToDevice));
-    if (h->d_skel_pts) {
-        (void)hipFree(h->d_skel_pts);
-        h->d_skel_pts = nullptr;
-    }
-    if (!h->skel_row_pt.empty()) {  // skeleton points in Ŵ row order (for HM_FAR_FROM_POINTS)
-        std::vector<double> xs(h->skel_row_pt.size() * (size_t)d);
+    std::vector<double> xs;  // skeleton points in Ŵ row order (for HM_FAR_FROM_POINTS)
+    if (!h->skel_row_pt.empty()) {
+        xs.resize(h->skel_row_pt.size() * (size_t)d);
         for (size_t t = 0; t < h->skel_row_pt.size(); t++)
             for (int64_t c = 0; c < d; c++) xs[t * (size_t)d + (size_t)c] = X[h->skel_row_pt[t] * ldx + c];
-        const hipError_t es = hipMalloc(&h->d_skel_pts, sizeof(double) * xs.size());
-        if (es != hipSuccess) {
-            h->d_skel_pts = nullptr;
-            return fail(es == hipErrorOutOfMemory ? HM_ERR_NOMEM : HM_ERR_DEVICE, "hm_set_points: device allocation");
-        }
-        HM_HIP(hipMemcpy(h->d_skel_pts, xs.data(), sizeof(double) * xs.size(), hipMemcpyHostToDevice));
     }
+    // build the new buffers first; the matrix keeps its old points (and
+    // their d, kernel and scale) unless every step succeeds
+    struct Owned {
+        double *p = nullptr;
+        ~Owned() {
+            if (p) (void)hipFree(p);
+        }
+    } np_, ns_;
+    HM_HIP(hipMalloc(&np_.p, sizeof(double) * xt.size()));
+    HM_HIP(hipMemcpy(np_.p, xt.data(), sizeof(double) * xt.size(), hipMemcpyHostToDevice));
+    if (!xs.empty()) {
+        HM_HIP(hipMalloc(&ns_.p, sizeof(double) * xs.size()));
+        HM_HIP(hipMemcpy(ns_.p, xs.data(), sizeof(double) * xs.size(), hipMemcpyHostToDevice));
+    }
+    HM_HIP(hipDeviceSynchronize());  // no evaluation may still read the old points
+    std::swap(h->d_pts, np_.p);       // the old buffers are freed by the guards
+    std::swap(h->d_skel_pts, ns_.p);
     h->pts_d = (int32_t)d;
     h->pts_kern = kernel;
     h->pts_scale = kernel == 0 ? 1.0 / (2.0 * h_param * h_param) : 1.0 / h_param;

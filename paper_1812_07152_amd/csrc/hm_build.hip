@@ -470,6 +470,9 @@ hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_mat
                 h->skel_row_pt[(size_t)(wrow[a] + i)] = r.skel[(size_t)(r.skel_ptr[a] + i)];
     }
     h->N = r.N;
+    h->repr_d = r.d;
+    h->repr_kernel = r.kernel;
+    h->repr_h = r.h;
     h->n_nodes = n;
     h->depth = r.depth;
     for (int a = 0; a < n; a++) h->max_rank = std::max(h->max_rank, r.rank[a]);

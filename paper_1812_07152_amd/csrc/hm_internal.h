@@ -167,6 +167,19 @@ struct PermDesc {
     int64_t N, Q;
 };
 
+// One request of a served sweep: its columns [col0, col0 + Q) of the sweep
+// come from W (original order, leading dimension ldw) and go to Y.
+struct ReqDesc {
+    const void *W;
+    int64_t ldw;
+    void *Y;
+    int64_t ldy;
+    int64_t col0, Q;
+};
+// Widest served sweep (columns); a sweep's column -> request map is an int16
+// table of this length.
+constexpr int kServeMaxCols = 1024;
+
 // A node-level job of the evaluation's dependency graph (host side).
 struct GJob {
     int32_t kind;        // 1 up, 2 down, 3 near, 4 leaf far part
@@ -250,6 +263,10 @@ struct hm_matrix_s {
     double *d_skel_pts = nullptr;          // skel_rows x pts_d, Ŵ row order (with skeletons)
     int32_t pts_d = 0, pts_kern = 0;
     double pts_scale = 0;
+    // what the representation was compressed with (its metadata; 0 = not stated)
+    int64_t repr_d = 0;
+    int32_t repr_kernel = 0;
+    double repr_h = 0;
 };
 
 namespace hm {
@@ -269,8 +286,7 @@ hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_mat
 
 // Kernel launchers (hm_kernels.hip).
 // Column tile for Q columns (16..256) in a phase of the given kind (1 up,
-// 2 down, 3 leaf), honouring the HM_BN_UP / HM_BN_DOWN / HM_BN_LEAF / HM_BN
-// environment overrides.
+// 2 down, 3 leaf): the smallest tile that holds Q columns, at most 256.
 int pick_bn(int64_t Q, int kind);
 // Whether a persistent launch with column tile bn over elem_bytes elements
 // also has 32- and 96-row tiles (besides 64 and 128).  Not in mixed-precision
@@ -292,6 +308,13 @@ hipError_t launch_permute_in(const void *W, int64_t ldw, void *Wt, int64_t Qp, c
 hipError_t launch_permute_out(const void *Yt, int64_t Qp, void *Y, int64_t ldy, const int64_t *perm,
                               int64_t N, int64_t Q, int elem_bytes, hipStream_t s);
 hipError_t launch_convert_f64_to_f32(const double *src, float *dst, int64_t n, hipStream_t s);
+// Served sweep: Wt[t * ldt + c] = W_r[perm[t] * ldw_r + c - col0_r] for the
+// request r = col2req[c] owning column c < cols, zero for cols <= c < width.
+hipError_t launch_gather_in(const ReqDesc *reqs, const int16_t *col2req, int64_t cols, int64_t width,
+                            void *Wt, int64_t ldt, const int64_t *perm, int64_t N, int elem_bytes, hipStream_t s);
+// Served sweep: Y_r[perm[t] * ldy_r + c - col0_r] = Yt[t * ldt + c] for c < cols.
+hipError_t launch_scatter_out(const ReqDesc *reqs, const int16_t *col2req, int64_t cols, const void *Yt,
+                              int64_t ldt, const int64_t *perm, int64_t N, int elem_bytes, hipStream_t s);
 // Split-BF16 copies of blocks (one per segment) of the FP64 store.
 // W (original order, ldw, FP64) -> split-BF16 W in tree order (see Split16),
 // one 32-row chunk per (chunks entry, column); columns >= Q and rows past a
@@ -316,9 +339,12 @@ struct OutScatter {
     const int64_t *perm = nullptr;
     bool from_points = false;  // FP64: the launch that computes near and/or far blocks from points
 };
-// Persistent launch of a plan (init + graph kernel) on stream s.
+// Persistent launch of a plan (init + graph kernel) on stream s.  counters:
+// the dependency counters to use (one per queue entry), or null for the
+// plan's own (launches that may overlap on one plan need their own).
 hipError_t launch_persistent(const GraphPlan &plan, int elem_bytes, const MatDesc *d_mat,
-                             int32_t *d_head, int grid, hipStream_t s, const OutScatter &out = OutScatter{});
+                             int32_t *d_head, int grid, hipStream_t s, const OutScatter &out = OutScatter{},
+                             int32_t *counters = nullptr);
 // Resident workgroups per CU of the persistent kernel for (elem_bytes, bn).
 int persistent_occupancy(int elem_bytes, int bn, bool split = false);
 

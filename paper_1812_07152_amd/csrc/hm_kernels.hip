@@ -24,7 +24,6 @@
 // B[l/16][l%16]; accumulator register r of lane l holds D[4r + l/16][l%16]
 // for FP64 and D[4(l/16) + r][l%16] for FP32.
 #include <algorithm>
-#include <cstdlib>
 
 #include "hm_internal.h"
 
@@ -1308,6 +1307,37 @@ __global__ void k_permute_out_batched(const PermDesc *__restrict__ d) {
     }
 }
 
+// Served sweeps: the columns of a sweep belong to several requests (col2req
+// maps a column to its request).  One thread per (tree row, column).
+template <typename T>
+__global__ void k_gather_in(const ReqDesc *__restrict__ reqs, const int16_t *__restrict__ col2req, int64_t cols,
+                            int64_t width, T *__restrict__ Wt, int64_t ldt, const int64_t *__restrict__ perm,
+                            int64_t N) {
+    const int64_t total = N * width;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t t = e / width, c = e % width;
+        T v = T(0);
+        if (c < cols) {
+            const ReqDesc &r = reqs[col2req[c]];
+            v = ((const T *)r.W)[perm[t] * r.ldw + (c - r.col0)];
+        }
+        Wt[t * ldt + c] = v;
+    }
+}
+
+template <typename T>
+__global__ void k_scatter_out(const ReqDesc *__restrict__ reqs, const int16_t *__restrict__ col2req, int64_t cols,
+                              const T *__restrict__ Yt, int64_t ldt, const int64_t *__restrict__ perm, int64_t N) {
+    const int64_t total = N * cols;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t t = e / cols, c = e % cols;
+        const ReqDesc &r = reqs[col2req[c]];
+        ((T *)r.Y)[perm[t] * r.ldy + (c - r.col0)] = Yt[t * ldt + c];
+    }
+}
+
 __global__ void k_f64_to_f32(const double *__restrict__ s, float *__restrict__ d, int64_t n) {
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
          e += (int64_t)gridDim.x * blockDim.x)
@@ -1354,12 +1384,7 @@ hipError_t dispatch(const hm_matrix_s *h, const Phase &ph, int bn, int64_t ldq,
 }  // namespace
 
 int pick_bn(int64_t Q, int kind) {
-    static const char *names[4] = {"HM_BN", "HM_BN_UP", "HM_BN_DOWN", "HM_BN_LEAF"};
-    for (const char *nm : {names[kind >= 1 && kind <= 3 ? kind : 0], names[0]})
-        if (const char *e = std::getenv(nm)) {
-            int v = std::atoi(e);
-            if (v == 16 || v == 32 || v == 64 || v == 128 || v == 256) return v;
-        }
+    (void)kind;
     if (Q <= 16) return 16;
     if (Q <= 32) return 32;
     if (Q <= 64) return 64;
@@ -1368,7 +1393,6 @@ int pick_bn(int64_t Q, int kind) {
 }
 
 int graph_bn(int64_t Q, int elem_bytes, bool split, double task_k) {
-    if (std::getenv("HM_BN")) return pick_bn(Q, 0);
     const int bn = pick_bn(Q, 3);
     // Tiles up to 128 columns fit two workgroups per compute unit (at most
     // 128 VGPRs, see k_persistent), so one workgroup's task switches (fetch,
@@ -1392,14 +1416,14 @@ namespace {
 
 template <typename T, int BN>
 hipError_t run_persistent(const GraphPlan &plan, const MatDesc *mats, int32_t *head, int grid,
-                          const OutScatter &out, hipStream_t s) {
+                          const OutScatter &out, int32_t *counters, hipStream_t s) {
     const int nt = plan.n_tasks;
     hipLaunchKernelGGL(k_persistent_init, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s,
-                       plan.d_tasks, nt, plan.d_counters, head);
+                       plan.d_tasks, nt, counters, head);
     if constexpr (sizeof(T) == 8 && BN != 64) {
         if (out.from_points) {
             hipLaunchKernelGGL((k_persistent<T, BN, false, true>), dim3((unsigned)grid), dim3(kPersistThreads), 0,
-                               s, plan.d_tasks, nt, plan.d_succ, plan.d_counters, head, head + 1, mats, out.Y,
+                               s, plan.d_tasks, nt, plan.d_succ, counters, head, head + 1, mats, out.Y,
                                out.ldy, out.Q, out.perm);
             return hipGetLastError();
         }
@@ -1407,24 +1431,24 @@ hipError_t run_persistent(const GraphPlan &plan, const MatDesc *mats, int32_t *h
     if (out.from_points) return hipErrorInvalidValue;
     if (sizeof(T) == 8 && plan.mode == 1)
         hipLaunchKernelGGL((k_persistent<T, BN, true>), dim3((unsigned)grid), dim3(kPersistThreads), 0,
-                           s, plan.d_tasks, nt, plan.d_succ, plan.d_counters, head, head + 1, mats, out.Y,
+                           s, plan.d_tasks, nt, plan.d_succ, counters, head, head + 1, mats, out.Y,
                            out.ldy, out.Q, out.perm);
     else
         hipLaunchKernelGGL((k_persistent<T, BN, false>), dim3((unsigned)grid), dim3(kPersistThreads), 0,
-                           s, plan.d_tasks, nt, plan.d_succ, plan.d_counters, head, head + 1, mats, out.Y,
+                           s, plan.d_tasks, nt, plan.d_succ, counters, head, head + 1, mats, out.Y,
                            out.ldy, out.Q, out.perm);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t persistent_bn(const GraphPlan &plan, const MatDesc *mats, int32_t *head, int grid,
-                         const OutScatter &out, hipStream_t s) {
+                         const OutScatter &out, int32_t *counters, hipStream_t s) {
     switch (plan.bn) {
-        case 16: return run_persistent<T, 16>(plan, mats, head, grid, out, s);
-        case 32: return run_persistent<T, 32>(plan, mats, head, grid, out, s);
-        case 64: return run_persistent<T, 64>(plan, mats, head, grid, out, s);
-        case 128: return run_persistent<T, 128>(plan, mats, head, grid, out, s);
-        default: return run_persistent<T, 256>(plan, mats, head, grid, out, s);
+        case 16: return run_persistent<T, 16>(plan, mats, head, grid, out, counters, s);
+        case 32: return run_persistent<T, 32>(plan, mats, head, grid, out, counters, s);
+        case 64: return run_persistent<T, 64>(plan, mats, head, grid, out, counters, s);
+        case 128: return run_persistent<T, 128>(plan, mats, head, grid, out, counters, s);
+        default: return run_persistent<T, 256>(plan, mats, head, grid, out, counters, s);
     }
 }
 
@@ -1445,10 +1469,12 @@ int occupancy_bn(int bn) {
 }  // namespace
 
 hipError_t launch_persistent(const GraphPlan &plan, int elem_bytes, const MatDesc *d_mat,
-                             int32_t *d_head, int grid, hipStream_t s, const OutScatter &out) {
+                             int32_t *d_head, int grid, hipStream_t s, const OutScatter &out,
+                             int32_t *counters) {
     if (plan.n_tasks == 0) return hipSuccess;
-    return elem_bytes == 8 ? persistent_bn<double>(plan, d_mat, d_head, grid, out, s)
-                           : persistent_bn<float>(plan, d_mat, d_head, grid, out, s);
+    int32_t *c = counters ? counters : plan.d_counters;
+    return elem_bytes == 8 ? persistent_bn<double>(plan, d_mat, d_head, grid, out, c, s)
+                           : persistent_bn<float>(plan, d_mat, d_head, grid, out, c, s);
 }
 
 int persistent_occupancy(int elem_bytes, int bn, bool split) {
@@ -1518,6 +1544,30 @@ hipError_t launch_make_bf16x3(const double *store, const Seg *segs, int nsegs, v
     if (nsegs == 0) return hipSuccess;
     hipLaunchKernelGGL(k_make_bf16x3, dim3((unsigned)nsegs), dim3(256), 0, s, store, segs,
                        (__bf16 *)store16);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_in(const ReqDesc *reqs, const int16_t *col2req, int64_t cols, int64_t width,
+                            void *Wt, int64_t ldt, const int64_t *perm, int64_t N, int elem_bytes, hipStream_t s) {
+    const int g = grid_for(N * width, 256);
+    if (elem_bytes == 8)
+        hipLaunchKernelGGL(k_gather_in<double>, dim3(g), dim3(256), 0, s, reqs, col2req, cols, width, (double *)Wt,
+                           ldt, perm, N);
+    else
+        hipLaunchKernelGGL(k_gather_in<float>, dim3(g), dim3(256), 0, s, reqs, col2req, cols, width, (float *)Wt,
+                           ldt, perm, N);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_out(const ReqDesc *reqs, const int16_t *col2req, int64_t cols, const void *Yt,
+                              int64_t ldt, const int64_t *perm, int64_t N, int elem_bytes, hipStream_t s) {
+    const int g = grid_for(N * cols, 256);
+    if (elem_bytes == 8)
+        hipLaunchKernelGGL(k_scatter_out<double>, dim3(g), dim3(256), 0, s, reqs, col2req, cols,
+                           (const double *)Yt, ldt, perm, N);
+    else
+        hipLaunchKernelGGL(k_scatter_out<float>, dim3(g), dim3(256), 0, s, reqs, col2req, cols,
+                           (const float *)Yt, ldt, perm, N);
     return hipGetLastError();
 }
 

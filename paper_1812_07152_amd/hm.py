@@ -18,7 +18,7 @@ HM_OK, HM_ERR_INVALID, HM_ERR_FORMAT, HM_ERR_NOMEM = 0, -1, -2, -3
 HM_ERR_DEVICE, HM_ERR_BUSY, HM_ERR_PENDING, HM_ERR_INTERNAL = -4, -5, -6, -7
 HM_F64, HM_F32 = 0, 1
 HM_PREC_FP64, HM_PREC_FP32, HM_PREC_BF16X3 = 0, 1, 2
-HM_TREE_ORDER, HM_PROFILE, HM_NEAR_FROM_POINTS, HM_FAR_FROM_POINTS = 1, 2, 4, 8
+HM_TREE_ORDER, HM_PROFILE, HM_NEAR_FROM_POINTS, HM_FAR_FROM_POINTS, HM_LEVEL_LAUNCHES = 1, 2, 4, 8, 16
 HM_LOAD_NO_NEAR_BLOCKS, HM_LOAD_NO_FAR_BLOCKS = 1 << 8, 1 << 9
 HM_BATCH_AUTOTUNE, HM_BATCH_NO_GRAPH = 1, 2
 STATUS_NAMES = {0: "HM_OK", -1: "HM_ERR_INVALID", -2: "HM_ERR_FORMAT", -3: "HM_ERR_NOMEM",
@@ -127,7 +127,7 @@ def _load():
     L.hm_server_add.argtypes = [_P, _P, ctypes.POINTER(ctypes.c_int)]
     L.hm_submit.restype = st
     L.hm_submit.argtypes = [_P, ctypes.c_int, _P, ctypes.c_int64, _P, ctypes.c_int64, ctypes.c_int64,
-                            ctypes.POINTER(ctypes.c_uint64)]
+                            _P, ctypes.POINTER(ctypes.c_uint64)]
     L.hm_poll.restype = st
     L.hm_poll.argtypes = [_P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]
     L.hm_server_stats.restype = st
@@ -211,6 +211,13 @@ def host_repr(src, skeletons: bool = True) -> tuple[hm_host_repr, list]:
         setattr(r, nme, arr(nme, np.float64))
     r.N = int(src.N)
     r.d = int(getattr(src, "d", 0))
+    # metadata: what the representation was compressed with (checked by hm_set_points)
+    params = getattr(src, "params", None) or {}
+    for k in ("kernel", "h", "tol", "tau", "rmax", "m"):
+        if k in params:
+            setattr(r, k, params[k])
+    if params.get("adm") == 1:
+        r.flags = 1
     r.n_nodes = int(src.n_nodes)
     r.depth = int(np.max(src.level))
     r.n_far, r.n_near = len(src.far_col), len(src.near_col)
@@ -470,8 +477,10 @@ def hm_server_add(s: Server, h: Matrix) -> int:
     return mid.value
 
 
-def hm_submit(s: Server, mat_id: int, W, Y, Q: int | None = None) -> int:
-    """Queue Y = K~ W (device tensors; keep them alive until hm_poll says done)."""
+def hm_submit(s: Server, mat_id: int, W, Y, Q: int | None = None, stream=None) -> int:
+    """Queue Y = K~ W (device tensors; keep them alive until hm_poll says done).
+    The request runs after the work enqueued on `stream` (default: torch's
+    current stream) before the call, e.g. the kernels that wrote W."""
     import torch
     want = torch.float64 if s.dtype == HM_F64 else torch.float32
     if not (W.is_cuda and Y.is_cuda) or W.dtype != want or Y.dtype != want:
@@ -485,7 +494,7 @@ def hm_submit(s: Server, mat_id: int, W, Y, Q: int | None = None) -> int:
             raise ValueError("hm_submit: tensors too small")
     t = ctypes.c_uint64()
     _check(lib.hm_submit(s.handle, mat_id, W.data_ptr(), W.stride(0), Y.data_ptr(), Y.stride(0), Q,
-                         ctypes.byref(t)))
+                         _stream_ptr(stream), ctypes.byref(t)))
     return t.value
 
 

@@ -53,11 +53,6 @@ def hmx():
     return hmx
 
 
-@pytest.fixture(autouse=True)
-def graph_launch(monkeypatch):
-    monkeypatch.delenv("HM_SCHED", raising=False)
-
-
 def built(name):
     if name not in _built:
         w = CASES[name]

@@ -25,12 +25,22 @@ def _say(msg):
     sys.stdout.flush()
 
 
+_SCHED = {"flags": 0}
+
+
 @pytest.fixture(params=["graph", "level"], autouse=True)
-def sched(request, monkeypatch):
+def sched(request):
     """Run each test under both launch styles: the persistent task-graph
-    launch (default) and one launch per tree level."""
-    monkeypatch.setenv("HM_SCHED", request.param)
-    return request.param
+    launch (default) and one launch per tree level (HM_LEVEL_LAUNCHES)."""
+    import paper_1812_07152_amd as hmx
+    _SCHED["flags"] = hmx.HM_LEVEL_LAUNCHES if request.param == "level" else 0
+    yield request.param
+    _SCHED["flags"] = 0
+
+
+def ev(hmx, M, W, Y, flags=0, **kw):
+    """hm_eval under the launch style of the running test."""
+    hmx.hm_eval(M, W, Y, flags=flags | _SCHED["flags"], **kw)
 
 
 @pytest.fixture(scope="module")
@@ -67,7 +77,7 @@ def gpu_eval(hmx, M, W, prec_f64=True, flags=0, Q=None):
     dt = torch.float64 if prec_f64 else torch.float32
     Wd = torch.from_numpy(W).to("cuda", dt)
     Yd = torch.full_like(Wd, float("nan"))
-    hmx.hm_eval(M, Wd, Yd, Q=Q, flags=flags)
+    ev(hmx, M, Wd, Yd, Q=Q, flags=flags)
     hmx.hm_check(M)  # synchronizes; raises if a bounded wait expired
     return Yd.double().cpu().numpy()
 
@@ -120,14 +130,14 @@ def test_tree_order_flag_and_strided_views(hmx):
     # tree order: W rows permuted by perm, Y returned in tree order
     Wt = torch.from_numpy(W[H.perm]).cuda()
     Yt = torch.empty_like(Wt)
-    hmx.hm_eval(M, Wt, Yt, flags=hmx.HM_TREE_ORDER)
+    ev(hmx, M, Wt, Yt, flags=hmx.HM_TREE_ORDER)
     torch.cuda.synchronize()
     check_f64(Yt.cpu().numpy(), Yref[H.perm])
     # strided: W and Y are column slices of wider buffers (ld > Q)
     big_w = torch.zeros(w.N, w.Q + 11, dtype=torch.float64, device="cuda")
     big_y = torch.full((w.N, w.Q + 5), 7.0, dtype=torch.float64, device="cuda")
     big_w[:, 3:3 + w.Q] = torch.from_numpy(W).cuda()
-    hmx.hm_eval(M, big_w[:, 3:], big_y, Q=w.Q)
+    ev(hmx, M, big_w[:, 3:], big_y, Q=w.Q)
     torch.cuda.synchronize()
     out = big_y.cpu().numpy()
     check_f64(out[:, :w.Q], Yref)
@@ -149,7 +159,7 @@ def test_q_zero_and_bad_arguments(hmx):
     M = hmx.hm_load_compressed_mem(H, 0)
     W = torch.zeros(w.N, 4, dtype=torch.float64, device="cuda")
     Y = torch.zeros_like(W)
-    hmx.hm_eval(M, W, Y, Q=0)      # valid no-op
+    ev(hmx, M, W, Y, Q=0)      # valid no-op
     from paper_1812_07152_amd import hm
     st = hm.lib.hm_eval(M.handle, W.data_ptr(), 4, Y.data_ptr(), 2, 4, hm.HM_F64, hm.HM_PREC_FP64, 0, None)
     assert st == hm.HM_ERR_INVALID          # ldy < Q
@@ -167,7 +177,8 @@ def test_c2_full_size_sampled_columns(hmx, sched):
     w = wl.C2
     _say("[parity] c2 full size: oracle compression")
     H = OracleH2.from_workload(w, wl.gen_points(w))
-    M = hmx.hm_load_compressed_mem(H, 0, hmx.precbit(hmx.HM_PREC_FP64) | hmx.precbit(hmx.HM_PREC_BF16X3))
+    M = hmx.hm_load_compressed_mem(H, 0, hmx.precbit(hmx.HM_PREC_FP64) | hmx.precbit(hmx.HM_PREC_BF16X3)
+                                   | hmx.precbit(hmx.HM_PREC_FP32))
     W = wl.gen_w(w)
     _say("[parity] c2 full size: gpu eval Q=256")
     Y = gpu_eval(hmx, M, W)
@@ -184,6 +195,20 @@ def test_c2_full_size_sampled_columns(hmx, sched):
         err = rel(Yd.cpu().numpy()[:, cols], Yref)
         _say(f"[mixed] case=c2 full size rel err={err:.3e}")
         assert err <= w.tol
+        # FP32 at full size, against the oracle on the FP32-rounded columns.
+        # Bar 2e-5: FP32 rounding of the blocks and of W (2^-24 each) plus
+        # FP32 accumulation over the near field's contraction, about 238
+        # leaves x 128 points = 30 000 terms (sqrt(K) 2^-24 ~ 1e-5 per
+        # product in the worst case, far less in the Frobenius norm)
+        _say("[parity] c2 full size: FP32 eval Q=256")
+        W32 = torch.from_numpy(W).to("cuda", torch.float32)
+        Y32 = torch.full_like(W32, float("nan"))
+        hmx.hm_eval(M, W32, Y32)
+        hmx.hm_check(M)
+        Yref32 = H.eval(np.ascontiguousarray(W[:, cols].astype(np.float32).astype(np.float64)))
+        err32 = rel(Y32.double().cpu().numpy()[:, cols], Yref32)
+        _say(f"[fp32] case=c2 full size rel err={err32:.3e}")
+        assert err32 <= 2e-5
 
 
 @pytest.mark.parametrize("name", ["c1", "mix8", "hss_lap", "deep_small_leaves"])
