@@ -171,6 +171,37 @@ hm_status hm_free(hm_matrix h);
 hm_status hm_eval(hm_matrix h, const void *W, int64_t ldw, void *Y, int64_t ldy, int64_t Q,
                   hm_dtype dtype, hm_prec prec, unsigned flags, void *stream);
 
+/* Bytes of the fixed device array behind hm_eval_noalloc (64 MiB per device). */
+#define HM_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, results (bitwise) and asynchrony as hm_eval, but the
+ * per-call device memory (W in tree order, the skeleton weights and
+ * potentials, their split-BF16 copies, the dependency counters and the
+ * launch descriptor) comes from one fixed array of HM_NOALLOC_SCRATCH_BYTES
+ * in device memory, which each device the library runs on holds until the
+ * process ends.  The call makes no hipMalloc, hipFree or other allocating
+ * call and no host-device copy: it enqueues kernels only.
+ *   - Limit: an evaluation that needs more than HM_NOALLOC_SCRATCH_BYTES
+ *     (about N*Q'*s + 2*R*Q'*s bytes, with Q' = Q rounded up to the column
+ *     tile, s the element size and R the total skeleton rank; the split
+ *     copies add 4 bytes a value) returns HM_ERR_INVALID and launches nothing.
+ *   - The task graph of the evaluation (per column-tile count, element type
+ *     and precision) must already exist: one hm_eval on h with the same
+ *     dtype, precision and a Q in the same column-tile class builds it.
+ *     HM_ERR_INVALID otherwise (and after it has been evicted: a matrix keeps
+ *     the 16 most recent graphs per element type).
+ *   - flags: HM_TREE_ORDER, HM_NEAR_FROM_POINTS, HM_FAR_FROM_POINTS as for
+ *     hm_eval; HM_LEVEL_LAUNCHES and HM_PROFILE return HM_ERR_INVALID.
+ *   - Every call on one device shares that device's array and leaves its
+ *     contents behind (each call initialises what it reads).  Calls that
+ *     overlap on one device race, whatever their matrices and streams: the
+ *     caller serializes them (one stream, or events).  An expired dependency
+ *     wait is reported by hm_check(h), as for hm_eval. */
+hm_status hm_eval_noalloc(hm_matrix h, const void *W, int64_t ldw, void *Y, int64_t ldy, int64_t Q,
+                          hm_dtype dtype, hm_prec prec, unsigned flags, void *stream);
+
 /* Matrix-free blocks (Section 2.1: a near block is the kernel matrix of
  * two leaves, K(X[I_a], X[I_b])).  Copies the N points (row i at X + i*ldx,
  * d coordinates, FP64, the caller's original point order, host memory) to the

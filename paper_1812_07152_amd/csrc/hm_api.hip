@@ -102,6 +102,55 @@ hm_status record(hm_matrix h, int group, hipStream_t s, hipEvent_t *ev) {
 }
 
 }  // namespace
+
+hm_status eval_setup(const char *who, hm_matrix h, const void *W, int64_t ldw, void *Y, int64_t ldy, int64_t Q,
+                     hm_dtype dtype, hm_prec prec, unsigned flags, EvalSetup &o) {
+    const std::string w = std::string(who) + ": ";
+    if (!h) return fail(HM_ERR_INVALID, w + "matrix handle is NULL");
+    if (Q < 0) return fail(HM_ERR_INVALID, w + "Q < 0");
+    if (Q == 0) return HM_OK;
+    if (!W || !Y) return fail(HM_ERR_INVALID, w + "W or Y is NULL");
+    if (ldw < Q || ldy < Q) return fail(HM_ERR_INVALID, w + "leading dimension < Q");
+    if (flags & ~(HM_TREE_ORDER | HM_PROFILE | HM_NEAR_FROM_POINTS | HM_FAR_FROM_POINTS | HM_LEVEL_LAUNCHES))
+        return fail(HM_ERR_INVALID, w + "unknown flags");
+    if (!((dtype == HM_F64 && prec == HM_PREC_FP64) || (dtype == HM_F32 && prec == HM_PREC_FP32) ||
+          (dtype == HM_F64 && prec == HM_PREC_BF16X3)))
+        return fail(HM_ERR_INVALID, w + "dtype and precision do not match");
+    o.mixed = prec == HM_PREC_BF16X3;
+    if (o.mixed ? !(h->store16 && h->prec[HM_PREC_FP64].blocks) : !h->prec[prec].blocks)
+        return fail(HM_ERR_INVALID, w + "precision was not loaded");
+    if (Q > (int64_t)1 << 24) return fail(HM_ERR_INVALID, w + "Q too large");
+    o.es = dtype == HM_F64 ? 8 : 4;
+    o.slot = dtype == HM_F64 ? 0 : 1;
+    if (o.mixed && (flags & HM_LEVEL_LAUNCHES))
+        return fail(HM_ERR_INVALID, w + "HM_PREC_BF16X3 runs on the task-graph launch only");
+    o.level_sched = (flags & HM_LEVEL_LAUNCHES) != 0;
+    o.near_pts = (flags & HM_NEAR_FROM_POINTS) != 0;
+    o.far_pts = (flags & HM_FAR_FROM_POINTS) != 0;
+    o.from_points = o.near_pts || o.far_pts;
+    if (!o.near_pts && !h->near_stored)
+        return fail(HM_ERR_INVALID, w + "the near blocks were not loaded (use HM_NEAR_FROM_POINTS)");
+    if (!o.far_pts && !h->far_stored)
+        return fail(HM_ERR_INVALID, w + "the far blocks were not loaded (use HM_FAR_FROM_POINTS)");
+    if (o.from_points && (prec != HM_PREC_FP64 || !h->d_pts || o.level_sched))
+        return fail(HM_ERR_INVALID, w + "HM_NEAR_FROM_POINTS and HM_FAR_FROM_POINTS need HM_PREC_FP64, "
+                                        "points set with hm_set_points and the task-graph launch");
+    if (o.far_pts && !h->d_skel_pts)
+        return fail(HM_ERR_INVALID, w + "HM_FAR_FROM_POINTS needs a representation loaded with its skeletons");
+    int *bk = o.bn_kind;
+    bk[0] = 0;
+    bk[1] = pick_bn(Q, 1);
+    bk[2] = pick_bn(Q, 2);
+    bk[3] = pick_bn(Q, 3);
+    if (!o.level_sched) bk[1] = bk[2] = bk[3] = graph_bn(Q, o.es, o.mixed, h->task_k);  // one tile for the graph
+    if (o.from_points && bk[3] == 64) bk[1] = bk[2] = bk[3] = 128;  // see k_persistent
+    const int bn_max = std::max({bk[1], bk[2], bk[3]});
+    o.Qp = (Q + bn_max - 1) / bn_max * bn_max;  // workspace leading dimension
+    o.perm = (flags & HM_TREE_ORDER) ? nullptr : h->d_perm;
+    o.valid = true;
+    return HM_OK;
+}
+
 }  // namespace hm
 
 using namespace hm;
@@ -207,44 +256,19 @@ hm_status hm_free(hm_matrix h) {
 
 hm_status hm_eval(hm_matrix h, const void *W, int64_t ldw, void *Y, int64_t ldy, int64_t Q,
                   hm_dtype dtype, hm_prec prec, unsigned flags, void *stream) {
-    if (!h) return fail(HM_ERR_INVALID, "hm_eval: matrix handle is NULL");
-    if (Q < 0) return fail(HM_ERR_INVALID, "hm_eval: Q < 0");
-    if (Q == 0) return HM_OK;
-    if (!W || !Y) return fail(HM_ERR_INVALID, "hm_eval: W or Y is NULL");
-    if (ldw < Q || ldy < Q) return fail(HM_ERR_INVALID, "hm_eval: leading dimension < Q");
-    if (flags & ~(HM_TREE_ORDER | HM_PROFILE | HM_NEAR_FROM_POINTS | HM_FAR_FROM_POINTS | HM_LEVEL_LAUNCHES))
-        return fail(HM_ERR_INVALID, "hm_eval: unknown flags");
-    if (!((dtype == HM_F64 && prec == HM_PREC_FP64) || (dtype == HM_F32 && prec == HM_PREC_FP32) ||
-          (dtype == HM_F64 && prec == HM_PREC_BF16X3)))
-        return fail(HM_ERR_INVALID, "hm_eval: dtype and precision do not match");
-    const bool mixed = prec == HM_PREC_BF16X3;
-    if (mixed ? !(h->store16 && h->prec[HM_PREC_FP64].blocks) : !h->prec[prec].blocks)
-        return fail(HM_ERR_INVALID, "hm_eval: precision was not loaded");
-    if (Q > (int64_t)1 << 24) return fail(HM_ERR_INVALID, "hm_eval: Q too large");
+    EvalSetup e;
+    {
+        hm_status vst = eval_setup("hm_eval", h, W, ldw, Y, ldy, Q, dtype, prec, flags, e);
+        if (vst != HM_OK || !e.valid) return vst;  // Q = 0: nothing to do
+    }
     DeviceScope ds(h->device);
     if (ds.err != hipSuccess) return fail(HM_ERR_DEVICE, "hm_eval: cannot select the device");
     hipStream_t s = (hipStream_t)stream;
-    const int es = dtype == HM_F64 ? 8 : 4, slot = dtype == HM_F64 ? 0 : 1;
-    if (mixed && (flags & HM_LEVEL_LAUNCHES))
-        return fail(HM_ERR_INVALID, "hm_eval: HM_PREC_BF16X3 runs on the task-graph launch only");
-    const bool level_sched = (flags & HM_LEVEL_LAUNCHES) != 0;
-    const bool near_pts = (flags & HM_NEAR_FROM_POINTS) != 0, far_pts = (flags & HM_FAR_FROM_POINTS) != 0;
-    const bool from_points = near_pts || far_pts;
-    if (!near_pts && !h->near_stored)
-        return fail(HM_ERR_INVALID, "hm_eval: the near blocks were not loaded (use HM_NEAR_FROM_POINTS)");
-    if (!far_pts && !h->far_stored)
-        return fail(HM_ERR_INVALID, "hm_eval: the far blocks were not loaded (use HM_FAR_FROM_POINTS)");
-    if (from_points && (prec != HM_PREC_FP64 || !h->d_pts || level_sched))
-        return fail(HM_ERR_INVALID, "hm_eval: HM_NEAR_FROM_POINTS and HM_FAR_FROM_POINTS need HM_PREC_FP64, "
-                                    "points set with hm_set_points and the task-graph launch");
-    if (far_pts && !h->d_skel_pts)
-        return fail(HM_ERR_INVALID, "hm_eval: HM_FAR_FROM_POINTS needs a representation loaded with its "
-                                    "skeletons");
-    int bn_kind[4] = {0, pick_bn(Q, 1), pick_bn(Q, 2), pick_bn(Q, 3)};
-    if (!level_sched) bn_kind[1] = bn_kind[2] = bn_kind[3] = graph_bn(Q, es, mixed, h->task_k);  // one tile for the graph
-    if (from_points && bn_kind[3] == 64) bn_kind[1] = bn_kind[2] = bn_kind[3] = 128;  // see k_persistent
-    const int bn_max = std::max({bn_kind[1], bn_kind[2], bn_kind[3]});
-    const int64_t Qp = (Q + bn_max - 1) / bn_max * bn_max;  // workspace leading dimension
+    const int es = e.es, slot = e.slot;
+    const bool mixed = e.mixed, level_sched = e.level_sched, near_pts = e.near_pts, far_pts = e.far_pts,
+               from_points = e.from_points;
+    const int *bn_kind = e.bn_kind;
+    const int64_t Qp = e.Qp;
     {
         hm_status st = reserve_ws(h, slot, Qp);
         // split workspaces: W (leaf rows), Ŵ and Ŷ (skeleton rows), 4 bytes a value
@@ -256,13 +280,12 @@ hm_status hm_eval(hm_matrix h, const void *W, int64_t ldw, void *Y, int64_t ldy,
     void *bufs[BUF_COUNT];
     for (int b = 0; b < BUF_COUNT; b++) bufs[b] = h->ws[slot][b];
     const bool prof = (flags & HM_PROFILE) != 0;
-    const int64_t *perm = (flags & HM_TREE_ORDER) ? nullptr : h->d_perm;
+    const int64_t *perm = e.perm;
 
     int grid = 0;
     GraphPlan *plan = nullptr;
     if (!level_sched) {
-        const int occ = persistent_occupancy(es, bn_kind[3], mixed);
-        const int workers = std::max(1, occ * h->n_cu);
+        const int workers = std::max(1, persistent_occupancy(es, bn_kind[3], mixed) * h->n_cu);
         hm_status pst = get_plan(h, slot, bn_kind[3], Qp, workers, &plan, mixed ? 1 : 0);
         if (pst != HM_OK) return pst;
         MatDesc md{h->prec[mixed ? HM_PREC_FP64 : prec].blocks, {bufs[0], bufs[1], bufs[2], bufs[3]},

@@ -339,6 +339,19 @@ struct OutScatter {
     const int64_t *perm = nullptr;
     bool from_points = false;  // FP64: the launch that computes near and/or far blocks from points
 };
+// Validated arguments of one evaluation and the launch shape they imply.
+struct EvalSetup {
+    bool valid = false;   // false with HM_OK: Q = 0, nothing to do
+    int es = 8, slot = 0; // element bytes of W and Y; workspace / plan slot (0 FP64, 1 FP32)
+    bool mixed = false, level_sched = false, near_pts = false, far_pts = false, from_points = false;
+    int bn_kind[4] = {0, 0, 0, 0};  // column tile per phase kind (1 up, 2 down, 3 leaf); one tile for the graph
+    int64_t Qp = 0;                 // workspace leading dimension (Q rounded up to the column tile)
+    const int64_t *perm = nullptr;  // tree position -> caller's row (null with HM_TREE_ORDER)
+};
+// Validate hm_eval's arguments against h (no device work, messages prefixed
+// by `who`) and derive the tiles and the workspace leading dimension.
+hm_status eval_setup(const char *who, hm_matrix h, const void *W, int64_t ldw, void *Y, int64_t ldy, int64_t Q,
+                     hm_dtype dtype, hm_prec prec, unsigned flags, EvalSetup &out);
 // Persistent launch of a plan (init + graph kernel) on stream s.  counters:
 // the dependency counters to use (one per queue entry), or null for the
 // plan's own (launches that may overlap on one plan need their own).
@@ -351,8 +364,9 @@ int persistent_occupancy(int elem_bytes, int bn, bool split = false);
 // Expand the job graph for Q columns with column tile bn, order it by list
 // scheduling on `workers` simulated workgroups, and upload it (hm_sched.hip).
 // The plan of h for (bn, ldq / bn column tiles), built and cached on first use.
+// build = false: look the plan up only (HM_ERR_INVALID when it was never built).
 hm_status get_plan(hm_matrix h, int slot, int bn, int64_t ldq, int workers, GraphPlan **out,
-                   int mode = 0);
+                   int mode = 0, bool build = true);
 // Grow h's workspaces for element-size slot to a leading dimension of ldq.
 hm_status reserve_ws(hm_matrix h, int slot, int64_t ldq);
 // One matrix's share of a (possibly multi-matrix) plan.

@@ -257,13 +257,16 @@ hm_status build_plan(const std::vector<PlanPart> &parts, int bn, int elem_bytes,
 }
 
 hm_status get_plan(hm_matrix h, int slot, int bn, int64_t ldq, int workers, GraphPlan **out,
-                   int mode) {
+                   int mode, bool build) {
     const int nq = (int)(ldq / bn);
     for (GraphPlan &p : h->plans[slot])
         if (p.bn == bn && p.Q == nq && p.mode == mode) {
             *out = &p;
             return HM_OK;
         }
+    if (!build)
+        return fail(HM_ERR_INVALID, "no task graph for this column-tile count, precision and element type yet: "
+                                    "one hm_eval with the same Q class, dtype and precision builds it");
     if (h->plans[slot].size() >= 16) {  // bounded cache: drop the oldest plan
         free_plan(h->plans[slot].front());
         h->plans[slot].erase(h->plans[slot].begin());

@@ -21,6 +21,7 @@ HM_PREC_FP64, HM_PREC_FP32, HM_PREC_BF16X3 = 0, 1, 2
 HM_TREE_ORDER, HM_PROFILE, HM_NEAR_FROM_POINTS, HM_FAR_FROM_POINTS, HM_LEVEL_LAUNCHES = 1, 2, 4, 8, 16
 HM_LOAD_NO_NEAR_BLOCKS, HM_LOAD_NO_FAR_BLOCKS = 1 << 8, 1 << 9
 HM_BATCH_AUTOTUNE, HM_BATCH_NO_GRAPH = 1, 2
+HM_NOALLOC_SCRATCH_BYTES = 64 << 20
 STATUS_NAMES = {0: "HM_OK", -1: "HM_ERR_INVALID", -2: "HM_ERR_FORMAT", -3: "HM_ERR_NOMEM",
                 -4: "HM_ERR_DEVICE", -5: "HM_ERR_BUSY", -6: "HM_ERR_PENDING", -7: "HM_ERR_INTERNAL"}
 
@@ -99,6 +100,8 @@ def _load():
     L.hm_eval.restype = st
     L.hm_eval.argtypes = [_P, _P, ctypes.c_int64, _P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int,
                           ctypes.c_int, ctypes.c_uint, _P]
+    L.hm_eval_noalloc.restype = st
+    L.hm_eval_noalloc.argtypes = L.hm_eval.argtypes
     L.hm_profile_read.restype = st
     L.hm_profile_read.argtypes = [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     L.hm_profile_reset.restype = st
@@ -322,33 +325,50 @@ def _stream_ptr(stream) -> int | None:
     return getattr(stream, "cuda_stream", stream)
 
 
-def hm_eval(h: Matrix, W, Y, Q: int | None = None, prec: int | None = None, flags: int = 0,
-            stream=None) -> None:
-    """Y = K~ W on the device.  W and Y are CUDA (HIP) tensors, row-major with
-    unit column stride, N x Q (leading dimensions from their row strides)."""
+def _eval_args(name: str, h: Matrix, W, Y, Q, prec, flags, stream):
+    """Argument checks and marshalling shared by hm_eval and hm_eval_noalloc."""
     import torch
     if not (W.is_cuda and Y.is_cuda):
-        raise ValueError("hm_eval: W and Y must be device tensors")
+        raise ValueError(f"{name}: W and Y must be device tensors")
     if W.dtype != Y.dtype or W.dtype not in (torch.float64, torch.float32):
-        raise ValueError("hm_eval: W and Y must both be float64 or both float32")
+        raise ValueError(f"{name}: W and Y must both be float64 or both float32")
     if W.dim() != 2 or Y.dim() != 2 or W.stride(1) != 1 or Y.stride(1) != 1:
-        raise ValueError("hm_eval: W and Y must be 2-D with unit column stride")
+        raise ValueError(f"{name}: W and Y must be 2-D with unit column stride")
     info = hm_info(h)
     if W.shape[0] < info["N"] or Y.shape[0] < info["N"]:
-        raise ValueError(f"hm_eval: W and Y need N={info['N']} rows")
+        raise ValueError(f"{name}: W and Y need N={info['N']} rows")
     if W.device.index != info["device"] or Y.device.index != info["device"]:
-        raise ValueError("hm_eval: tensors are not on the matrix's device")
+        raise ValueError(f"{name}: tensors are not on the matrix's device")
     dtype = HM_F64 if W.dtype == torch.float64 else HM_F32
     if prec is None:
         prec = HM_PREC_FP64 if dtype == HM_F64 else HM_PREC_FP32
     if Q is None:
         Q = W.shape[1]
     if Q == 0:
-        return
+        return None
     if W.shape[1] < Q or Y.shape[1] < Q:
-        raise ValueError("hm_eval: tensors narrower than Q")
-    _check(lib.hm_eval(h, W.data_ptr(), W.stride(0), Y.data_ptr(), Y.stride(0), Q, dtype, prec,
-                       flags, _stream_ptr(stream)))
+        raise ValueError(f"{name}: tensors narrower than Q")
+    return (h, W.data_ptr(), W.stride(0), Y.data_ptr(), Y.stride(0), Q, dtype, prec, flags, _stream_ptr(stream))
+
+
+def hm_eval(h: Matrix, W, Y, Q: int | None = None, prec: int | None = None, flags: int = 0,
+            stream=None) -> None:
+    """Y = K~ W on the device.  W and Y are CUDA (HIP) tensors, row-major with
+    unit column stride, N x Q (leading dimensions from their row strides)."""
+    args = _eval_args("hm_eval", h, W, Y, Q, prec, flags, stream)
+    if args is not None:
+        _check(lib.hm_eval(*args))
+
+
+def hm_eval_noalloc(h: Matrix, W, Y, Q: int | None = None, prec: int | None = None, flags: int = 0,
+                    stream=None) -> None:
+    """hm_eval with its per-call device memory in the library's fixed device
+    array (HM_NOALLOC_SCRATCH_BYTES): allocates nothing.  The evaluation's
+    task graph must exist already (an hm_eval of the same width class, dtype
+    and precision builds it)."""
+    args = _eval_args("hm_eval_noalloc", h, W, Y, Q, prec, flags, stream)
+    if args is not None:
+        _check(lib.hm_eval_noalloc(*args))
 
 
 def hm_set_points(h: Matrix, X: np.ndarray, kernel: int, h_param: float) -> None:

@@ -73,6 +73,8 @@ def test_missing_file_and_null_arguments():
     st, msg = _status("/nonexistent/file.hmc")
     assert st == hm.HM_ERR_INVALID and "cannot open" in msg
     assert hm.lib.hm_eval(None, None, 1, None, 1, 1, 0, 0, 0, None) == hm.HM_ERR_INVALID
+    assert hm.lib.hm_eval_noalloc(None, None, 1, None, 1, 1, 0, 0, 0, None) == hm.HM_ERR_INVALID
+    assert "hm_eval_noalloc" in hm.hm_last_error()
     assert hm.lib.hm_info(None, None) == hm.HM_ERR_INVALID
     assert hm.lib.hm_free(None) == hm.HM_OK
     out = ctypes.c_void_p()
