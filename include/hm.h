@@ -376,6 +376,70 @@ hm_status hm_repr_write(hm_repr r, const char *path);
 /* Release r (NULL accepted). */
 hm_status hm_repr_free(hm_repr r);
 
+/* ---------------------------------------------------------------------------
+ * Reusing inspection (Section 5 "Reusing Inspection"): the compression is
+ * split in two phases.  inspector-p1 holds what depends on the points and
+ * the admissibility condition only (tree, interaction lists, row sampling);
+ * inspector-p2 holds what depends on the kernel function and the accuracy
+ * (the low-rank approximation of every node and the blocks).  When the
+ * kernel, its bandwidth or the accuracy change, only p2 runs again, on the
+ * p1 output kept from before.  Here p1 runs on the host and p2 on the GPU. */
+typedef struct hm_structure_s *hm_structure;  /* library-owned inspector-p1 output */
+
+typedef struct {
+    int64_t N, d;
+    int32_t n_nodes, depth;
+    int64_t n_far, n_near;
+    int64_t rows_total;  /* row-sample entries over all nodes */
+} hm_structure_info_t;
+
+/* inspector-p1 on the host: the tree, the far and near lists and every
+ * node's row sample, with the same readings as hm_compress (fields used:
+ * leaf_size, admissibility, tau, sample_rows, seed, threads; the kernel,
+ * h, tol and max_rank fields are ignored).  X is N x d row-major FP64 host
+ * memory, copied (the caller may free it on return).  HM_ERR_INVALID for bad
+ * options or non-finite coordinates. */
+hm_status hm_inspect_p1(const double *X, int64_t N, int64_t d, const hm_compress_opts *opts,
+                        hm_structure *out);
+hm_status hm_structure_info(hm_structure s, hm_structure_info_t *out);
+/* Row sample of one node: original point indices in tree order.  *count
+ * receives its length; rows (may be NULL) receives the entries when
+ * cap >= *count (HM_ERR_INVALID otherwise). */
+hm_status hm_structure_rows(hm_structure s, int32_t node, int64_t *rows, int64_t cap, int64_t *count);
+hm_status hm_structure_free(hm_structure s);
+
+/* inspector-p2 on GPU `device` (Section 3.1 low-rank approximation by
+ * interpolative decomposition, Section 5 reuse): for every node, deepest
+ * level first, the kernel block A = K(X[rows], X[candidates]) of its row
+ * sample and its candidate columns (a leaf's points, or its children's
+ * skeletons) is formed on the device, its Gram matrix A^T A is taken on the
+ * matrix cores, and a pivoted partial Cholesky of the Gram matrix gives the
+ * pivots and the triangular factor of a column-pivoted QR of A (the same
+ * pivots and |R_jj| in exact arithmetic).  The rank is the first j with
+ * R_jj <= tol * R_11, capped at max_rank; the interpolation matrix is
+ * [I, R11^-1 R12] in pivot order.  The far blocks B_ab = K(X[skel_a],
+ * X[skel_b]) and the near blocks D_ab = K(X[I_a], X[I_b]) are generated on
+ * the device.  The result is a host representation (with its skeletons) for
+ * hm_load_compressed_mem or hm_repr_write.  kernel 0 is
+ * exp(-|x-y|^2 / (2 h^2)), 1 is exp(-|x-y| / h); h > 0, tol >= 0,
+ * 1 <= max_rank <= 1024 and leaves of at most 2048 points (HM_ERR_INVALID
+ * otherwise).  Synchronous; the structure is only read and may be reused by
+ * any number of p2 runs. */
+hm_status hm_inspect_p2(hm_structure s, int device, int32_t kernel, double h, double tol, int32_t max_rank,
+                        hm_repr *out);
+
+/* inspector-p2 straight into a device matrix: the same IDs as hm_inspect_p2,
+ * then the device store of hm_load_compressed_mem built on `device` with
+ * prec_mask (same meaning and checks), its far and near blocks generated in
+ * the store from the points instead of being copied through the host (the
+ * data layout construction of Section 3.2 done on the device).  Results of
+ * hm_eval on it equal those on hm_load_compressed_mem(hm_inspect_p2(...))
+ * bitwise.  With HM_LOAD_NO_NEAR_BLOCKS / HM_LOAD_NO_FAR_BLOCKS the blocks
+ * are not generated; hm_set_points with the same points, kernel and h then
+ * enables HM_NEAR_FROM_POINTS / HM_FAR_FROM_POINTS. */
+hm_status hm_inspect_p2_load(hm_structure s, int device, int32_t kernel, double h, double tol, int32_t max_rank,
+                             unsigned prec_mask, hm_matrix *out);
+
 /* Message for the last non-OK status returned on this thread. */
 const char *hm_last_error(void);
 

@@ -12,3 +12,4 @@ from .hm import (HM_F32, HM_F64, HM_FAR_FROM_POINTS, HM_LOAD_NO_FAR_BLOCKS, HM_L
                  HM_LEVEL_LAUNCHES, HM_NOALLOC_SCRATCH_BYTES, HM_PROFILE, HM_TREE_ORDER, HMError, Matrix, Repr, hm_check, hm_compress, hm_eval, hm_eval_noalloc, hm_free,
                  hm_info, hm_last_error, hm_load_compressed, hm_load_compressed_mem, hm_profile_read,
                  hm_profile_reset, hm_repr_free, hm_repr_write, hm_set_points, precbit)
+from .hm import Structure, hm_inspect_p1, hm_inspect_p2, hm_inspect_p2_load  # noqa: F401

@@ -162,7 +162,8 @@ hm_status repack_source(const double *host, std::vector<RepackJob> &jobs, double
 
 }  // namespace
 
-hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_matrix *out) {
+hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_matrix *out,
+                       const BlockSource *gen) {
     const int32_t n = r.n_nodes;
     const bool no_near = (prec_mask & HM_LOAD_NO_NEAR_BLOCKS) != 0;
     const bool no_far = (prec_mask & HM_LOAD_NO_FAR_BLOCKS) != 0;
@@ -185,7 +186,10 @@ hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_mat
     }
     for (int a = 0; a < n; a++) h16row[a + 1] = h16row[a] + round_up(r.rank[a], Split16::kRows);
 
+    if (gen && (r.skel_ptr.size() != (size_t)n + 1))
+        return fail(HM_ERR_INVALID, "generated blocks need the skeletons in the representation");
     Planner P;
+    std::vector<GenJob> gjobs;  // far and near blocks generated from the points (gen)
     std::vector<std::vector<int>> by_level((size_t)r.depth + 1);
     for (int a = 0; a < n; a++) by_level[(size_t)r.level[a]].push_back(a);
 
@@ -241,6 +245,8 @@ hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_mat
                 if (!no_far) {
                     off = P.alloc(kb, kap);
                     P.jobs[1].push_back({r.far_off[e], off, ka, kb, 0, 0, kb, kap});
+                    if (gen)  // rows: a's skeleton, columns: bn's skeleton
+                        gjobs.push_back({off, r.N + r.skel_ptr[a], r.N + r.skel_ptr[bn], ka, kb, kap, 0});
                 }
                 b.segs.push_back(seg(off, wrow[bn], kap, kb, BUF_WHAT, h16row[bn]));
                 b.segs.back().from_pts = 2;
@@ -275,6 +281,8 @@ hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_mat
                 if (!no_near) {
                     off = P.alloc(mb, map);
                     P.jobs[2].push_back({r.near_off[e], off, ma, mb, 0, 0, mb, map});
+                    if (gen)  // rows: a's points, columns: bn's points (tree order)
+                        gjobs.push_back({off, r.start[a], r.start[bn], ma, mb, map, 0});
                 }
                 b.segs.push_back(seg(off, r.start[bn], map, mb, BUF_WT, w16row[bn]));
                 b.segs.back().from_pts = 1;
@@ -503,7 +511,8 @@ hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_mat
     h->prec[HM_PREC_FP64].bytes = sizeof(double) * (size_t)h->store_elems;
     HM_HIP(hipMemsetAsync(store64, 0, sizeof(double) * (size_t)h->store_elems, s));
     {
-        const int64_t max_src = std::max({r.basis_len, r.B_len, r.D_len, (int64_t)1});
+        const int64_t max_src = gen ? std::max(r.basis_len, (int64_t)1)
+                                    : std::max({r.basis_len, r.B_len, r.D_len, (int64_t)1});
         const int64_t stage_elems = std::min<int64_t>(max_src, (int64_t)64 << 20);  // <= 512 MiB
         const int64_t max_jobs = 1 << 16;
         DevicePtrs tmp;
@@ -514,10 +523,20 @@ hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_mat
         HM_HIP(hipMalloc(&d_jobs, sizeof(RepackJob) * (size_t)max_jobs));
         tmp.add(d_jobs);
         const double *src[3] = {r.basis_ptr(), r.B_ptr(), r.D_ptr()};
-        for (int k = 0; k < 3; k++) {
+        for (int k = 0; k < (gen ? 1 : 3); k++) {
             hm_status st = repack_source(src[k], P.jobs[k], store64, stage, stage_elems, d_jobs,
                                          max_jobs, s);
             if (st != HM_OK) return st;
+        }
+        if (gen) {
+            const int64_t per = max_jobs * (int64_t)sizeof(RepackJob) / (int64_t)sizeof(GenJob);
+            for (size_t i = 0; i < gjobs.size(); i += (size_t)per) {
+                const int cnt = (int)std::min<size_t>((size_t)per, gjobs.size() - i);
+                HM_HIP(hipMemcpyAsync(d_jobs, gjobs.data() + i, sizeof(GenJob) * (size_t)cnt,
+                                      hipMemcpyHostToDevice, s));
+                HM_HIP(launch_gen_store((const GenJob *)d_jobs, cnt, *gen, store64, s));
+                HM_HIP(hipStreamSynchronize(s));
+            }
         }
     }
     if (prec_mask & HM_PRECBIT(HM_PREC_BF16X3)) {

@@ -31,10 +31,6 @@
 
 #include "hm_internal.h"
 
-struct hm_repr_s {
-    hm::HostRepr r;
-    std::vector<int64_t> skel_ptr, skel;
-};
 
 namespace hm {
 namespace {
@@ -463,6 +459,79 @@ hm_status hm_compress(const double *X, int64_t N, int64_t d, const hm_compress_o
         return st;
     }
     *out = r;
+    return HM_OK;
+}
+
+hm_status hm_inspect_p1(const double *X, int64_t N, int64_t d, const hm_compress_opts *opts,
+                        hm_structure *out) {
+    if (!out) return fail(HM_ERR_INVALID, "hm_inspect_p1: out is NULL");
+    *out = nullptr;
+    if (!X || !opts) return fail(HM_ERR_INVALID, "hm_inspect_p1: NULL argument");
+    if (N < 1 || d < 1) return fail(HM_ERR_INVALID, "hm_inspect_p1: need N >= 1 and d >= 1");
+    if (opts->leaf_size < 2 || opts->sample_rows < 1 || (opts->admissibility != 0 && opts->admissibility != 1) ||
+        !(opts->tau >= 0.0))
+        return fail(HM_ERR_INVALID, "hm_inspect_p1: invalid options");
+    for (int64_t i = 0; i < N * d; i++)
+        if (!std::isfinite(X[i])) return fail(HM_ERR_INVALID, "hm_inspect_p1: non-finite point coordinate");
+    hm_structure st = new (std::nothrow) hm_structure_s();
+    if (!st) return fail(HM_ERR_NOMEM, "hm_inspect_p1: allocation failed");
+    unsigned hw = std::thread::hardware_concurrency();
+    const int threads = opts->threads > 0 ? opts->threads : (int)std::max(1u, hw);
+    Structure &S = st->s;
+    Inspector I{X, N, d, *opts, threads, S.r, {}, {}, {}};
+    I.tree();
+    I.geometry();
+    I.interactions();
+    // the row sample of every node (original point indices), in tree-position order
+    const int n = S.r.n_nodes;
+    std::vector<std::vector<int64_t>> rows((size_t)n);
+    parallel_for(n, threads, [&](int64_t a) {
+        rows[(size_t)a] = I.sample_rows((int)a);
+        for (int64_t &t : rows[(size_t)a]) t = S.r.perm[(size_t)t];
+    });
+    S.rows_ptr.assign((size_t)n + 1, 0);
+    for (int a = 0; a < n; a++) S.rows_ptr[(size_t)a + 1] = S.rows_ptr[(size_t)a] + (int64_t)rows[(size_t)a].size();
+    S.rows.resize((size_t)S.rows_ptr[(size_t)n]);
+    for (int a = 0; a < n; a++) std::copy(rows[(size_t)a].begin(), rows[(size_t)a].end(), S.rows.begin() + S.rows_ptr[(size_t)a]);
+    S.X.assign(X, X + N * d);
+    S.leaf_size = opts->leaf_size;
+    S.admissibility = opts->admissibility;
+    S.tau = opts->tau;
+    S.r.m = opts->leaf_size;
+    S.r.tau = opts->tau;
+    S.r.flags = opts->admissibility == 1 ? 1u : 0u;
+    *out = st;
+    return HM_OK;
+}
+
+hm_status hm_structure_info(hm_structure s, hm_structure_info_t *o) {
+    if (!s || !o) return fail(HM_ERR_INVALID, "hm_structure_info: NULL argument");
+    const Structure &S = s->s;
+    o->N = S.r.N;
+    o->d = S.r.d;
+    o->n_nodes = S.r.n_nodes;
+    o->depth = S.r.depth;
+    o->n_far = (int64_t)S.r.far_col.size();
+    o->n_near = (int64_t)S.r.near_col.size();
+    o->rows_total = (int64_t)S.rows.size();
+    return HM_OK;
+}
+
+hm_status hm_structure_rows(hm_structure s, int32_t node, int64_t *rows, int64_t cap, int64_t *count) {
+    if (!s || !count) return fail(HM_ERR_INVALID, "hm_structure_rows: NULL argument");
+    const Structure &S = s->s;
+    if (node < 0 || node >= S.r.n_nodes) return fail(HM_ERR_INVALID, "hm_structure_rows: no such node");
+    const int64_t b = S.rows_ptr[(size_t)node], e = S.rows_ptr[(size_t)node + 1];
+    *count = e - b;
+    if (rows) {
+        if (cap < e - b) return fail(HM_ERR_INVALID, "hm_structure_rows: cap too small");
+        std::copy(S.rows.begin() + b, S.rows.begin() + e, rows);
+    }
+    return HM_OK;
+}
+
+hm_status hm_structure_free(hm_structure s) {
+    delete s;
     return HM_OK;
 }
 

@@ -209,6 +209,19 @@ struct GraphPlan {
     double est_ms = 0;   // list-scheduling estimate (diagnostic)
 };
 
+// Output of inspector-p1 (Section 5 "Reusing Inspection"): everything the
+// compression needs that depends on the points and the admissibility only,
+// not on the kernel function or the accuracy.  Built once on the host, reused
+// by every inspector-p2 run.
+struct Structure {
+    HostRepr r;                        // tree, perm, geometry-derived far/near lists; no ranks or blocks
+    std::vector<double> X;             // N x d points, original order (a copy)
+    std::vector<int64_t> rows_ptr;     // row sample of node a: rows[rows_ptr[a] .. rows_ptr[a+1]),
+    std::vector<int64_t> rows;         //   original point indices of the sampled far-field points
+    int32_t leaf_size = 0, admissibility = 0;
+    double tau = 0;
+};
+
 struct PrecStore {
     void *blocks = nullptr;   // device block store (FP64 or FP32 elements)
     size_t bytes = 0;
@@ -269,6 +282,15 @@ struct hm_matrix_s {
     double repr_h = 0;
 };
 
+struct hm_repr_s {
+    hm::HostRepr r;
+    std::vector<int64_t> skel_ptr, skel;
+};
+
+struct hm_structure_s {
+    hm::Structure s;
+};
+
 namespace hm {
 
 // Thread-local error reporting.
@@ -281,8 +303,30 @@ hm_status from_view(const hm_host_repr &v, HostRepr &out);
 // Structural validation shared by both loaders.
 hm_status validate(const HostRepr &r);
 
+// Where the far and near blocks of build_matrix come from when they are not
+// in the representation's arrays: generated in the device store from the
+// points (inspector-p2 builds a matrix this way without copying its blocks
+// through the host).  All device pointers belong to the caller and stay
+// valid during build_matrix.
+struct BlockSource {
+    const double *X = nullptr;       // device, N x d points in the caller's original order
+    int32_t d = 0, kern = 0;         // kernel 0: exp(-r^2 kscale), 1: exp(-r kscale)
+    double kscale = 0;
+    const int64_t *idx = nullptr;    // device: [perm (N entries) | every node's skeleton, node order]
+};
+// One generated block: dst[t * ld + i] = K(X[idx[r_off + i]], X[idx[c_off + t]])
+// for i < rows, t < cols, and zero for rows <= i < ld.
+struct GenJob {
+    int64_t dst_off, r_off, c_off;
+    int32_t rows, cols, ld, pad_;
+};
+hipError_t launch_gen_store(const GenJob *jobs, int njobs, const BlockSource &src, double *store, hipStream_t s);
+
 // Build the device store, tables and phases for a validated representation.
-hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_matrix *out);
+// gen (optional): generate the far and near blocks from the points instead
+// of copying them from r.B and r.D (which may then be empty).
+hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_matrix *out,
+                       const BlockSource *gen = nullptr);
 
 // Kernel launchers (hm_kernels.hip).
 // Column tile for Q columns (16..256) in a phase of the given kind (1 up,

@@ -60,6 +60,12 @@ class hm_compress_opts(ctypes.Structure):
                 ("threads", ctypes.c_int32)]
 
 
+class hm_structure_info_t(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int64), ("d", ctypes.c_int64), ("n_nodes", ctypes.c_int32),
+                ("depth", ctypes.c_int32), ("n_far", ctypes.c_int64), ("n_near", ctypes.c_int64),
+                ("rows_total", ctypes.c_int64)]
+
+
 class hm_batch_info_t(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("column_tile", ctypes.c_int32), ("n_tasks", ctypes.c_int32),
                 ("workgroups", ctypes.c_int32), ("flops", ctypes.c_double),
@@ -149,6 +155,21 @@ def _load():
     L.hm_repr_write.argtypes = [_P, ctypes.c_char_p]
     L.hm_repr_free.restype = st
     L.hm_repr_free.argtypes = [_P]
+    L.hm_inspect_p1.restype = st
+    L.hm_inspect_p1.argtypes = [_P, ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(hm_compress_opts),
+                                ctypes.POINTER(_P)]
+    L.hm_structure_info.restype = st
+    L.hm_structure_info.argtypes = [_P, ctypes.POINTER(hm_structure_info_t)]
+    L.hm_structure_rows.restype = st
+    L.hm_structure_rows.argtypes = [_P, ctypes.c_int32, _P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
+    L.hm_structure_free.restype = st
+    L.hm_structure_free.argtypes = [_P]
+    L.hm_inspect_p2_load.restype = st
+    L.hm_inspect_p2_load.argtypes = [_P, ctypes.c_int, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                     ctypes.c_int32, ctypes.c_uint, ctypes.POINTER(_P)]
+    L.hm_inspect_p2.restype = st
+    L.hm_inspect_p2.argtypes = [_P, ctypes.c_int, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                ctypes.c_int32, ctypes.POINTER(_P)]
     return L
 
 
@@ -279,6 +300,60 @@ def hm_compress(X: np.ndarray, *, kernel: int, h: float, leaf_size: int, tol: fl
     out = _P()
     _check(lib.hm_compress(X.ctypes.data, X.shape[0], X.shape[1], ctypes.byref(o), ctypes.byref(out)))
     return Repr(out.value)
+
+
+class Structure:
+    """inspector-p1 output owned by libhm: tree, interaction lists and row
+    samples of a point set, reused by every inspector-p2 run."""
+
+    def __init__(self, handle: int):
+        self.handle = handle
+        info = hm_structure_info_t()
+        _check(lib.hm_structure_info(handle, ctypes.byref(info)))
+        for k, _ in hm_structure_info_t._fields_:
+            setattr(self, k, getattr(info, k))
+
+    def rows(self, node: int) -> np.ndarray:
+        """Row sample of a node: original point indices in tree order."""
+        cnt = ctypes.c_int64()
+        _check(lib.hm_structure_rows(self.handle, int(node), None, 0, ctypes.byref(cnt)))
+        out = np.zeros(max(cnt.value, 1), np.int64)
+        _check(lib.hm_structure_rows(self.handle, int(node), out.ctypes.data, len(out), ctypes.byref(cnt)))
+        return out[:cnt.value]
+
+    def __del__(self):
+        if getattr(self, "handle", None) and lib is not None:
+            lib.hm_structure_free(self.handle)
+            self.handle = None
+
+
+def hm_inspect_p1(X: np.ndarray, *, leaf_size: int, admissibility: int, tau: float, sample_rows: int = 4096,
+                  seed: int = 7, threads: int = 0) -> Structure:
+    """inspector-p1 (host): tree, far/near lists and row samples."""
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    o = hm_compress_opts(0, 1.0, leaf_size, 0.0, 1, admissibility, tau, sample_rows, seed, threads)
+    out = _P()
+    _check(lib.hm_inspect_p1(X.ctypes.data, X.shape[0], X.shape[1], ctypes.byref(o), ctypes.byref(out)))
+    return Structure(out.value)
+
+
+def hm_inspect_p2(s: Structure, device: int = 0, *, kernel: int, h: float, tol: float, max_rank: int) -> Repr:
+    """inspector-p2 on the GPU: IDs of every node and the blocks, for one
+    kernel function and accuracy, on a kept inspector-p1 structure."""
+    out = _P()
+    _check(lib.hm_inspect_p2(s.handle, int(device), int(kernel), float(h), float(tol), int(max_rank),
+                             ctypes.byref(out)))
+    return Repr(out.value)
+
+
+def hm_inspect_p2_load(s: Structure, device: int = 0, *, kernel: int, h: float, tol: float, max_rank: int,
+                       prec_mask: int = precbit(HM_PREC_FP64)) -> "Matrix":
+    """inspector-p2 on the GPU straight into a device matrix (blocks generated
+    in the device store)."""
+    out = _P()
+    _check(lib.hm_inspect_p2_load(s.handle, int(device), int(kernel), float(h), float(tol), int(max_rank),
+                                  int(prec_mask), ctypes.byref(out)))
+    return Matrix(out.value)
 
 
 def hm_repr_write(r: Repr, path: str) -> None:
