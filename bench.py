@@ -563,6 +563,81 @@ def bench_mixed(args) -> dict:
     }
 
 
+def bench_compression(args) -> dict:
+    """Reusing inspection (paper Section 5, its Fig. 10 scenario): the headline
+    workload (N = 65536, d = 8) compressed for five accuracies 1e-1 ... 1e-5.
+    Without reuse every change reruns the whole compression; with reuse
+    inspector-p1 (tree, interaction lists, row samples; host) runs once and
+    only inspector-p2 (IDs on the GPU, blocks generated in the device store)
+    runs per accuracy.  Beside it, the host inspector (the same readings, all
+    host cores) followed by the upload, per accuracy.  Every time includes
+    building the device matrix that the evaluation uses."""
+    import numpy as np
+    import torch
+
+    import paper_1812_07152_amd as hmx
+    import workloads as wl
+    from oracle.oracle import exact_rows
+
+    w = wl.C2
+    X = wl.gen_points(w)
+    tols = (1e-1, 1e-2, 1e-3, 1e-4, 1e-5)
+    mask = hmx.precbit(hmx.HM_PREC_FP64)
+    t = time.perf_counter()
+    S = hmx.hm_inspect_p1(X, leaf_size=w.m, admissibility=w.adm, tau=w.tau, sample_rows=w.sample_rows,
+                          seed=w.sample_seed)
+    t_p1 = time.perf_counter() - t
+    W = torch.from_numpy(wl.gen_w(w, Q=8)).cuda()
+    rows = np.random.default_rng(11).choice(w.N, 256, replace=False)
+    Yex = exact_rows(X, w.kernel, w.h, rows, W.cpu().numpy())
+    per = []
+    for tol in tols:
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        M = hmx.hm_inspect_p2_load(S, 0, kernel=w.kernel, h=w.h, tol=tol, max_rank=w.rmax, prec_mask=mask)
+        torch.cuda.synchronize()
+        t_p2 = time.perf_counter() - t
+        # the IDs alone (no blocks in the store)
+        t = time.perf_counter()
+        M0 = hmx.hm_inspect_p2_load(S, 0, kernel=w.kernel, h=w.h, tol=tol, max_rank=w.rmax,
+                                    prec_mask=mask | hmx.HM_LOAD_NO_NEAR_BLOCKS | hmx.HM_LOAD_NO_FAR_BLOCKS)
+        torch.cuda.synchronize()
+        t_ids = time.perf_counter() - t
+        del M0
+        Y = torch.empty_like(W)
+        hmx.hm_eval(M, W, Y)
+        hmx.hm_check(M)
+        e = float(np.linalg.norm(Y.cpu().numpy()[rows] - Yex) / np.linalg.norm(Yex))
+        info = hmx.hm_info(M)
+        del M
+        t = time.perf_counter()
+        R = hmx.hm_compress(X, kernel=w.kernel, h=w.h, leaf_size=w.m, tol=tol, max_rank=w.rmax,
+                            admissibility=w.adm, tau=w.tau, sample_rows=w.sample_rows, seed=w.sample_seed)
+        t_host = time.perf_counter() - t
+        t = time.perf_counter()
+        Mh = hmx.hm_load_compressed_mem(R, 0, mask)
+        torch.cuda.synchronize()
+        t_load = time.perf_counter() - t
+        del Mh, R
+        per.append({"tol": tol, "p2_gpu_s": t_p2, "p2_ids_only_s": t_ids, "host_compress_s": t_host,
+                    "host_upload_s": t_load, "eps_f_sampled": e, "gflop_per_column": info["flops_per_col"] / 1e9})
+        print(f"[compression] tol={tol:g}: p2 {t_p2:.2f} s (IDs {t_ids:.2f} s), host {t_host:.2f} + "
+              f"{t_load:.2f} s, eps_f {e:.2e}", file=sys.stderr, flush=True)
+    reuse = t_p1 + sum(p["p2_gpu_s"] for p in per)
+    no_reuse = sum(t_p1 + p["p2_gpu_s"] for p in per)
+    host = sum(p["host_compress_s"] + p["host_upload_s"] for p in per)
+    return {
+        "metric": "compression time over five accuracy changes (s), inspector-p1 reused",
+        "value": reuse, "unit": "s", "higher_is_better": False, "dtype": "f64",
+        "config": {"workload": w.name, "N": w.N, "d": w.d, "tols": list(tols), "leaf": w.m,
+                   "max_rank": w.rmax, "sample_rows": w.sample_rows},
+        "p1_host_s": t_p1, "per_accuracy": per,
+        "total_s": {"gpu_p2_with_p1_reuse": reuse, "gpu_without_reuse": no_reuse,
+                    "host_inspector_and_upload": host},
+        "speedup_reuse_vs_host": host / reuse,
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -580,10 +655,12 @@ def main() -> int:
                     help="mixed form: skip the N=65536 workload reported beside the main one")
     ap.add_argument("--mixed-c2-only", action="store_true",
                     help="mixed form: run the N=65536 workload alone")
-    ap.add_argument("--form", choices=("plain", "batched", "serving", "mixed", "points"), default="plain",
+    ap.add_argument("--form", choices=("plain", "batched", "serving", "mixed", "points", "compression"),
+                    default="plain",
                     help="plain: the headline workload; batched: 64 uneven matrices in one launch; "
                          "serving: 8 resident matrices under a request stream; mixed: split BF16; "
-                         "points: near and far blocks computed from the points")
+                         "points: near and far blocks computed from the points; compression: "
+                         "inspector-p1 reuse over five accuracy changes")
     ap.add_argument("--burst", type=int, default=128, help="serving: requests in the saturation burst")
     ap.add_argument("--serving-seconds", type=float, default=3.0, help="serving: seconds per load level")
     ap.add_argument("--serving-seed", type=int, default=4)
@@ -608,6 +685,9 @@ def main() -> int:
         return 0
     if args.form == "points":
         print(json.dumps(bench_points(args)), flush=True)
+        return 0
+    if args.form == "compression":
+        print(json.dumps(bench_compression(args)), flush=True)
         return 0
 
     import numpy as np
@@ -754,6 +834,9 @@ def main() -> int:
             t = time.perf_counter()
             out["forms"]["mixed_c4"] = compact(bench_mixed_c4(args))
             print(f"[bench] mixed C4 form done ({time.perf_counter() - t:.0f} s)", file=sys.stderr, flush=True)
+        t = time.perf_counter()
+        out["forms"]["compression_reuse"] = compact(bench_compression(args))
+        print(f"[bench] compression reuse done ({time.perf_counter() - t:.0f} s)", file=sys.stderr, flush=True)
     print(json.dumps(out), flush=True)
     return 0
 
