@@ -140,7 +140,9 @@ typedef struct {
     int32_t n_phases;               /* launches of one evaluation (excluding permutes) */
 } hm_info_t;
 
-/* Load the compressed representation from an HMC1 file (the inspector's
+/* Load the compressed representation (the output of the compression phase,
+ * Section 3.1, stored in the order the evaluation visits it as the paper's
+ * CDS format does, Section 3.2) from an HMC1 file (the inspector's
  * output: 128-byte little-endian header "HMC1", version 1, then the arrays of
  * hm_host_repr in its field order) onto HIP device `device`, keeping the
  * precisions in prec_mask (HM_PRECBIT(HM_PREC_FP64) | ...).  The file is
@@ -160,7 +162,10 @@ hm_status hm_info(hm_matrix h, hm_info_t *out);
  * make sure no enqueued hm_eval on h is still running. */
 hm_status hm_free(hm_matrix h);
 
-/* Y = K~ W for Q columns on `stream` (a hipStream_t, NULL = null stream).
+/* The evaluation phase (Section 2.1 "Evaluation"): Y = K~ W for Q columns on
+ * `stream` (a hipStream_t, NULL = null stream), by the tree loops (up pass
+ * with the bases, down pass) and the reduction loops (far blocks B, near
+ * blocks D) of the paper, as one persistent task-graph launch.
  * dtype must be HM_F64 with HM_PREC_FP64 or HM_PREC_BF16X3, HM_F32 with HM_PREC_FP32; the
  * precision must have been loaded.  flags: HM_TREE_ORDER, HM_PROFILE, and
  * HM_NEAR_FROM_POINTS and HM_FAR_FROM_POINTS (HM_PREC_FP64 with points set by

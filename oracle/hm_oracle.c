@@ -48,8 +48,10 @@ typedef struct {
     int m;          /* leaf size */
     double tol;     /* ID tolerance (relative to |R_11|) */
     int rmax;       /* rank cap */
-    int adm;        /* 0 distance admissibility, 1 HSS */
+    int adm;        /* 0 distance admissibility, 1 HSS, 2 budget (H^2-b) */
     double tau;
+    int part;       /* 0 median of the widest coordinate, 1 two-means direction */
+    double budget;  /* budget admissibility: near leaves per leaf = floor(budget * #leaves) */
     int64_t S;      /* row-sample cap */
     uint64_t seed;  /* sample seed */
     double *X;      /* N x d copy of the points (original order) */
@@ -62,6 +64,8 @@ typedef struct {
     int *parent, *left, *right, *level;
     double *centroid; /* n_nodes x d */
     double *radius;
+    double *split_c;  /* n_nodes x 2d: the two means of a two-means split (tests) */
+    unsigned char *leafnear; /* n_leaves x n_leaves near relation (budget admissibility) */
 
     /* interaction lists (CSR by row node, sorted by column node) */
     int64_t *far_ptr;  int *far_col;  int64_t n_far;
@@ -116,6 +120,87 @@ static int orc_key_cmp(const void *a, const void *b)
     return (x->idx > y->idx) - (x->idx < y->idx);
 }
 
+/* Two-means split of the points at tree positions [s, s + sz) (Section 3.1:
+ * two-means partitioning for high-dimensional data).  Reading: the two means
+ * of the node's points are found by Lloyd's iteration started from the point
+ * farthest from the node's centroid and the point farthest from that one
+ * (lowest original index on ties); a point goes to the second mean only if it
+ * is strictly nearer to it.  The iteration stops when the assignment repeats
+ * (the means are then a fixed point), when a group would be empty, or after
+ * 100 rounds.  To keep the perfect tree (leaves of at most m points, all on
+ * level L), the node is then cut at the median along the direction between
+ * the two means: points ordered by (x . (c2 - c1), original index), the left
+ * child takes the first floor(n/2).  c1 and c2 are kept in split_c. */
+static double orc_d2(const double *x, const double *y, int d)
+{
+    double r2 = 0.0;
+    for (int t = 0; t < d; t++) {
+        double df = x[t] - y[t];
+        r2 += df * df;
+    }
+    return r2;
+}
+
+static void orc_two_means_keys(orc_h2 *H, int node, int64_t s, int64_t sz, orc_key *keys)
+{
+    int d = H->d;
+    double *cen = calloc((size_t)d, sizeof(double));
+    double *c1 = H->split_c + (size_t)node * 2 * d, *c2 = c1 + d;
+    for (int64_t p = s; p < s + sz; p++)
+        for (int t = 0; t < d; t++) cen[t] += H->X[H->perm[p] * d + t];
+    for (int t = 0; t < d; t++) cen[t] /= (double)sz;
+    /* farthest point from the centroid, then farthest point from it */
+    int64_t i1 = -1, i2 = -1;
+    double best = -1.0;
+    for (int64_t p = s; p < s + sz; p++) {
+        int64_t i = H->perm[p];
+        double r2 = orc_d2(H->X + i * d, cen, d);
+        if (r2 > best || (r2 == best && i < i1)) { best = r2; i1 = i; }
+    }
+    best = -1.0;
+    for (int64_t p = s; p < s + sz; p++) {
+        int64_t i = H->perm[p];
+        double r2 = orc_d2(H->X + i * d, H->X + i1 * d, d);
+        if (r2 > best || (r2 == best && i < i2)) { best = r2; i2 = i; }
+    }
+    memcpy(c1, H->X + i1 * d, sizeof(double) * d);
+    memcpy(c2, H->X + i2 * d, sizeof(double) * d);
+    unsigned char *grp = malloc((size_t)sz), *prev = malloc((size_t)sz);
+    for (int64_t p = 0; p < sz; p++) {
+        const double *x = H->X + H->perm[s + p] * d;
+        grp[p] = orc_d2(x, c2, d) < orc_d2(x, c1, d);
+    }
+    double *m1 = malloc(sizeof(double) * d), *m2 = malloc(sizeof(double) * d);
+    for (int it = 0; it < 100; it++) {
+        int64_t n1 = 0, n2 = 0;
+        for (int t = 0; t < d; t++) m1[t] = m2[t] = 0.0;
+        for (int64_t p = 0; p < sz; p++) {
+            const double *x = H->X + H->perm[s + p] * d;
+            double *m = grp[p] ? m2 : m1;
+            for (int t = 0; t < d; t++) m[t] += x[t];
+            if (grp[p]) n2++; else n1++;
+        }
+        if (n1 == 0 || n2 == 0) break;
+        for (int t = 0; t < d; t++) { c1[t] = m1[t] / (double)n1; c2[t] = m2[t] / (double)n2; }
+        memcpy(prev, grp, (size_t)sz);
+        int changed = 0;
+        for (int64_t p = 0; p < sz; p++) {
+            const double *x = H->X + H->perm[s + p] * d;
+            grp[p] = orc_d2(x, c2, d) < orc_d2(x, c1, d);
+            changed |= grp[p] != prev[p];
+        }
+        if (!changed) break;
+    }
+    for (int64_t p = 0; p < sz; p++) {
+        int64_t i = H->perm[s + p];
+        double v = 0.0;
+        for (int t = 0; t < d; t++) v += H->X[i * d + t] * (c2[t] - c1[t]);
+        keys[p].idx = i;
+        keys[p].v = v;
+    }
+    free(cen); free(grp); free(prev); free(m1); free(m2);
+}
+
 static void orc_build_tree(orc_h2 *H)
 {
     int L = 0;
@@ -130,6 +215,7 @@ static void orc_build_tree(orc_h2 *H)
     H->left = malloc(sizeof(int) * n);
     H->right = malloc(sizeof(int) * n);
     H->level = malloc(sizeof(int) * n);
+    H->split_c = calloc((size_t)n * 2 * H->d, sizeof(double));
     for (int64_t t = 0; t < H->N; t++) H->perm[t] = t;
     H->start[0] = 0;
     H->size[0] = H->N;
@@ -144,6 +230,14 @@ static void orc_build_tree(orc_h2 *H)
         H->left[i] = l; H->right[i] = r;
         H->parent[l] = H->parent[r] = i;
         int64_t s = H->start[i], sz = H->size[i];
+        if (H->part == 1) {
+            orc_two_means_keys(H, i, s, sz, keys);
+            qsort(keys, (size_t)sz, sizeof(orc_key), orc_key_cmp);
+            for (int64_t p = 0; p < sz; p++) H->perm[s + p] = keys[p].idx;
+            H->start[l] = s;        H->size[l] = sz / 2;
+            H->start[r] = s + sz / 2; H->size[r] = sz - sz / 2;
+            continue;
+        }
         /* widest coordinate of the bounding box */
         int jstar = 0;
         double best = -1.0;
@@ -225,10 +319,57 @@ static void orc_push(orc_pairs *P, int a, int b)
     P->v[P->n].a = a; P->v[P->n].b = b; P->n++;
 }
 
+/* Far clusters / leaves ordered by centroid distance, ties by node number. */
+typedef struct { double dist; int node; } orc_fc;
+
+static int orc_fc_cmp(const void *x, const void *y)
+{
+    const orc_fc *p = (const orc_fc *)x, *q = (const orc_fc *)y;
+    if (p->dist != q->dist) return p->dist < q->dist ? -1 : 1;
+    return (p->node > q->node) - (p->node < q->node);
+}
+
+/* Budget admissibility (Section 4.1: the budget parameter of GOFMM, 0.03 for
+ * H^2-b, 0 for HSS).  Reading: every leaf is near itself and the
+ * floor(budget * #leaves) other leaves with the nearest centroids (ties by
+ * node number); the relation is made symmetric.  Two distinct nodes are
+ * admissible iff no leaf below one is near a leaf below the other.  Leaves
+ * below a node of level l are the 2^(L-l) consecutive leaves starting at
+ * (a + 1) 2^(L-l) - 1 (breadth-first numbering of a perfect tree). */
+static void orc_budget_near(orc_h2 *H)
+{
+    int L = H->L, first = (1 << L) - 1, nl = 1 << L;
+    H->leafnear = calloc((size_t)nl * nl, 1);
+    int64_t kb = (int64_t)floor(H->budget * nl);
+    if (kb > nl - 1) kb = nl - 1;
+    orc_fc *fc = malloc(sizeof(orc_fc) * nl);
+    for (int x = 0; x < nl; x++) {
+        H->leafnear[(size_t)x * nl + x] = 1;
+        int q = 0;
+        for (int y = 0; y < nl; y++)
+            if (y != x) { fc[q].node = first + y; fc[q].dist = orc_dist(H, first + x, first + y); q++; }
+        qsort(fc, (size_t)q, sizeof(orc_fc), orc_fc_cmp);
+        for (int64_t j = 0; j < kb; j++) {
+            int y = fc[j].node - first;
+            H->leafnear[(size_t)x * nl + y] = H->leafnear[(size_t)y * nl + x] = 1;
+        }
+    }
+    free(fc);
+}
+
 static int orc_admissible(const orc_h2 *H, int a, int b)
 {
     if (a == b) return 0;
     if (H->adm == 1) return 1;
+    if (H->adm == 2) {
+        int L = H->L, first = (1 << L) - 1, nl = 1 << L;
+        int64_t ca = (int64_t)1 << (L - H->level[a]), cb = (int64_t)1 << (L - H->level[b]);
+        int64_t fa = (a + 1) * ca - 1 - first, fb = (b + 1) * cb - 1 - first;
+        for (int64_t x = fa; x < fa + ca; x++)
+            for (int64_t y = fb; y < fb + cb; y++)
+                if (H->leafnear[(size_t)x * nl + y]) return 0;
+        return 1;
+    }
     return H->tau * orc_dist(H, a, b) > 2.0 * H->radius[a] + 2.0 * H->radius[b];
 }
 
@@ -275,6 +416,7 @@ static void orc_to_csr(int n, orc_pairs *P, int64_t **ptr, int **col)
 static void orc_interactions(orc_h2 *H)
 {
     orc_pairs far = {0}, near = {0};
+    if (H->adm == 2) orc_budget_near(H);
     orc_interact(H, 0, 0, &far, &near);
     H->n_far = far.n; H->n_near = near.n;
     orc_to_csr(H->n_nodes, &far, &H->far_ptr, &H->far_col);
@@ -383,15 +525,8 @@ static uint64_t orc_mix64(uint64_t z)
     return z ^ (z >> 31);
 }
 
-typedef struct { double dist; int node; } orc_fc;
 typedef struct { uint64_t key; int64_t pos; } orc_hk;
 
-static int orc_fc_cmp(const void *x, const void *y)
-{
-    const orc_fc *p = (const orc_fc *)x, *q = (const orc_fc *)y;
-    if (p->dist != q->dist) return p->dist < q->dist ? -1 : 1;
-    return (p->node > q->node) - (p->node < q->node);
-}
 
 static int orc_hk_cmp(const void *x, const void *y)
 {
@@ -632,21 +767,24 @@ void orc_free(orc_h2 *H)
     void *ptrs[] = {H->X, H->perm, H->start, H->size, H->parent, H->left, H->right, H->level,
                     H->centroid, H->radius, H->far_ptr, H->far_col, H->near_ptr, H->near_col,
                     H->rank, H->basis_off, H->basis, H->skel_ptr, H->skel, H->cap_hit,
-                    H->far_off, H->B, H->near_off, H->D};
+                    H->far_off, H->B, H->near_off, H->D, H->split_c, H->leafnear};
     for (size_t i = 0; i < sizeof(ptrs) / sizeof(ptrs[0]); i++) free(ptrs[i]);
     free(H);
 }
 
-/* Build the compressed representation from points X (N x d, original order). */
-orc_h2 *orc_build(const double *X, int64_t N, int d, int kernel, double h, int m, double tol,
-                  int rmax, int adm, double tau, int64_t S, uint64_t seed)
+/* Build the compressed representation from points X (N x d, original order).
+ * part: 0 widest-coordinate median, 1 two-means; adm: 0 distance (tau),
+ * 1 HSS, 2 budget (budget in [0, 1]). */
+orc_h2 *orc_build_ex(const double *X, int64_t N, int d, int kernel, double h, int m, double tol,
+                     int rmax, int adm, double tau, int64_t S, uint64_t seed, int part, double budget)
 {
     if (N < 1 || d < 1 || m < 2 || rmax < 0 || S < 1 || h <= 0.0 || tol < 0.0) return NULL;
+    if (part < 0 || part > 1 || adm < 0 || adm > 2 || !(budget >= 0.0 && budget <= 1.0)) return NULL;
     for (int64_t i = 0; i < N * d; i++)
         if (!isfinite(X[i])) return NULL;
     orc_h2 *H = calloc(1, sizeof(orc_h2));
     H->N = N; H->d = d; H->kernel = kernel; H->h = h; H->m = m; H->tol = tol; H->rmax = rmax;
-    H->adm = adm; H->tau = tau; H->S = S; H->seed = seed;
+    H->adm = adm; H->tau = tau; H->S = S; H->seed = seed; H->part = part; H->budget = budget;
     H->X = malloc(sizeof(double) * (size_t)N * d);
     memcpy(H->X, X, sizeof(double) * (size_t)N * d);
     orc_build_tree(H);
@@ -655,6 +793,21 @@ orc_h2 *orc_build(const double *X, int64_t N, int d, int kernel, double h, int m
     orc_compress(H);
     orc_blocks(H);
     return H;
+}
+
+orc_h2 *orc_build(const double *X, int64_t N, int d, int kernel, double h, int m, double tol,
+                  int rmax, int adm, double tau, int64_t S, uint64_t seed)
+{
+    return orc_build_ex(X, N, d, kernel, h, m, tol, rmax, adm, tau, S, seed, 0, 0.0);
+}
+
+/* The two means of a two-means split of node a (2d values: c1 then c2);
+ * returns 0 when a was not split that way. */
+int orc_split_centers(const orc_h2 *H, int a, double *out)
+{
+    if (a < 0 || a >= H->n_nodes || H->part != 1 || H->left[a] < 0) return 0;
+    memcpy(out, H->split_c + (size_t)a * 2 * H->d, sizeof(double) * 2 * H->d);
+    return 1;
 }
 
 /* Sizes: out[0..] = N, d, L, n_nodes, n_far, n_near, basis_len, B_len, D_len, skel_len. */

@@ -32,6 +32,13 @@ def lib():
         L.orc_build.argtypes = [_f64p, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                 ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                 ctypes.c_double, ctypes.c_int64, ctypes.c_uint64]
+        L.orc_build_ex.restype = ctypes.c_void_p
+        L.orc_build_ex.argtypes = [_f64p, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                   ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                   ctypes.c_double, ctypes.c_int64, ctypes.c_uint64, ctypes.c_int,
+                                   ctypes.c_double]
+        L.orc_split_centers.restype = ctypes.c_int
+        L.orc_split_centers.argtypes = [ctypes.c_void_p, ctypes.c_int, _f64p]
         L.orc_free.argtypes = [ctypes.c_void_p]
         L.orc_sizes.argtypes = [ctypes.c_void_p, _i64p]
         L.orc_ptrs.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
@@ -106,13 +113,14 @@ class OracleH2:
     """Compressed H^2 representation built by the oracle, with its arrays copied out."""
 
     def __init__(self, X: np.ndarray, *, kernel: int, h: float, m: int, tol: float, rmax: int,
-                 adm: int, tau: float, sample_rows: int = 4096, sample_seed: int = 7):
+                 adm: int, tau: float, sample_rows: int = 4096, sample_seed: int = 7,
+                 part: int = 0, budget: float = 0.0):
         X = np.ascontiguousarray(X, dtype=np.float64)
         N, d = X.shape
         self.params = dict(kernel=kernel, h=h, m=m, tol=tol, rmax=rmax, adm=adm, tau=tau,
-                           sample_rows=sample_rows, sample_seed=sample_seed)
-        self._h = lib().orc_build(_p(X, _f64p), N, d, kernel, h, m, tol, rmax, adm, tau,
-                                  sample_rows, sample_seed)
+                           sample_rows=sample_rows, sample_seed=sample_seed, part=part, budget=budget)
+        self._h = lib().orc_build_ex(_p(X, _f64p), N, d, kernel, h, m, tol, rmax, adm, tau,
+                                     sample_rows, sample_seed, part, budget)
         if not self._h:
             raise ValueError("oracle rejected the inputs")
         s = np.zeros(10, np.int64)
@@ -147,7 +155,7 @@ class OracleH2:
     @classmethod
     def from_workload(cls, w, X: np.ndarray) -> "OracleH2":
         return cls(X, kernel=w.kernel, h=w.h, m=w.m, tol=w.tol, rmax=w.rmax, adm=w.adm, tau=w.tau,
-                   sample_rows=w.sample_rows, sample_seed=w.sample_seed)
+                   sample_rows=w.sample_rows, sample_seed=w.sample_seed, part=w.part, budget=w.budget)
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -242,6 +250,13 @@ class OracleH2:
         lib().orc_exact_rows(self._h, _p(rows, _i64p), len(rows), _p(W, _f64p), W.shape[1],
                              _p(out, _f64p))
         return out
+
+    def split_centers(self, a: int):
+        """(c1, c2): the two means of node a's two-means split, or None."""
+        out = np.zeros(2 * self.d, np.float64)
+        if not lib().orc_split_centers(self._h, int(a), _p(out, _f64p)):
+            return None
+        return out[:self.d].copy(), out[self.d:].copy()
 
     def row_sample(self, a: int) -> np.ndarray:
         """Rows (tree positions, ascending) of the ID of node a."""

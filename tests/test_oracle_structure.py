@@ -13,6 +13,11 @@ CASES = [
     wl.small("mix8", N=1500, d=8, points="mixture", m=40, h=1.0),
     wl.small("hss", N=900, d=3, m=30, adm=wl.ADM_HSS),
     wl.small("single", N=50, d=3, m=64),
+    # the paper's high-d structure: two-means tree, budget admissibility (H^2-b)
+    wl.small("tm_budget", N=1500, d=8, points="mixture", m=40, h=1.0, adm=wl.ADM_BUDGET, budget=0.1,
+             part=wl.PART_TWO_MEANS),
+    wl.small("tm_distance", N=1000, d=5, points="normal", m=32, h=2.0, part=wl.PART_TWO_MEANS),
+    wl.small("budget_u3", N=1200, d=3, m=20, adm=wl.ADM_BUDGET, budget=0.05),
 ]
 
 
@@ -49,6 +54,8 @@ def test_tree_is_perfect_partition(built):
 
 def test_split_is_median_of_widest_coordinate(built):
     w, X, H = built
+    if w.part != wl.PART_MEDIAN:
+        pytest.skip("two-means tree (tests/test_oracle_highd.py)")
     for a in range(H.n_nodes):
         if H.left[a] < 0:
             continue
@@ -99,11 +106,15 @@ def test_lists_are_symmetric_and_sorted(built):
 def test_admissibility_decisions(built):
     w, X, H = built
 
+    near_leaf = budget_near_relation(w, H) if w.adm == wl.ADM_BUDGET else None
+
     def adm(a, b):
         if a == b:
             return False
         if w.adm == wl.ADM_HSS:
             return True
+        if w.adm == wl.ADM_BUDGET:
+            return not near_leaf[np.ix_(leaves_below(H, a), leaves_below(H, b))].any()
         dist = np.linalg.norm(H.centroid[a] - H.centroid[b])
         return w.tau * dist > 2 * H.radius[a] + 2 * H.radius[b]
 
@@ -114,6 +125,49 @@ def test_admissibility_decisions(built):
         assert pa == pb or not adm(pa, pb)
     for a, b, _ in H.near_pairs():
         assert not adm(a, b)
+
+
+def leaves_below(H, a):
+    """Leaf indices (0-based among the leaves, in node order) below node a."""
+    first = 2 ** H.L - 1
+    lv = [x - first for x in range(first, H.n_nodes)
+          if x == a or _is_ancestor(H, a, x)]
+    return np.array(lv, dtype=np.int64)
+
+
+def _is_ancestor(H, a, x):
+    while x > 0:
+        x = int(H.parent[x])
+        if x == a:
+            return True
+    return False
+
+
+def budget_near_relation(w, H):
+    """Near relation between leaves under the budget reading, by brute force:
+    each leaf with itself and its floor(budget * #leaves) nearest leaves by
+    centroid distance (ties by node number), made symmetric."""
+    first, nl = 2 ** H.L - 1, 2 ** H.L
+    C = H.centroid[first:first + nl]
+    kb = min(int(np.floor(w.budget * nl)), nl - 1)
+    near = np.eye(nl, dtype=bool)
+    for x in range(nl):
+        dist = np.sqrt(((C - C[x]) ** 2).sum(1))
+        order = [y for y in np.lexsort((np.arange(nl), dist)) if y != x][:kb]
+        near[x, order] = True
+        near[order, x] = True
+    return near
+
+
+def test_budget_near_lists_are_the_relation():
+    w = CASES[5]
+    H = OracleH2.from_workload(w, wl.gen_points(w))
+    near_leaf = budget_near_relation(w, H)
+    first = 2 ** H.L - 1
+    got = np.zeros_like(near_leaf)
+    for a, b, _ in H.near_pairs():
+        got[a - first, b - first] = True
+    assert np.array_equal(got, near_leaf)
 
 
 def test_hss_far_is_sibling():

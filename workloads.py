@@ -31,6 +31,10 @@ KERNEL_LAPLACE = 1   # exp(-r / h)
 
 ADM_DISTANCE = 0     # far iff tau * dist > diam(a) + diam(b)
 ADM_HSS = 1          # every off-diagonal block is far (weak admissibility)
+ADM_BUDGET = 2       # near = each leaf's budget share of nearest leaves (H^2-b); the rest far
+
+PART_MEDIAN = 0      # cut at the median of the widest coordinate
+PART_TWO_MEANS = 1   # cut at the median along the direction between two means
 
 
 @dataclasses.dataclass(frozen=True)
@@ -53,6 +57,8 @@ class Workload:
     n_comp: int = 16       # mixture components
     sample_rows: int = 4096  # row-sample cap for the ID (exact rows below it)
     sample_seed: int = 7
+    part: int = PART_MEDIAN  # tree partitioner
+    budget: float = 0.0      # ADM_BUDGET: near leaves per leaf = floor(budget * #leaves)
 
     def key(self) -> str:
         return hashlib.sha256(repr(dataclasses.astuple(self)).encode()).hexdigest()[:16]
@@ -67,6 +73,12 @@ C1 = Workload("c1_n4096_d3_uniform", N=4096, d=3, points="uniform", point_seed=0
 C2 = Workload("c2_n65536_d8_mixture", N=65536, d=8, points="mixture", point_seed=0,
               kernel=KERNEL_GAUSSIAN, h=1.0, m=128, tol=1e-5, rmax=128,
               adm=ADM_DISTANCE, tau=2.0, Q=256)
+
+# The headline points under the paper's high-d structure (Section 3.1: two-means
+# tree for d > 3; Section 4.1: budget 0.03, "H^2-b").
+C2B = Workload("c2b_n65536_d8_mixture_two_means_budget", N=65536, d=8, points="mixture", point_seed=0,
+               kernel=KERNEL_GAUSSIAN, h=1.0, m=128, tol=1e-5, rmax=128,
+               adm=ADM_BUDGET, tau=2.0, Q=256, part=PART_TWO_MEANS, budget=0.03)
 
 # Mixed-precision case: 262144 points, d=28 i.i.d. normal, Laplace, HSS.
 C4 = Workload("c4_n262144_d28_normal", N=262144, d=28, points="normal", point_seed=0,
@@ -115,11 +127,12 @@ def serving_workloads() -> list[Workload]:
 def small(name: str, N: int, d: int = 3, points: str = "uniform", m: int = 32,
           Q: int = 8, adm: int = ADM_DISTANCE, kernel: int = KERNEL_GAUSSIAN,
           h: float = 0.5, tol: float = 1e-6, rmax: int = 64, tau: float = 2.0,
-          seed: int = 3, sample_rows: int = 4096) -> Workload:
+          seed: int = 3, sample_rows: int = 4096, part: int = PART_MEDIAN,
+          budget: float = 0.0) -> Workload:
     """A small workload for unit tests and edge cases."""
     return Workload(name, N=N, d=d, points=points, point_seed=seed, kernel=kernel, h=h,
                     m=m, tol=tol, rmax=rmax, adm=adm, tau=tau, Q=Q, w_seed=seed + 1,
-                    sample_rows=sample_rows)
+                    sample_rows=sample_rows, part=part, budget=budget)
 
 
 def gen_points(w: Workload) -> np.ndarray:
