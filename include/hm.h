@@ -349,9 +349,11 @@ hm_status hm_server_destroy(hm_server s);
  * interaction computation, sampling, ID low-rank approximation).  Runs on the
  * host CPU threads; its output feeds hm_load_compressed_mem.  Readings of the
  * steps the paper leaves open: a perfect binary tree cut at the median of the
- * widest coordinate; far iff tau * centroid distance > diam(a) + diam(b)
+ * widest coordinate (or, with partitioner 1, along the direction between the
+ * two means of Lloyd's 2-means of the node's points: Section 3.1 two-means
+ * partitioning); far iff tau * centroid distance > diam(a) + diam(b)
  * (diam = twice the largest distance to the centroid), or every off-diagonal
- * pair for HSS; ID rows = the whole far field when it has at most sample_rows
+ * pair for HSS, or the budget rule below (Section 4.1); ID rows = the whole far field when it has at most sample_rows
  * points, otherwise half from the nearest far clusters and half by a seeded
  * SplitMix64 key; pivoted-QR ID with rank = first j with |R_jj| <= tol |R_11|,
  * capped at max_rank. */
@@ -361,11 +363,16 @@ typedef struct {
     int32_t leaf_size;      /* m >= 2: leaves hold at most m points */
     double tol;             /* ID tolerance relative to |R_11| (>= 0) */
     int32_t max_rank;       /* rank cap */
-    int32_t admissibility;  /* 0 distance (uses tau), 1 HSS */
+    int32_t admissibility;  /* 0 distance (uses tau), 1 HSS, 2 budget (uses budget; H^2-b) */
     double tau;
     int64_t sample_rows;    /* row-sample cap S of each ID */
     uint64_t seed;          /* sample seed */
     int32_t threads;        /* host threads (0 = all hardware threads) */
+    int32_t partitioner;    /* 0 median of the widest coordinate, 1 two-means direction (d > 3) */
+    double budget;          /* admissibility 2: each leaf is near itself and its
+                               floor(budget * #leaves) nearest leaves by centroid distance
+                               (symmetrized); two nodes are far iff no leaf below one is near a
+                               leaf below the other.  0.03 is the paper's H^2-b, 0 gives HSS */
 } hm_compress_opts;
 
 typedef struct hm_repr_s *hm_repr;  /* library-owned host representation */

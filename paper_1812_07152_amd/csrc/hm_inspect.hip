@@ -112,6 +112,10 @@ struct Inspector {
                 R.level[a] = lev;
                 if (lev == L) return;
                 const int64_t s = R.start[a], sz = R.size[a];
+                if (o.partitioner == 1) {
+                    two_means_split(a, s, sz);
+                    return;
+                }
                 int jstar = 0;
                 double best = -1.0;
                 for (int64_t t = 0; t < d; t++) {
@@ -142,6 +146,99 @@ struct Inspector {
         }
     }
 
+    static double dist2(const double *x, const double *y, int64_t d) {
+        double r2 = 0.0;
+        for (int64_t t = 0; t < d; t++) {
+            const double df = x[t] - y[t];
+            r2 += df * df;
+        }
+        return r2;
+    }
+
+    // Two-means split of node a over tree positions [s, s + sz): Lloyd's
+    // 2-means from the point farthest from the centroid and the point
+    // farthest from it (lowest index on ties; a point joins the second mean
+    // only when strictly nearer), until the assignment repeats (at most 100
+    // rounds, or until a group would be empty); then the median cut along the
+    // direction between the two means, points ordered by (projection, index).
+    void two_means_split(int a, int64_t s, int64_t sz) {
+        std::vector<double> cen((size_t)d, 0.0), c1((size_t)d), c2((size_t)d), m1((size_t)d), m2((size_t)d);
+        const int64_t *pp = R.perm.data() + s;
+        for (int64_t p = 0; p < sz; p++)
+            for (int64_t t = 0; t < d; t++) cen[(size_t)t] += X[pp[p] * d + t];
+        for (int64_t t = 0; t < d; t++) cen[(size_t)t] /= (double)sz;
+        int64_t i1 = -1, i2 = -1;
+        double best = -1.0;
+        for (int64_t p = 0; p < sz; p++) {
+            const int64_t i = pp[p];
+            const double r2 = dist2(X + i * d, cen.data(), d);
+            if (r2 > best || (r2 == best && i < i1)) {
+                best = r2;
+                i1 = i;
+            }
+        }
+        best = -1.0;
+        for (int64_t p = 0; p < sz; p++) {
+            const int64_t i = pp[p];
+            const double r2 = dist2(X + i * d, X + i1 * d, d);
+            if (r2 > best || (r2 == best && i < i2)) {
+                best = r2;
+                i2 = i;
+            }
+        }
+        std::copy(X + i1 * d, X + i1 * d + d, c1.begin());
+        std::copy(X + i2 * d, X + i2 * d + d, c2.begin());
+        std::vector<unsigned char> grp((size_t)sz), prev((size_t)sz);
+        for (int64_t p = 0; p < sz; p++) {
+            const double *x = X + pp[p] * d;
+            grp[(size_t)p] = dist2(x, c2.data(), d) < dist2(x, c1.data(), d);
+        }
+        for (int it = 0; it < 100; it++) {
+            int64_t n1 = 0, n2 = 0;
+            std::fill(m1.begin(), m1.end(), 0.0);
+            std::fill(m2.begin(), m2.end(), 0.0);
+            for (int64_t p = 0; p < sz; p++) {
+                const double *x = X + pp[p] * d;
+                std::vector<double> &m = grp[(size_t)p] ? m2 : m1;
+                for (int64_t t = 0; t < d; t++) m[(size_t)t] += x[t];
+                if (grp[(size_t)p])
+                    n2++;
+                else
+                    n1++;
+            }
+            if (n1 == 0 || n2 == 0) break;
+            for (int64_t t = 0; t < d; t++) {
+                c1[(size_t)t] = m1[(size_t)t] / (double)n1;
+                c2[(size_t)t] = m2[(size_t)t] / (double)n2;
+            }
+            prev = grp;
+            bool changed = false;
+            for (int64_t p = 0; p < sz; p++) {
+                const double *x = X + pp[p] * d;
+                grp[(size_t)p] = dist2(x, c2.data(), d) < dist2(x, c1.data(), d);
+                changed |= grp[(size_t)p] != prev[(size_t)p];
+            }
+            if (!changed) break;
+        }
+        std::vector<std::pair<double, int64_t>> key((size_t)sz);
+        for (int64_t p = 0; p < sz; p++) {
+            const int64_t i = pp[p];
+            double v = 0.0;
+            for (int64_t t = 0; t < d; t++) v += X[i * d + t] * (c2[(size_t)t] - c1[(size_t)t]);
+            key[(size_t)p] = {v, i};
+        }
+        std::sort(key.begin(), key.end());
+        for (int64_t p = 0; p < sz; p++) R.perm[(size_t)(s + p)] = key[(size_t)p].second;
+        const int l = 2 * a + 1, r = 2 * a + 2;
+        R.left[a] = l;
+        R.right[a] = r;
+        R.parent[l] = R.parent[r] = a;
+        R.start[l] = s;
+        R.size[l] = sz / 2;
+        R.start[r] = s + sz / 2;
+        R.size[r] = sz - sz / 2;
+    }
+
     void geometry() {
         const int n = R.n_nodes;
         cen.assign((size_t)n * d, 0.0);
@@ -164,13 +261,56 @@ struct Inspector {
         });
     }
 
+    // Budget admissibility: near leaves as a prefix-summed 0/1 matrix, so
+    // that "some leaf below a is near some leaf below b" is one lookup.
+    int nl_ = 0, first_leaf_ = 0;
+    std::vector<int32_t> near_sum_;  // (nl+1) x (nl+1) inclusive prefix sums
+
+    void budget_near() {
+        const int L = R.depth;
+        nl_ = 1 << L;
+        first_leaf_ = nl_ - 1;
+        int64_t kb = (int64_t)std::floor(o.budget * nl_);
+        kb = std::min<int64_t>(kb, nl_ - 1);
+        std::vector<unsigned char> nearm((size_t)nl_ * nl_, 0);
+        std::vector<std::pair<double, int>> cl;
+        for (int x = 0; x < nl_; x++) {
+            nearm[(size_t)x * nl_ + x] = 1;
+            cl.clear();
+            for (int y = 0; y < nl_; y++)
+                if (y != x) cl.push_back({cdist(first_leaf_ + x, first_leaf_ + y), first_leaf_ + y});
+            std::partial_sort(cl.begin(), cl.begin() + kb, cl.end());
+            for (int64_t j = 0; j < kb; j++) {
+                const int y = cl[(size_t)j].second - first_leaf_;
+                nearm[(size_t)x * nl_ + y] = nearm[(size_t)y * nl_ + x] = 1;
+            }
+        }
+        near_sum_.assign((size_t)(nl_ + 1) * (nl_ + 1), 0);
+        for (int x = 0; x < nl_; x++)
+            for (int y = 0; y < nl_; y++)
+                near_sum_[(size_t)(x + 1) * (nl_ + 1) + y + 1] = nearm[(size_t)x * nl_ + y] +
+                                                                  near_sum_[(size_t)x * (nl_ + 1) + y + 1] +
+                                                                  near_sum_[(size_t)(x + 1) * (nl_ + 1) + y] -
+                                                                  near_sum_[(size_t)x * (nl_ + 1) + y];
+    }
+
     bool admissible(int a, int b) const {
         if (a == b) return false;
         if (o.admissibility == 1) return true;
+        if (o.admissibility == 2) {
+            // leaves below a node of level l: 2^(L-l) consecutive ones from (a+1) 2^(L-l) - 1
+            const int64_t ca = (int64_t)1 << (R.depth - R.level[a]), cb = (int64_t)1 << (R.depth - R.level[b]);
+            const int64_t fa = (a + 1) * ca - 1 - first_leaf_, fb = (b + 1) * cb - 1 - first_leaf_;
+            const int64_t w = nl_ + 1;
+            const int32_t cnt = near_sum_[(size_t)((fa + ca) * w + fb + cb)] - near_sum_[(size_t)(fa * w + fb + cb)] -
+                                near_sum_[(size_t)((fa + ca) * w + fb)] + near_sum_[(size_t)(fa * w + fb)];
+            return cnt == 0;
+        }
         return o.tau * cdist(a, b) > 2.0 * rad[a] + 2.0 * rad[b];
     }
 
     void interactions() {
+        if (o.admissibility == 2) budget_near();
         std::vector<std::pair<int, int>> far, near;
         std::vector<std::pair<int, int>> stack{{0, 0}};
         while (!stack.empty()) {
@@ -427,7 +567,8 @@ hm_status hm_compress(const double *X, int64_t N, int64_t d, const hm_compress_o
     if (N < 1 || d < 1) return fail(HM_ERR_INVALID, "hm_compress: need N >= 1 and d >= 1");
     if (opts->leaf_size < 2 || opts->max_rank < 0 || opts->sample_rows < 1 || !(opts->h > 0.0) ||
         !(opts->tol >= 0.0) || (opts->kernel != 0 && opts->kernel != 1) ||
-        (opts->admissibility != 0 && opts->admissibility != 1))
+        opts->admissibility < 0 || opts->admissibility > 2 || opts->partitioner < 0 || opts->partitioner > 1 ||
+        !(opts->budget >= 0.0 && opts->budget <= 1.0))
         return fail(HM_ERR_INVALID, "hm_compress: invalid options");
     for (int64_t i = 0; i < N * d; i++)
         if (!std::isfinite(X[i])) return fail(HM_ERR_INVALID, "hm_compress: non-finite point coordinate");
@@ -447,7 +588,7 @@ hm_status hm_compress(const double *X, int64_t N, int64_t d, const hm_compress_o
     R.tau = opts->tau;
     R.rmax = opts->max_rank;
     R.m = opts->leaf_size;
-    R.flags = opts->admissibility == 1 ? 1u : 0u;
+    R.flags = opts->admissibility == 1 ? 1u : opts->admissibility == 2 ? 2u : 0u;
     r->skel_ptr.assign(R.n_nodes + 1, 0);
     for (int a = 0; a < R.n_nodes; a++) {
         r->skel_ptr[a + 1] = r->skel_ptr[a] + (int64_t)I.skel[a].size();
@@ -468,8 +609,9 @@ hm_status hm_inspect_p1(const double *X, int64_t N, int64_t d, const hm_compress
     *out = nullptr;
     if (!X || !opts) return fail(HM_ERR_INVALID, "hm_inspect_p1: NULL argument");
     if (N < 1 || d < 1) return fail(HM_ERR_INVALID, "hm_inspect_p1: need N >= 1 and d >= 1");
-    if (opts->leaf_size < 2 || opts->sample_rows < 1 || (opts->admissibility != 0 && opts->admissibility != 1) ||
-        !(opts->tau >= 0.0))
+    if (opts->leaf_size < 2 || opts->sample_rows < 1 || opts->admissibility < 0 || opts->admissibility > 2 ||
+        !(opts->tau >= 0.0) || opts->partitioner < 0 || opts->partitioner > 1 ||
+        !(opts->budget >= 0.0 && opts->budget <= 1.0))
         return fail(HM_ERR_INVALID, "hm_inspect_p1: invalid options");
     for (int64_t i = 0; i < N * d; i++)
         if (!std::isfinite(X[i])) return fail(HM_ERR_INVALID, "hm_inspect_p1: non-finite point coordinate");
@@ -499,7 +641,7 @@ hm_status hm_inspect_p1(const double *X, int64_t N, int64_t d, const hm_compress
     S.tau = opts->tau;
     S.r.m = opts->leaf_size;
     S.r.tau = opts->tau;
-    S.r.flags = opts->admissibility == 1 ? 1u : 0u;
+    S.r.flags = opts->admissibility == 1 ? 1u : opts->admissibility == 2 ? 2u : 0u;
     *out = st;
     return HM_OK;
 }

@@ -57,7 +57,7 @@ class hm_compress_opts(ctypes.Structure):
                 ("tol", ctypes.c_double), ("max_rank", ctypes.c_int32),
                 ("admissibility", ctypes.c_int32), ("tau", ctypes.c_double),
                 ("sample_rows", ctypes.c_int64), ("seed", ctypes.c_uint64),
-                ("threads", ctypes.c_int32)]
+                ("threads", ctypes.c_int32), ("partitioner", ctypes.c_int32), ("budget", ctypes.c_double)]
 
 
 class hm_structure_info_t(ctypes.Structure):
@@ -293,10 +293,10 @@ class Repr:
 
 def hm_compress(X: np.ndarray, *, kernel: int, h: float, leaf_size: int, tol: float, max_rank: int,
                 admissibility: int, tau: float, sample_rows: int = 4096, seed: int = 7,
-                threads: int = 0) -> Repr:
+                threads: int = 0, partitioner: int = 0, budget: float = 0.0) -> Repr:
     X = np.ascontiguousarray(X, dtype=np.float64)
     o = hm_compress_opts(kernel, h, leaf_size, tol, max_rank, admissibility, tau, sample_rows, seed,
-                         threads)
+                         threads, partitioner, budget)
     out = _P()
     _check(lib.hm_compress(X.ctypes.data, X.shape[0], X.shape[1], ctypes.byref(o), ctypes.byref(out)))
     return Repr(out.value)
@@ -328,10 +328,11 @@ class Structure:
 
 
 def hm_inspect_p1(X: np.ndarray, *, leaf_size: int, admissibility: int, tau: float, sample_rows: int = 4096,
-                  seed: int = 7, threads: int = 0) -> Structure:
+                  seed: int = 7, threads: int = 0, partitioner: int = 0, budget: float = 0.0) -> Structure:
     """inspector-p1 (host): tree, far/near lists and row samples."""
     X = np.ascontiguousarray(X, dtype=np.float64)
-    o = hm_compress_opts(0, 1.0, leaf_size, 0.0, 1, admissibility, tau, sample_rows, seed, threads)
+    o = hm_compress_opts(0, 1.0, leaf_size, 0.0, 1, admissibility, tau, sample_rows, seed, threads,
+                         partitioner, budget)
     out = _P()
     _check(lib.hm_inspect_p1(X.ctypes.data, X.shape[0], X.shape[1], ctypes.byref(o), ctypes.byref(out)))
     return Structure(out.value)

@@ -37,6 +37,8 @@ CASES = {
                            h=1.0, tol=1e-10, rmax=200, Q=5),
     "tall_tiles_d28": wl.small("tall28", N=3000, d=28, points="normal", m=256, adm=wl.ADM_HSS,
                                kernel=wl.KERNEL_LAPLACE, h=4.0, tol=1e-8, rmax=200, Q=5),
+    "tm_budget": wl.small("tm_budget", N=3000, d=8, points="mixture", m=50, h=1.0, adm=wl.ADM_BUDGET,
+                          budget=0.1, part=wl.PART_TWO_MEANS, Q=24),
 }
 _built = {}
 

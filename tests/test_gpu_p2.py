@@ -51,12 +51,14 @@ CASES = {
                      kernel=wl.KERNEL_LAPLACE, h=4.0, tol=1e-4, rmax=200, Q=40),
     "deep_small_leaves": wl.small("deep", N=2048, d=3, m=8, Q=4, rmax=8),
     "single_node": wl.small("single_node", N=100, d=3, m=128, Q=5),
+    "tm_budget": wl.small("tm_budget", N=3000, d=8, points="mixture", m=50, h=1.0, adm=wl.ADM_BUDGET,
+                          budget=0.1, part=wl.PART_TWO_MEANS, Q=20),
 }
 
 
 def p1_of(hmx, w, X):
     return hmx.hm_inspect_p1(X, leaf_size=w.m, admissibility=w.adm, tau=w.tau, sample_rows=w.sample_rows,
-                             seed=w.sample_seed)
+                             seed=w.sample_seed, partitioner=w.part, budget=w.budget)
 
 
 def candidates(H, a):

@@ -61,6 +61,10 @@ CASES = {
     "tall": wl.small("tall", N=4096, d=28, points="normal", m=256, adm=wl.ADM_HSS,
                      kernel=wl.KERNEL_LAPLACE, h=4.0, tol=1e-4, rmax=200, Q=40),
     "deep_small_leaves": wl.small("deep", N=2048, d=3, m=8, Q=4, rmax=8),
+    # the paper's high-d structure: two-means tree and budget admissibility
+    # (far pairs on six levels, near lists of a budget share of the leaves)
+    "tm_budget": wl.small("tm_budget", N=3000, d=8, points="mixture", m=50, h=1.0, adm=wl.ADM_BUDGET,
+                          budget=0.1, part=wl.PART_TWO_MEANS, Q=24),
 }
 _built = {}
 
@@ -211,7 +215,7 @@ def test_c2_full_size_sampled_columns(hmx, sched):
         assert err32 <= 2e-5
 
 
-@pytest.mark.parametrize("name", ["c1", "mix8", "hss_lap", "deep_small_leaves"])
+@pytest.mark.parametrize("name", ["c1", "mix8", "hss_lap", "deep_small_leaves", "tm_budget"])
 def test_mixed_precision_bf16x3(hmx, name, sched):
     """Split-BF16 near/far/leaf-basis products with FP32 accumulation, FP64
     transfers and final sum.  Bar: 5e-5 relative Frobenius against the FP64
@@ -291,3 +295,30 @@ def test_mixed_precision_shapes_and_flags(hmx, sched):
     hmx.hm_eval(M, Wt, Yt, prec=hmx.HM_PREC_BF16X3, flags=hmx.HM_TREE_ORDER)
     hmx.hm_check(M)
     assert rel(Yt.cpu().numpy(), Yref[H.perm]) <= 5e-5
+
+
+@pytest.mark.timeout(900)
+def test_c2b_full_size_sampled_columns(hmx, sched):
+    """The headline points under the paper's high-d structure (two-means tree,
+    budget 0.03: H^2-b) at full size, Q = 256, against the oracle's tree walk
+    on 4 sampled columns; FP64 to the parity bar, split BF16 within the
+    workload's tol."""
+    w = wl.C2B
+    _say("[parity] c2b full size: oracle compression")
+    X = wl.gen_points(w)
+    H = OracleH2.from_workload(w, X)
+    M = hmx.hm_load_compressed_mem(H, 0, hmx.precbit(hmx.HM_PREC_FP64) | hmx.precbit(hmx.HM_PREC_BF16X3))
+    W = wl.gen_w(w)
+    _say("[parity] c2b full size: gpu eval Q=256")
+    Y = gpu_eval(hmx, M, W)
+    cols = np.random.default_rng(43).choice(w.Q, 4, replace=False)
+    Yref = H.eval(np.ascontiguousarray(W[:, cols]))
+    check_f64(Y[:, cols], Yref)
+    if sched == "graph":
+        Wd = torch.from_numpy(W).cuda()
+        Yd = torch.full_like(Wd, float("nan"))
+        hmx.hm_eval(M, Wd, Yd, prec=hmx.HM_PREC_BF16X3)
+        hmx.hm_check(M)
+        err = rel(Yd.cpu().numpy()[:, cols], Yref)
+        _say(f"[mixed] case=c2b full size rel err={err:.3e}")
+        assert err <= w.tol

@@ -19,6 +19,11 @@ CASES = [
     wl.small("hss_lap", N=900, d=3, m=30, adm=wl.ADM_HSS, kernel=wl.KERNEL_LAPLACE, h=2.0, rmax=30),
     wl.small("sampled", N=3000, d=3, m=40, sample_rows=300),
     wl.small("single", N=60, d=3, m=64),
+    wl.small("tm_budget", N=2000, d=8, points="mixture", m=40, h=1.0, adm=wl.ADM_BUDGET, budget=0.1,
+             part=wl.PART_TWO_MEANS),
+    wl.small("tm_distance_lap", N=1500, d=6, points="normal", m=32, h=2.0, kernel=wl.KERNEL_LAPLACE,
+             part=wl.PART_TWO_MEANS),
+    wl.small("budget_u3", N=1500, d=3, m=20, adm=wl.ADM_BUDGET, budget=0.05),
 ]
 
 
@@ -26,7 +31,7 @@ def compress(w, X):
     from paper_1812_07152_amd import hm_compress
     return hm_compress(X, kernel=w.kernel, h=w.h, leaf_size=w.m, tol=w.tol, max_rank=w.rmax,
                        admissibility=w.adm, tau=w.tau, sample_rows=w.sample_rows,
-                       seed=w.sample_seed, threads=4)
+                       seed=w.sample_seed, threads=4, partitioner=w.part, budget=w.budget)
 
 
 @pytest.mark.parametrize("w", CASES, ids=[c.name for c in CASES])
