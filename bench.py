@@ -563,6 +563,61 @@ def bench_mixed(args) -> dict:
     }
 
 
+def bench_h2b(args) -> dict:
+    """The headline points (N = 65536, d = 8, Q = 256) under the paper's
+    structure for high-dimensional data: two-means tree (Section 3.1) and
+    budget admissibility 0.03, "H^2-b" (Section 4.1).  Built by inspector-p1
+    (host) and inspector-p2 on the GPU; FP64 and split BF16, with eps_f on
+    256 sampled rows against the exact product."""
+    import numpy as np
+    import torch
+
+    import paper_1812_07152_amd as hmx
+    import workloads as wl
+    from oracle.oracle import exact_rows
+
+    w = wl.C2B
+    X = wl.gen_points(w)
+    t = time.perf_counter()
+    S = hmx.hm_inspect_p1(X, leaf_size=w.m, admissibility=w.adm, tau=w.tau, sample_rows=w.sample_rows,
+                          seed=w.sample_seed, partitioner=w.part, budget=w.budget)
+    t_p1 = time.perf_counter() - t
+    t = time.perf_counter()
+    M = hmx.hm_inspect_p2_load(S, 0, kernel=w.kernel, h=w.h, tol=w.tol, max_rank=w.rmax,
+                               prec_mask=hmx.precbit(hmx.HM_PREC_FP64) | hmx.precbit(hmx.HM_PREC_BF16X3))
+    torch.cuda.synchronize()
+    t_p2 = time.perf_counter() - t
+    info = hmx.hm_info(M)
+    flops = info["flops_per_col"] * w.Q
+    W = torch.from_numpy(wl.gen_w(w)).cuda()
+    ms64, ph64, n64, Y64 = time_variant(hmx, torch, M, W, args.steps, args.warmup)
+    msm, phm, nm, Ym = time_variant(hmx, torch, M, W, args.steps, args.warmup, prec=hmx.HM_PREC_BF16X3)
+    graph_ms = ph64[3] / max(n64[3], 1)
+    rows = np.random.default_rng(12).choice(w.N, 256, replace=False)
+    cols = np.arange(16)
+    Yex = exact_rows(X, w.kernel, w.h, rows, W[:, cols].cpu().numpy())
+
+    def eps(Y):
+        Ys = Y[:, :16].cpu().numpy()[rows]
+        return float(np.linalg.norm(Ys - Yex) / np.linalg.norm(Yex))
+
+    return {
+        "metric": "K~W GFLOP/s (algorithmic), H^2-b structure", "value": flops / (ms64 * 1e-3) / 1e9,
+        "unit": "GFLOP/s", "ms_per_step": ms64, "dtype": "f64",
+        "config": {"workload": w.name, "N": w.N, "d": w.d, "Q": w.Q, "partitioner": "two-means",
+                   "admissibility": f"budget {w.budget}", "leaf": w.m, "tol": w.tol, "max_rank": w.rmax,
+                   "n_near_pairs": info["n_near"], "n_far_pairs": info["n_far"], "gflop_per_step": flops / 1e9,
+                   "E_V": info["E_V"], "E_T": info["E_T"], "E_B": info["E_B"], "E_D": info["E_D"]},
+        "roofline": {"bound": "mfma", "kernel": "k_persistent<double,...> (task-graph launch)",
+                     "achieved": flops / (graph_ms * 1e-3) / 1e12, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": flops / (graph_ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, "launch_ms": graph_ms},
+        "mixed_bf16x3": {"ms_per_step": msm, "value": flops / (msm * 1e-3) / 1e9, "speedup_vs_fp64": ms64 / msm,
+                         "rel_err_vs_gpu_fp64": float(torch.linalg.norm(Ym - Y64) / torch.linalg.norm(Y64))},
+        "eps_f_sampled": {"fp64": eps(Y64), "mixed_bf16x3": eps(Ym), "rows": 256, "columns": 16},
+        "setup_s": {"p1_host": t_p1, "p2_gpu_and_store": t_p2},
+    }
+
+
 def bench_compression(args) -> dict:
     """Reusing inspection (paper Section 5, its Fig. 10 scenario): the headline
     workload (N = 65536, d = 8) compressed for five accuracies 1e-1 ... 1e-5.
@@ -655,7 +710,7 @@ def main() -> int:
                     help="mixed form: skip the N=65536 workload reported beside the main one")
     ap.add_argument("--mixed-c2-only", action="store_true",
                     help="mixed form: run the N=65536 workload alone")
-    ap.add_argument("--form", choices=("plain", "batched", "serving", "mixed", "points", "compression"),
+    ap.add_argument("--form", choices=("plain", "batched", "serving", "mixed", "points", "compression", "h2b"),
                     default="plain",
                     help="plain: the headline workload; batched: 64 uneven matrices in one launch; "
                          "serving: 8 resident matrices under a request stream; mixed: split BF16; "
@@ -688,6 +743,9 @@ def main() -> int:
         return 0
     if args.form == "compression":
         print(json.dumps(bench_compression(args)), flush=True)
+        return 0
+    if args.form == "h2b":
+        print(json.dumps(bench_h2b(args)), flush=True)
         return 0
 
     import numpy as np
@@ -834,6 +892,9 @@ def main() -> int:
             t = time.perf_counter()
             out["forms"]["mixed_c4"] = compact(bench_mixed_c4(args))
             print(f"[bench] mixed C4 form done ({time.perf_counter() - t:.0f} s)", file=sys.stderr, flush=True)
+        t = time.perf_counter()
+        out["forms"]["h2b_structure"] = compact(bench_h2b(args))
+        print(f"[bench] H^2-b structure done ({time.perf_counter() - t:.0f} s)", file=sys.stderr, flush=True)
         t = time.perf_counter()
         out["forms"]["compression_reuse"] = compact(bench_compression(args))
         print(f"[bench] compression reuse done ({time.perf_counter() - t:.0f} s)", file=sys.stderr, flush=True)
