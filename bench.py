@@ -704,6 +704,8 @@ def main() -> int:
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the batched, served and N=262144 mixed-precision forms after the headline")
     ap.add_argument("--no-c4", action="store_true", help="skip the N=262144 mixed-precision form")
+    ap.add_argument("--no-symmetric", dest="symmetric", action="store_false",
+                    help="skip the symmetric-store variant of the headline step")
     ap.add_argument("--no-near-from-points", dest="near_from_points", action="store_false",
                     help="skip the matrix-free near-field variant of the FP64 step")
     ap.add_argument("--mixed-c4-only", dest="mixed_both", action="store_false",
@@ -767,7 +769,7 @@ def main() -> int:
     M = hmx.hm_load_compressed_mem(R, 0, precs)
     t_load = time.perf_counter() - t
     info = hmx.hm_info(M)
-    if not args.near_from_points:
+    if not (args.near_from_points or args.symmetric):
         del R
     flops = info["flops_per_col"] * w.Q
     W64 = torch.from_numpy(Wn).to("cuda", torch.float64)
@@ -825,6 +827,28 @@ def main() -> int:
             "launch_ms": phm[3] / max(nm[3], 1), "speedup_vs_fp64": ms64 / msm,
             "rel_err_vs_gpu_fp64": float(np.linalg.norm(results["mixed_bf16x3"] - results["fp64"])
                                          / np.linalg.norm(results["fp64"]))}
+    if args.symmetric:
+        # symmetric store: each far and near block of a pair stored once, the
+        # mirror product reading it transposed (same results bitwise)
+        t = time.perf_counter()
+        Ms = hmx.hm_load_compressed_mem(R, 0, precs | hmx.HM_LOAD_SYMMETRIC)
+        t_sload = time.perf_counter() - t
+        sinfo = hmx.hm_info(Ms)
+        sym = {"store_gb_fp64": sinfo["bytes_fp64"] / 1e9, "store_gb_fp32": sinfo["bytes_fp32"] / 1e9,
+               "load_s": t_sload}
+        mss, phs, nss, Ys = time_variant(hmx, torch, Ms, W64, args.steps, args.warmup)
+        sym["fp64"] = {"ms_per_step": mss, "value": flops / (mss * 1e-3) / 1e9, "launch_ms": phs[3] / max(nss[3], 1),
+                       "speedup_vs_full_store": ms64 / mss,
+                       "bitwise_equal_to_full_store": bool(np.array_equal(Ys.cpu().numpy(), results["fp64"]))}
+        if not args.no_fp32:
+            ms32s, _, _, _ = time_variant(hmx, torch, Ms, W64.float(), args.steps, args.warmup)
+            sym["fp32"] = {"ms_per_step": ms32s, "speedup_vs_full_store": out["fp32"]["ms_per_step"] / ms32s}
+        if not args.no_mixed:
+            msms, _, _, _ = time_variant(hmx, torch, Ms, W64, args.steps, args.warmup, prec=hmx.HM_PREC_BF16X3)
+            sym["mixed_bf16x3"] = {"ms_per_step": msms,
+                                   "speedup_vs_full_store": out["mixed_bf16x3"]["ms_per_step"] / msms}
+        out["symmetric_store"] = sym
+        del Ms
     if args.near_from_points:
         # matrix-free near field: the same FP64 step with every near block
         # computed from the points in the product tiles (stored blocks unread)

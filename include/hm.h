@@ -76,6 +76,15 @@ typedef enum { HM_PREC_FP64 = 0, HM_PREC_FP32 = 1, HM_PREC_BF16X3 = 2 } hm_prec;
  * skeletons (skel_ptr/skel; HM_ERR_INVALID otherwise); every hm_eval on the
  * matrix must then pass HM_FAR_FROM_POINTS. */
 #define HM_LOAD_NO_FAR_BLOCKS (1u << 9)
+/* prec_mask bit: symmetric storage.  The kernel matrix is symmetric
+ * (Section 1), so B_ba = B_ab^T and D_ba = D_ab^T: each far and near block of
+ * an unordered pair is stored once (for the lower node number) and the other
+ * product reads it transposed; the FP64 and FP32 stores hold about half the
+ * bytes (the split-BF16 store keeps both orientations).  The representation
+ * must be symmetric bitwise (partner in the other node's list, transposed
+ * values): HM_ERR_FORMAT otherwise.  Results equal those of the full store
+ * bitwise. */
+#define HM_LOAD_SYMMETRIC (1u << 10)
 
 /* hm_eval flags */
 #define HM_TREE_ORDER 1u  /* W and Y are already in tree order: skip both permutes */

@@ -285,7 +285,7 @@ hm_status hm_eval(hm_matrix h, const void *W, int64_t ldw, void *Y, int64_t ldy,
     int grid = 0;
     GraphPlan *plan = nullptr;
     if (!level_sched) {
-        const int workers = std::max(1, persistent_occupancy(es, bn_kind[3], mixed) * h->n_cu);
+        const int workers = std::max(1, persistent_occupancy(es, bn_kind[3], mixed, h->symmetric) * h->n_cu);
         hm_status pst = get_plan(h, slot, bn_kind[3], Qp, workers, &plan, mixed ? 1 : 0);
         if (pst != HM_OK) return pst;
         MatDesc md{h->prec[mixed ? HM_PREC_FP64 : prec].blocks, {bufs[0], bufs[1], bufs[2], bufs[3]},

@@ -110,7 +110,9 @@ hm_status configure(hm_batch b, int bn) {
         parts.push_back({h, i, (int)(b->ldq[i] / bn)});
     }
     HM_HIP(hipMemcpy(b->d_mats, mats.data(), sizeof(MatDesc) * b->n, hipMemcpyHostToDevice));
-    const int occ = persistent_occupancy(b->es, bn);
+    bool sym = false;
+    for (int i = 0; i < b->n; i++) sym = sym || b->hs[i]->symmetric;
+    const int occ = persistent_occupancy(b->es, bn, false, sym);
     const int workers = std::max(1, occ * b->hs[0]->n_cu);
     hm_status st = build_plan(parts, bn, b->es, workers, b->plan);
     if (st != HM_OK) return st;

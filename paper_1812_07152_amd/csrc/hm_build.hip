@@ -16,12 +16,54 @@
 // The root has no far pairs (it overlaps every node), so it is skipped.
 #include <algorithm>
 #include <cstring>
+#include <map>
 
 #include "hm_internal.h"
 
 namespace hm {
 
 namespace {
+
+// A symmetric store needs B_ba = B_ab^T and D_ba = D_ab^T (the kernel
+// matrix is symmetric, Section 1; the oracle and the inspectors produce them
+// bitwise): every pair must have its partner in the other node's list and
+// the transposed values.
+hm_status check_symmetric(const HostRepr &r, bool near, bool far) {
+    auto find = [](const std::vector<int64_t> &ptr, const std::vector<int32_t> &col, int a, int b) -> int64_t {
+        auto first = col.begin() + ptr[(size_t)a], last = col.begin() + ptr[(size_t)a + 1];
+        auto it = std::lower_bound(first, last, b);
+        return (it != last && *it == b) ? (int64_t)(it - col.begin()) : -1;
+    };
+    for (int a = 0; a < r.n_nodes; a++) {
+        if (far)
+            for (int64_t e = r.far_ptr[(size_t)a]; e < r.far_ptr[(size_t)a + 1]; e++) {
+                const int b = r.far_col[(size_t)e];
+                if (b <= a) continue;
+                const int64_t f = find(r.far_ptr, r.far_col, b, a);
+                if (f < 0) return fail(HM_ERR_FORMAT, "HM_LOAD_SYMMETRIC: far lists are not symmetric");
+                const int64_t ka = r.rank[(size_t)a], kb = r.rank[(size_t)b];
+                const double *x = r.B_ptr() + r.far_off[(size_t)e], *y = r.B_ptr() + r.far_off[(size_t)f];
+                for (int64_t i = 0; i < ka; i++)
+                    for (int64_t j = 0; j < kb; j++)
+                        if (x[i * kb + j] != y[j * ka + i])
+                            return fail(HM_ERR_FORMAT, "HM_LOAD_SYMMETRIC: a far block is not the transpose of its mirror");
+            }
+        if (near)
+            for (int64_t e = r.near_ptr[(size_t)a]; e < r.near_ptr[(size_t)a + 1]; e++) {
+                const int b = r.near_col[(size_t)e];
+                if (b < a) continue;
+                const int64_t f = find(r.near_ptr, r.near_col, b, a);
+                if (f < 0) return fail(HM_ERR_FORMAT, "HM_LOAD_SYMMETRIC: near lists are not symmetric");
+                const int64_t ma = r.size[(size_t)a], mb = r.size[(size_t)b];
+                const double *x = r.D_ptr() + r.near_off[(size_t)e], *y = r.D_ptr() + r.near_off[(size_t)f];
+                for (int64_t i = 0; i < ma; i++)
+                    for (int64_t j = 0; j < mb; j++)
+                        if (x[i * mb + j] != y[j * ma + i])
+                            return fail(HM_ERR_FORMAT, "HM_LOAD_SYMMETRIC: a near block is not the transpose of its mirror");
+            }
+    }
+    return HM_OK;
+}
 
 int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
@@ -188,6 +230,16 @@ hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_mat
 
     if (gen && (r.skel_ptr.size() != (size_t)n + 1))
         return fail(HM_ERR_INVALID, "generated blocks need the skeletons in the representation");
+    const bool sym = (prec_mask & HM_LOAD_SYMMETRIC) != 0;
+    if (sym && !gen) {
+        hm_status st = check_symmetric(r, !no_near, !no_far);
+        if (st != HM_OK) return st;
+    }
+    // symmetric store: the block of an unordered pair {a, b} is stored once,
+    // for the row node a <= b (visited first); the other job reads it as a
+    // mirror (Seg::trans), its rows tstride apart
+    std::map<std::pair<int, int>, std::pair<int64_t, int32_t>> stored;  // pair -> (offset, lda)
+    int32_t max_tstride = 0;
     Planner P;
     std::vector<GenJob> gjobs;  // far and near blocks generated from the points (gen)
     std::vector<std::vector<int>> by_level((size_t)r.depth + 1);
@@ -242,14 +294,24 @@ hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_mat
                 if (kb == 0) continue;
                 // left out of the store as the near blocks are (below)
                 int64_t off = 0;
-                if (!no_far) {
+                int32_t tstride = 0;
+                if (!no_far && sym && bn < a) {
+                    auto it = stored.find({bn, a});
+                    if (it == stored.end()) return fail(HM_ERR_INTERNAL, "symmetric store: far block not placed");
+                    off = it->second.first;
+                    tstride = it->second.second;
+                    max_tstride = std::max(max_tstride, tstride);
+                } else if (!no_far) {
                     off = P.alloc(kb, kap);
                     P.jobs[1].push_back({r.far_off[e], off, ka, kb, 0, 0, kb, kap});
                     if (gen)  // rows: a's skeleton, columns: bn's skeleton
                         gjobs.push_back({off, r.N + r.skel_ptr[a], r.N + r.skel_ptr[bn], ka, kb, kap, 0});
+                    if (sym) stored[{a, bn}] = {off, kap};
                 }
                 b.segs.push_back(seg(off, wrow[bn], kap, kb, BUF_WHAT, h16row[bn]));
                 b.segs.back().from_pts = 2;
+                b.segs.back().trans = tstride > 0;
+                b.segs.back().tstride = tstride;
                 E_B += (int64_t)ka * kb;
             }
             const int32_t p = r.parent[a];
@@ -278,14 +340,24 @@ hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_mat
                 // left out of the store: the segment's A offset is never read
                 // (its evaluations compute the block from the points)
                 int64_t off = 0;
-                if (!no_near) {
+                int32_t tstride = 0;
+                if (!no_near && sym && bn < a) {
+                    auto it = stored.find({bn, a});
+                    if (it == stored.end()) return fail(HM_ERR_INTERNAL, "symmetric store: near block not placed");
+                    off = it->second.first;
+                    tstride = it->second.second;
+                    max_tstride = std::max(max_tstride, tstride);
+                } else if (!no_near) {
                     off = P.alloc(mb, map);
                     P.jobs[2].push_back({r.near_off[e], off, ma, mb, 0, 0, mb, map});
                     if (gen)  // rows: a's points, columns: bn's points (tree order)
                         gjobs.push_back({off, r.start[a], r.start[bn], ma, mb, map, 0});
+                    if (sym) stored[{a, bn}] = {off, map};
                 }
                 b.segs.push_back(seg(off, r.start[bn], map, mb, BUF_WT, w16row[bn]));
                 b.segs.back().from_pts = 1;
+                b.segs.back().trans = tstride > 0;
+                b.segs.back().tstride = tstride;
                 E_D += (int64_t)ma * mb;
             }
             const int32_t k = r.rank[a];
@@ -469,6 +541,7 @@ hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_mat
         }
     } guard{h};
     h->device = device;
+    h->symmetric = sym;
     h->near_stored = !no_near;
     h->far_stored = !no_far;
     if (!r.skel_ptr.empty()) {  // original point of each Ŵ row (node a's rows follow its skeleton)
@@ -492,7 +565,8 @@ hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_mat
     h->E_D = E_D;
     h->skel_rows = wrow[n];
     // slack after the last block: a tile taller than its block reads past it
-    h->store_elems = P.store_off + 512;
+    // (a mirror block's rows are tstride apart: up to 128 rows of them)
+    h->store_elems = P.store_off + 512 + (int64_t)128 * max_tstride;
     h->phases = P.phases;
     h->task_k = job_task_k(jobs);
     h->gjobs = std::move(jobs);

@@ -41,6 +41,10 @@ struct Seg {
                       //   2: far block B_ab of the job's node a and node b whose Ŵ rows start
                       //      at b_row (x: a's skeleton points, y: b's, both in Ŵ row order)
                       //   0: stored only
+    int32_t trans;    // 1: a mirror block of a symmetric store: element (row i, contraction t) at
+                      //   a_off + i * tstride + t (the stored block of the partner pair, read
+                      //   transposed); 0: K-major as above
+    int32_t tstride;  // trans: distance between consecutive rows of this A block (elements)
     int32_t pad_;
 };
 
@@ -207,6 +211,7 @@ struct GraphPlan {
     int32_t *d_succ = nullptr;
     int32_t *d_counters = nullptr;
     double est_ms = 0;   // list-scheduling estimate (diagnostic)
+    bool sym = false;    // some matrix of the plan has a symmetric store (mirror blocks)
 };
 
 // Output of inspector-p1 (Section 5 "Reusing Inspection"): everything the
@@ -268,6 +273,7 @@ struct hm_matrix_s {
     void *ws[2][hm::BUF_COUNT] = {{nullptr}};
     size_t ws_bytes[2][hm::BUF_COUNT] = {{0}};
     hm::ProfileAcc prof;
+    bool symmetric = false;                // loaded with HM_LOAD_SYMMETRIC (mirror blocks in the store)
     bool near_stored = true;               // false: loaded with HM_LOAD_NO_NEAR_BLOCKS
     bool far_stored = true;                // false: loaded with HM_LOAD_NO_FAR_BLOCKS
     std::vector<int64_t> skel_row_pt;      // original point index of each Ŵ row (empty: no skeletons)
@@ -403,7 +409,7 @@ hipError_t launch_persistent(const GraphPlan &plan, int elem_bytes, const MatDes
                              int32_t *d_head, int grid, hipStream_t s, const OutScatter &out = OutScatter{},
                              int32_t *counters = nullptr);
 // Resident workgroups per CU of the persistent kernel for (elem_bytes, bn).
-int persistent_occupancy(int elem_bytes, int bn, bool split = false);
+int persistent_occupancy(int elem_bytes, int bn, bool split = false, bool sym = false);
 
 // Expand the job graph for Q columns with column tile bn, order it by list
 // scheduling on `workers` simulated workgroups, and upload it (hm_sched.hip).

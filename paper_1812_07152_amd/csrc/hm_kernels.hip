@@ -84,6 +84,8 @@ __device__ __forceinline__ Seg load_seg(const Seg *p) {
     s.Kpad = g->Kpad;
     s.a_off16 = g->a_off16;
     s.b_row16 = g->b_row16;
+    s.trans = g->trans;
+    s.tstride = g->tstride;
     return s;
 }
 
@@ -96,6 +98,15 @@ __device__ __forceinline__ Seg load_seg(const Seg *p) {
 __device__ __forceinline__ void load_lds16(const void *src, const char *lds_dst) {
     const uint32_t a = (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) char *)lds_dst;
     asm volatile("global_load_lds_dwordx4 %0, off" ::"v"(src), "{m0}"(__builtin_amdgcn_readfirstlane(a))
+                 : "memory");
+}
+
+// The same with 4 bytes a lane: the 64 lanes' words land in 256 bytes of LDS,
+// lane l at lds_addr + 4 l.  Used for the A chunks of mirror blocks (see
+// product_loop_f64_dma), whose values are gathered along a stride.
+__device__ __forceinline__ void load_lds4(const void *src, const char *lds_dst) {
+    const uint32_t a = (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) char *)lds_dst;
+    asm volatile("global_load_lds_dword %0, off" ::"v"(src), "{m0}"(__builtin_amdgcn_readfirstlane(a))
                  : "memory");
 }
 
@@ -115,6 +126,8 @@ __device__ __forceinline__ Seg load_seg_scalar(const Seg *p) {
     s.a_off16 = g->a_off16;
     s.b_row16 = g->b_row16;
     s.from_pts = g->from_pts;
+    s.trans = g->trans;
+    s.tstride = g->tstride;
     s.pad_ = 0;
     return s;
 }
@@ -194,7 +207,10 @@ __device__ __forceinline__ int frag_row(int lane, int r) {
 // ROWPERM (FP64 only): fragment row x reads A row 4(x % 4) + x / 4, which
 // puts the FP64 accumulators in the FP32 register layout (frag_row<true>),
 // so that a product can continue from FP32 partial sums.
-template <typename T, int BM, int BN, int WAVES_M, int WAVES_N, int NT, bool ROWPERM = false>
+// SYM: the loop may meet mirror blocks of a symmetric store (Seg::trans); a
+// separate instantiation, so that the loops of full stores keep their
+// registers and code.
+template <typename T, int BM, int BN, int WAVES_M, int WAVES_N, int NT, bool ROWPERM = false, bool SYM = false>
 __device__ __forceinline__ void product_loop(
     const Seg *__restrict__ segs, int sb, int se, int m0, const T *__restrict__ store, T *buf0, T *buf1,
     T *buf2, T *buf3, int64_t ldq, int64_t n0, T *As_, T *Bs_,
@@ -228,13 +244,26 @@ __device__ __forceinline__ void product_loop(
     // Unconditional loads: thread slots beyond the chunk re-load its last
     // vector, B rows beyond K re-load row K-1 (multiplied by zero rows of A).
     auto load = [&](const Seg &sg, int kk) {
-        const T *A = store + sg.a_off + m0 + (int64_t)kk * sg.lda;
         const T *Bp = bufp(sg.b_buf) + (sg.b_row) * ldq + n0;
+        if (SYM && sg.trans) {  // mirror block: the VEC rows of a vector sit tstride apart
+            const T *A = store + sg.a_off + (int64_t)m0 * sg.tstride + kk;
+            int mt = tid;  // opaque: these offsets are not hoisted out of the task loop
+            asm volatile("" : "+v"(mt));
 #pragma unroll
-        for (int u = 0; u < A_PER; u++) {
-            const int idx = min(tid + u * NT, A_VECS - 1);
-            const int kr = idx / A_ROWV, c = (idx % A_ROWV) * VEC;
-            ra[u] = load_global<vec_t>(A + (int64_t)kr * sg.lda + c);
+            for (int u = 0; u < A_PER; u++) {
+                const int idx = min(mt + u * NT, A_VECS - 1);
+                const int kr = idx / A_ROWV, c = (idx % A_ROWV) * VEC;
+#pragma unroll
+                for (int v = 0; v < VEC; v++) ra[u][v] = load_global<T>(A + (int64_t)(c + v) * sg.tstride + kr);
+            }
+        } else {
+            const T *A = store + sg.a_off + m0 + (int64_t)kk * sg.lda;
+#pragma unroll
+            for (int u = 0; u < A_PER; u++) {
+                const int idx = min(tid + u * NT, A_VECS - 1);
+                const int kr = idx / A_ROWV, c = (idx % A_ROWV) * VEC;
+                ra[u] = load_global<vec_t>(A + (int64_t)kr * sg.lda + c);
+            }
         }
 #pragma unroll
         for (int u = 0; u < B_PER; u++) {
@@ -340,7 +369,7 @@ struct NearGen {
 };
 constexpr int kPointLds = 128 * kMaxPointDim * 8;  // the tile's points, BM <= 128
 
-template <int BM, int BN, int WAVES_M, int WAVES_N, int NT, bool ROWPERM>
+template <int BM, int BN, int WAVES_M, int WAVES_N, int NT, bool ROWPERM, bool SYM = false>
 __device__ __forceinline__ void product_loop_f64_dma(
     const Seg *__restrict__ segs, int sb, int se, int m0, const double *__restrict__ store, double *buf0,
     double *buf1, double *buf2, double *buf3, int64_t ldq, int64_t n0, char *lds,
@@ -374,11 +403,21 @@ __device__ __forceinline__ void product_loop_f64_dma(
     // 64 q + lane of block q is (row kr, value pair p) of A or of B; B rows
     // past K re-load row K - 1 (multiplied by zero rows of A).
     const bool gen = ng.pts != nullptr;
-    auto issue = [&](int st, const Seg &sg, int kk) {
+    // A mirror block (sg.trans) holds a row's contraction values
+    // contiguously, tstride apart from the next row's, so the 16-byte slots of
+    // the K-major stage layout (two rows' values at one contraction row) are
+    // gathered: four 4-byte direct loads per 1 KB block, lane l of load w
+    // fetching word l % 4 of slot 16 w + l / 4, i.e. one half of the value of
+    // row 2 pr + (l % 4) / 2.  The stage layout, and so the MFMA operand reads,
+    // are the ones of a stored K-major block.  Such a chunk issues
+    // MIRROR_EXTRA more loads a wave (see the waits below).
+    auto issue = [&](int st, const Seg &sg, int kk) -> bool {
         const double *A = store + sg.a_off + m0 + (int64_t)kk * sg.lda;
+        const char *AT = reinterpret_cast<const char *>(store + sg.a_off + (int64_t)m0 * sg.tstride + kk);
         const double *Bp = bufp(sg.b_buf) + sg.b_row * ldq + n0;
         char *stage = lds + st * kStage;
         const bool make_a = gen && sg.from_pts == ng.kind;  // wave-uniform
+        const bool mirror = SYM && sg.trans && !make_a;     // wave-uniform
 #pragma unroll
         for (int u = 0; u < PER_WAVE; u++) {
             int q = min(u * 8 + wave, BLOCKS - 1);  // wave-uniform
@@ -386,6 +425,19 @@ __device__ __forceinline__ void product_loop_f64_dma(
             // bytes its own load writes, to the same place), so that every
             // wave still issues PER_WAVE loads per chunk
             if (make_a && q < A_BLOCKS) q = A_BLOCKS + q % (BLOCKS - A_BLOCKS);
+            if (mirror && q < A_BLOCKS) {
+                // the lane index made opaque here: addresses computed per use,
+                // not once per kernel and held through the task loop
+                int ml = lane;
+                asm volatile("" : "+v"(ml));
+#pragma unroll
+                for (int w = 0; w < 4; w++) {
+                    const int t = q * 64 + w * 16 + (ml >> 2), kr = t / (BM / 2);
+                    const int pr = (t % (BM / 2)) ^ ((kr & 1) ? SWA : 0), row = 2 * pr + ((ml >> 1) & 1);
+                    load_lds4(AT + ((int64_t)row * sg.tstride + kr) * 8 + (ml & 1) * 4, stage + q * 1024 + w * 256);
+                }
+                continue;
+            }
             const double *src;
             if (q < A_BLOCKS) {
                 const int t = q * 64 + lane, kr = t / (BM / 2), pr = (t % (BM / 2)) ^ ((kr & 1) ? SWA : 0);
@@ -396,7 +448,20 @@ __device__ __forceinline__ void product_loop_f64_dma(
             }
             load_lds16(src, stage + q * 1024);
         }
+        return mirror;
     };
+    // Loads a wave issues beyond PER_WAVE for a mirror chunk: 3 more for each
+    // of its A blocks; the smallest count over the waves (a wave with more
+    // then waits a little longer than it must, never less).
+    constexpr int MIRROR_EXTRA = [] {
+        int lo = 1 << 20;
+        for (int w = 0; w < 8; w++) {
+            int na = 0;
+            for (int u = 0; u < PER_WAVE; u++) na += ((u * 8 + w < BLOCKS - 1 ? u * 8 + w : BLOCKS - 1) < A_BLOCKS);
+            lo = na < lo ? na : lo;
+        }
+        return 3 * lo;
+    }();
     // The A block of a chunk of a segment made from points: A[k][m] =
     // K(x_a[m], x_b[kk + k]), zero past the segment's K rows and the tile's
     // rows.  Wave w takes rows w and w + 8 (x_b through scalar loads), lanes
@@ -556,15 +621,22 @@ __device__ __forceinline__ void product_loop_f64_dma(
         // register allocator copy every accumulator)
         if constexpr (STAGES == 3) {
             bool next_valid = cur.s < se;
-            issue(1, cur.sg, cur.kk);
+            // whether the chunk issued last (c + 1 at the wait) was loaded as
+            // a mirror block: it then has MIRROR_EXTRA more loads in flight
+            bool newest_mirror = SYM && issue(1, cur.sg, cur.kk);
+            if (!SYM) issue(1, cur.sg, cur.kk);
             if (gen && cur.sg.from_pts == ng.kind) make_all(1, cur.sg, cur.kk);
             cur = advance(cur);  // chunk c + 2
             bool more = true;
             do {
-                wait_vm_barrier<PER_WAVE>();  // chunk c landed; stage of c + 2 free
+                // chunk c landed; stage of c + 2 free
+                if (SYM && newest_mirror)
+                    wait_vm_barrier<PER_WAVE + MIRROR_EXTRA>();
+                else
+                    wait_vm_barrier<PER_WAVE>();
                 const bool after_valid = cur.s < se;
                 const int gst = st == 0 ? 2 : st - 1;
-                issue(gst, cur.sg, cur.kk);
+                newest_mirror = issue(gst, cur.sg, cur.kk);
                 compute_and_make(st, gen && cur.sg.from_pts == ng.kind, gst, cur.sg, cur.kk);
                 more = next_valid;
                 next_valid = after_valid;
@@ -706,7 +778,8 @@ __device__ __forceinline__ void store_tile(const TileJob &task, OUT *buf0, OUT *
 // can be written from consecutive rows.
 // DMA (FP64, persistent launch): the direct global-to-LDS loop, with As_ the
 // start of an LDS region of f64_lds_bytes<BM, BN, ROWPERM>() bytes.
-template <typename T, int BM, int BN, int WAVES_M, int WAVES_N, int NT, bool ROWPERM = false, bool DMA = false>
+template <typename T, int BM, int BN, int WAVES_M, int WAVES_N, int NT, bool ROWPERM = false, bool DMA = false,
+          bool SYM = false>
 __device__ __forceinline__ void block_product(const TileJob &task, const Seg *__restrict__ segs,
                                               const T *__restrict__ store, T *buf0, T *buf1,
                                               T *buf2, T *buf3, int64_t ldq, int64_t n0, T *As_,
@@ -720,13 +793,15 @@ __device__ __forceinline__ void block_product(const TileJob &task, const Seg *__
     if constexpr (DMA && sizeof(T) == 8) {
         ng.a_row = task.out_row;        // the tile's first row (task.m0 is its offset in the block)
         ng.m_valid = min(BM, task.M);   // the tile's rows
-        product_loop_f64_dma<BM, BN, WAVES_M, WAVES_N, NT, ROWPERM>(segs, task.seg_begin, task.seg_end, task.m0,
-                                                                   store, buf0, buf1, buf2, buf3, ldq, n0,
-                                                                   reinterpret_cast<char *>(As_), acc, ng);
+        product_loop_f64_dma<BM, BN, WAVES_M, WAVES_N, NT, ROWPERM, SYM>(segs, task.seg_begin, task.seg_end,
+                                                                        task.m0, store, buf0, buf1, buf2, buf3,
+                                                                        ldq, n0, reinterpret_cast<char *>(As_),
+                                                                        acc, ng);
     }
     else
-        product_loop<T, BM, BN, WAVES_M, WAVES_N, NT, ROWPERM>(segs, task.seg_begin, task.seg_end, task.m0, store,
-                                                               buf0, buf1, buf2, buf3, ldq, n0, As_, Bs_, acc);
+        product_loop<T, BM, BN, WAVES_M, WAVES_N, NT, ROWPERM, SYM>(segs, task.seg_begin, task.seg_end, task.m0,
+                                                                    store, buf0, buf1, buf2, buf3, ldq, n0, As_,
+                                                                    Bs_, acc);
     store_tile<T, typename Mfma<T>::acc_t, BM, BN, WAVES_M, WAVES_N, ROWPERM || sizeof(T) == 4>(
         task, buf0, buf1, buf2, buf3, ldq, n0, As_, acc);
 }
@@ -999,7 +1074,9 @@ __global__ void k_make_bf16x3(const double *__restrict__ store, const Seg *__res
     for (int64_t e = threadIdx.x; e < nchunks * per_chunk; e += blockDim.x) {
         const int c = (int)(e / per_chunk), rem = (int)(e % per_chunk), i = rem / kKC, k = rem % kKC;
         const int kk = c * kKC + k;
-        const float v = kk < sg.K ? (float)store[sg.a_off + (int64_t)kk * sg.lda + i] : 0.0f;
+        const float v = kk < sg.K ? (float)store[sg.trans ? sg.a_off + (int64_t)i * sg.tstride + kk
+                                                          : sg.a_off + (int64_t)kk * sg.lda + i]
+                                  : 0.0f;
         __bf16 hi, lo;
         split_bf16(v, hi, lo);
         __bf16 *dst = store16 + sg.a_off16 + (int64_t)c * 2 * per_chunk;
@@ -1009,7 +1086,7 @@ __global__ void k_make_bf16x3(const double *__restrict__ store, const Seg *__res
 }
 
 // One launch = one phase: workgroup (x, y) computes task x, column tile y.
-template <typename T, int BM, int BN, int WAVES_M, int WAVES_N>
+template <typename T, int BM, int BN, int WAVES_M, int WAVES_N, bool SYM>
 __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void k_block_products(
     const Task *__restrict__ tasks, const Seg *__restrict__ segs, int task_begin,
     const T *__restrict__ store, T *buf0, T *buf1, T *buf2, T *buf3, int64_t ldq) {
@@ -1018,8 +1095,8 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void k_block_products(
     __shared__ __attribute__((aligned(16))) T Bs[2 * kBK * (BN + lds_pad<T>())];
     const Task t = tasks[task_begin + blockIdx.x];
     const TileJob job{t.out_row, t.out_buf, t.M, t.m0, t.seg_begin, t.seg_end, 0};  // workspace output
-    block_product<T, BM, BN, WAVES_M, WAVES_N, NT>(job, segs, store, buf0, buf1, buf2, buf3, ldq,
-                                                   (int64_t)blockIdx.y * BN, As, Bs);
+    block_product<T, BM, BN, WAVES_M, WAVES_N, NT, false, false, SYM>(job, segs, store, buf0, buf1, buf2, buf3,
+                                                                      ldq, (int64_t)blockIdx.y * BN, As, Bs);
 }
 
 // Wave layouts of the persistent kernel (8 waves) per tile: {WAVES_M, WAVES_N}.
@@ -1050,7 +1127,7 @@ constexpr int kWaitLimit = 1 << 20;  // polls (each followed by a sleep) before 
 // GEN: the FP64 launch that computes the near blocks from the points (see
 // NearGen); a separate instantiation, so that the stored-block launch keeps
 // its registers and code.
-template <typename T, int BN, bool SPLIT, bool GEN = false>
+template <typename T, int BN, bool SPLIT, bool GEN = false, bool SYM = false>
 __global__ __launch_bounds__(kPersistThreads, BN <= 128 ? 4 : 1) void k_persistent(
     const PTask *__restrict__ tasks, int n_tasks, const int32_t *__restrict__ succ,
     int32_t *counters, int32_t *head, int32_t *err, const MatDesc *__restrict__ mats, void *Y, int64_t ldy,
@@ -1146,23 +1223,23 @@ __global__ __launch_bounds__(kPersistThreads, BN <= 128 ? 4 : 1) void k_persiste
             }
         } else if (pt.bm == 128) {
             block_product<T, 128, BN, PLayout<128, BN>::WMv, PLayout<128, BN>::WN, kPersistThreads,
-                          SPLIT && sizeof(T) == 8, sizeof(T) == 8>(job, segs, store, (T *)md.buf[0], (T *)md.buf[1],
+                          SPLIT && sizeof(T) == 8, sizeof(T) == 8, SYM || GEN>(job, segs, store, (T *)md.buf[0], (T *)md.buf[1],
                                                    (T *)md.buf[2], (T *)md.buf[3], md.ldq, n0, As, Bs, ng);
         } else if (!fine_tiles(sizeof(T), BN, SPLIT) || pt.bm == 64) {
             block_product<T, 64, BN, PLayout<64, BN>::WMv, PLayout<64, BN>::WN, kPersistThreads,
-                          SPLIT && sizeof(T) == 8, sizeof(T) == 8>(job, segs, store, (T *)md.buf[0], (T *)md.buf[1],
+                          SPLIT && sizeof(T) == 8, sizeof(T) == 8, SYM || GEN>(job, segs, store, (T *)md.buf[0], (T *)md.buf[1],
                                                    (T *)md.buf[2], (T *)md.buf[3], md.ldq, n0, As, Bs, ng);
         } else if constexpr (fine_tiles(sizeof(T), BN, SPLIT)) {
             // 32- and 96-row tiles, for output blocks whose row count would
             // waste most of a 64- or 128-row tile
             if (pt.bm == 96)
                 block_product<T, 96, BN, PLayout<96, BN>::WMv, PLayout<96, BN>::WN, kPersistThreads, false,
-                              sizeof(T) == 8>(
+                              sizeof(T) == 8, SYM || GEN>(
                     job, segs, store, (T *)md.buf[0], (T *)md.buf[1], (T *)md.buf[2], (T *)md.buf[3],
                     md.ldq, n0, As, Bs, ng);
             else
                 block_product<T, 32, BN, PLayout<32, BN>::WMv, PLayout<32, BN>::WN, kPersistThreads, false,
-                              sizeof(T) == 8>(
+                              sizeof(T) == 8, SYM || GEN>(
                     job, segs, store, (T *)md.buf[0], (T *)md.buf[1], (T *)md.buf[2], (T *)md.buf[3],
                     md.ldq, n0, As, Bs, ng);
         }
@@ -1353,9 +1430,14 @@ template <typename T, int BM, int BN, int WM_, int WN_>
 hipError_t run(const Phase &ph, const hm_matrix_s *h, const T *store, void *const bufs[4],
                int64_t ldq, hipStream_t s) {
     dim3 grid((unsigned)ph.task_count, (unsigned)(ldq / BN));
-    hipLaunchKernelGGL((k_block_products<T, BM, BN, WM_, WN_>), grid, dim3(64 * WM_ * WN_), 0, s,
-                       h->d_tasks, h->d_segs, ph.task_begin, store, (T *)bufs[0], (T *)bufs[1],
-                       (T *)bufs[2], (T *)bufs[3], ldq);
+    if (h->symmetric)
+        hipLaunchKernelGGL((k_block_products<T, BM, BN, WM_, WN_, true>), grid, dim3(64 * WM_ * WN_), 0, s,
+                           h->d_tasks, h->d_segs, ph.task_begin, store, (T *)bufs[0], (T *)bufs[1],
+                           (T *)bufs[2], (T *)bufs[3], ldq);
+    else
+        hipLaunchKernelGGL((k_block_products<T, BM, BN, WM_, WN_, false>), grid, dim3(64 * WM_ * WN_), 0, s,
+                           h->d_tasks, h->d_segs, ph.task_begin, store, (T *)bufs[0], (T *)bufs[1],
+                           (T *)bufs[2], (T *)bufs[3], ldq);
     return hipGetLastError();
 }
 
@@ -1433,6 +1515,10 @@ hipError_t run_persistent(const GraphPlan &plan, const MatDesc *mats, int32_t *h
         hipLaunchKernelGGL((k_persistent<T, BN, true>), dim3((unsigned)grid), dim3(kPersistThreads), 0,
                            s, plan.d_tasks, nt, plan.d_succ, counters, head, head + 1, mats, out.Y,
                            out.ldy, out.Q, out.perm);
+    else if (plan.sym)
+        hipLaunchKernelGGL((k_persistent<T, BN, false, false, true>), dim3((unsigned)grid), dim3(kPersistThreads),
+                           0, s, plan.d_tasks, nt, plan.d_succ, counters, head, head + 1, mats, out.Y,
+                           out.ldy, out.Q, out.perm);
     else
         hipLaunchKernelGGL((k_persistent<T, BN, false>), dim3((unsigned)grid), dim3(kPersistThreads), 0,
                            s, plan.d_tasks, nt, plan.d_succ, counters, head, head + 1, mats, out.Y,
@@ -1452,16 +1538,16 @@ hipError_t persistent_bn(const GraphPlan &plan, const MatDesc *mats, int32_t *he
     }
 }
 
-template <typename T, bool SPLIT>
+template <typename T, bool SPLIT, bool SYM = false>
 int occupancy_bn(int bn) {
     int n = 0;
     hipError_t e = hipSuccess;
     switch (bn) {
-        case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_persistent<T, 16, SPLIT>, kPersistThreads, 0); break;
-        case 32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_persistent<T, 32, SPLIT>, kPersistThreads, 0); break;
-        case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_persistent<T, 64, SPLIT>, kPersistThreads, 0); break;
-        case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_persistent<T, 128, SPLIT>, kPersistThreads, 0); break;
-        default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_persistent<T, 256, SPLIT>, kPersistThreads, 0); break;
+        case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_persistent<T, 16, SPLIT, false, SYM>, kPersistThreads, 0); break;
+        case 32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_persistent<T, 32, SPLIT, false, SYM>, kPersistThreads, 0); break;
+        case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_persistent<T, 64, SPLIT, false, SYM>, kPersistThreads, 0); break;
+        case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_persistent<T, 128, SPLIT, false, SYM>, kPersistThreads, 0); break;
+        default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_persistent<T, 256, SPLIT, false, SYM>, kPersistThreads, 0); break;
     }
     return e == hipSuccess ? std::max(n, 1) : 1;
 }
@@ -1477,9 +1563,11 @@ hipError_t launch_persistent(const GraphPlan &plan, int elem_bytes, const MatDes
                            : persistent_bn<float>(plan, d_mat, d_head, grid, out, c, s);
 }
 
-int persistent_occupancy(int elem_bytes, int bn, bool split) {
-    if (elem_bytes == 8) return split ? occupancy_bn<double, true>(bn) : occupancy_bn<double, false>(bn);
-    return occupancy_bn<float, false>(bn);
+int persistent_occupancy(int elem_bytes, int bn, bool split, bool sym) {
+    if (elem_bytes == 8)
+        return split ? occupancy_bn<double, true>(bn) : sym ? occupancy_bn<double, false, true>(bn)
+                                                            : occupancy_bn<double, false>(bn);
+    return sym ? occupancy_bn<float, false, true>(bn) : occupancy_bn<float, false>(bn);
 }
 
 hipError_t launch_permute_in(const void *W, int64_t ldw, void *Wt, int64_t Qp, const int64_t *perm,

@@ -251,6 +251,8 @@ hm_status build_plan(const std::vector<PlanPart> &parts, int bn, int elem_bytes,
                     std::string("uploading the task graph: ") + hipGetErrorString(err));
     }
     plan.bn = bn;
+    plan.sym = false;
+    for (const PlanPart &pp : parts) plan.sym = plan.sym || pp.h->symmetric;
     plan.n_tasks = total;
     plan.est_ms = makespan;
     return HM_OK;

@@ -188,7 +188,7 @@ bool try_launch(hm_server S, int m, int si) {
         e = launch_gather_in(sl.d_reqs, sl.d_col2req, cols, width, sl.ws[BUF_WT], kServeMaxCols, R.h->d_perm,
                              R.h->N, S->es, st);
     if (e == hipSuccess) {
-        const int workers = std::max(1, persistent_occupancy(S->es, shape.first) * R.h->n_cu);
+        const int workers = std::max(1, persistent_occupancy(S->es, shape.first, false, R.h->symmetric) * R.h->n_cu);
         e = launch_persistent(plan, S->es, sl.mats + m, sl.head, std::min(plan.n_tasks, workers), st,
                               OutScatter{}, sl.counters);
     }
@@ -419,7 +419,7 @@ hm_status hm_server_add(hm_server S, hm_matrix h, int *mat_id) {
         if (R.plans.count(shape)) continue;
         GraphPlan p;
         std::vector<PlanPart> parts{{h, 0, shape.second, 0}};
-        st = build_plan(parts, shape.first, S->es, persistent_occupancy(S->es, shape.first) * h->n_cu, p);
+        st = build_plan(parts, shape.first, S->es, persistent_occupancy(S->es, shape.first, false, h->symmetric) * h->n_cu, p);
         if (st == HM_OK) {
             n_counters = std::max<int64_t>(n_counters, p.n_tasks);
             R.plans[shape] = p;
