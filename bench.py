@@ -272,7 +272,8 @@ def bench_serving(args) -> dict:
         R = hmx.hm_compress(wl.gen_points(w), kernel=w.kernel, h=w.h, leaf_size=w.m, tol=w.tol,
                             max_rank=w.rmax, admissibility=w.adm, tau=w.tau,
                             sample_rows=w.sample_rows, seed=w.sample_seed)
-        mats.append(hmx.hm_load_compressed_mem(R, 0, hmx.precbit(hmx.HM_PREC_FP32)))
+        mats.append(hmx.hm_load_compressed_mem(R, 0, hmx.precbit(hmx.HM_PREC_FP32)
+                                               | (hmx.HM_LOAD_SYMMETRIC if args.serving_symmetric else 0)))
         del R
         print(f"[serving] built {w.name} ({time.perf_counter() - t:.0f} s)", file=sys.stderr, flush=True)
     t_build = time.perf_counter() - t
@@ -298,7 +299,7 @@ def bench_serving(args) -> dict:
     torch.cuda.synchronize()
     plain_s = time.perf_counter() - t0
 
-    S = hmx.hm_server_create(0, hbm_budget=24 << 30, max_slots=4, dtype=hmx.HM_F32)
+    S = hmx.hm_server_create(0, hbm_budget=24 << 30, max_slots=args.serving_slots, dtype=hmx.HM_F32)
     ids = [hmx.hm_server_add(S, mt) for mt in mats]
 
     def run(reqs, gaps):
@@ -365,7 +366,9 @@ def bench_serving(args) -> dict:
         "value": flops(burst) / (len(burst) / sat_rps) / 1e9, "unit": "GFLOP/s", "n_gpus": 1,
         "higher_is_better": True, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "c5_8_resident_n16384_524288", "matrices": [w.name for w in specs],
-                   "Q": "U{1..256}", "burst_requests": len(burst), "slots": 4, "hbm_budget_gib": 24},
+                   "Q": "U{1..256}", "burst_requests": len(burst), "slots": args.serving_slots, "hbm_budget_gib": 24,
+                   "symmetric_store": bool(args.serving_symmetric),
+                   "store_gb_fp32": sum(i["bytes_fp32"] for i in infos) / 1e9},
         "saturation_rps": sat_rps,
         "plain_per_request": {"rps": len(burst) / plain_s, "gflops": flops(burst) / plain_s / 1e9},
         "speedup_vs_plain": (len(burst) / plain_s) and sat_rps / (len(burst) / plain_s),
@@ -721,6 +724,8 @@ def main() -> int:
     ap.add_argument("--burst", type=int, default=128, help="serving: requests in the saturation burst")
     ap.add_argument("--serving-seconds", type=float, default=3.0, help="serving: seconds per load level")
     ap.add_argument("--serving-seed", type=int, default=4)
+    ap.add_argument("--serving-slots", type=int, default=4, help="serving: concurrent sweeps (slots)")
+    ap.add_argument("--serving-symmetric", action="store_true", help="serving: symmetric stores")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after timing, run one device copy of this many MiB (a kernel of "
                          "known traffic for calibrating HBM counters)")
