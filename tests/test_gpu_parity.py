@@ -215,16 +215,26 @@ def test_c2_full_size_sampled_columns(hmx, sched):
         assert err32 <= 2e-5
 
 
+def mixed_bar(w):
+    """Bar of a split-BF16 result against the FP64 oracle: the case's
+    compression tol (capped at 5e-5) where that is at or above the split
+    path's rounding floor of about 1e-5 (derived in the test below); a case
+    compressed tighter (tol 1e-6: mix8, hss_lap, deep_small_leaves,
+    tm_budget) is held to 5e-5, since there rounding, not compression, sets
+    the error."""
+    return min(w.tol, 5e-5) if w.tol >= 1e-5 else 5e-5
+
+
 @pytest.mark.parametrize("name", ["c1", "mix8", "hss_lap", "deep_small_leaves", "tm_budget"])
 def test_mixed_precision_bf16x3(hmx, name, sched):
     """Split-BF16 near/far/leaf-basis products with FP32 accumulation, FP64
-    transfers and final sum.  Bar: 5e-5 relative Frobenius against the FP64
-    oracle.  Derivation: each split product drops lo*lo (|lo| <= 2^-9 |v|, so
-    the dropped term is <= 2^-18 relative) and rounds operands to FP32 before
-    splitting (2^-24); FP32 accumulation over a contraction of length K adds
-    about sqrt(K) * 2^-24.  Summed over the two or three products a value
-    passes through (leaf basis, far block, leaf basis), the bound is ~1e-5
-    with margin to 5e-5."""
+    transfers and final sum.  Bar: mixed_bar (relative Frobenius against the
+    FP64 oracle).  Rounding floor: each split product drops lo*lo (|lo| <=
+    2^-9 |v|, so the dropped term is <= 2^-18 relative) and rounds operands to
+    FP32 before splitting (2^-24); FP32 accumulation over a contraction of
+    length K adds about sqrt(K) * 2^-24.  Summed over the two or three
+    products a value passes through (leaf basis, far block, leaf basis), that
+    is ~1e-5."""
     if sched == "level":
         pytest.skip("mixed precision runs on the task-graph launch only")
     w, H = built(name)
@@ -236,16 +246,16 @@ def test_mixed_precision_bf16x3(hmx, name, sched):
     hmx.hm_eval(M, Wd, Yd, prec=hmx.HM_PREC_BF16X3)
     hmx.hm_check(M)
     err = rel(Yd.cpu().numpy(), H.eval(W))
-    _say(f"[mixed] case={name} rel err={err:.3e}")
-    assert err <= 5e-5
+    _say(f"[mixed] case={name} tol={w.tol:g} rel err={err:.3e} bar={mixed_bar(w):g}")
+    assert err <= mixed_bar(w)
 
 
 def test_mixed_precision_tall_tiles(hmx, sched):
     """Split BF16 where ranks (200) and leaves (256 points) exceed one 128-row
     tile: the split copies of Ŵ and of the leaves' Ŷ are written by two row
     tiles per node (the second starting 128 rows into the node's 32-row
-    chunks).  Q = 40 and 300 run different column tiles; 5e-5 bar against the
-    FP64 oracle."""
+    chunks).  Q = 40 and 300 run different column tiles; mixed_bar against
+    the FP64 oracle."""
     if sched == "level":
         pytest.skip("mixed precision runs on the task-graph launch only")
     w, H = built("tall")
@@ -259,14 +269,14 @@ def test_mixed_precision_tall_tiles(hmx, sched):
         hmx.hm_check(M)
         err = rel(Yd.cpu().numpy(), H.eval(W))
         _say(f"[mixed] case=tall Q={Q} rel err={err:.3e}")
-        assert err <= 5e-5
+        assert err <= mixed_bar(w)
 
 
 def test_mixed_precision_shapes_and_flags(hmx, sched):
     """Split BF16 through the same entry point with Q = 1 and ragged Q (the
     last column tile partly empty), strided W/Y views (columns beyond Q must
-    stay untouched) and tree-order rows; the 5e-5 bar of the four-structure
-    test against the FP64 oracle."""
+    stay untouched) and tree-order rows; mixed_bar against the FP64
+    oracle."""
     if sched == "level":
         pytest.skip("mixed precision runs on the task-graph launch only")
     w, H = built("mix8")
@@ -279,7 +289,7 @@ def test_mixed_precision_shapes_and_flags(hmx, sched):
         hmx.hm_check(M)
         err = rel(Yd.cpu().numpy(), H.eval(W))
         _say(f"[mixed] case=mix8 Q={Q} rel err={err:.3e}")
-        assert err <= 5e-5
+        assert err <= mixed_bar(w)
     W = wl.gen_w(w)
     Yref = H.eval(W)
     big_w = torch.zeros(w.N, w.Q + 11, dtype=torch.float64, device="cuda")
@@ -288,13 +298,13 @@ def test_mixed_precision_shapes_and_flags(hmx, sched):
     hmx.hm_eval(M, big_w[:, 3:], big_y, Q=w.Q, prec=hmx.HM_PREC_BF16X3)
     hmx.hm_check(M)
     out = big_y.cpu().numpy()
-    assert rel(out[:, :w.Q], Yref) <= 5e-5
+    assert rel(out[:, :w.Q], Yref) <= mixed_bar(w)
     assert np.all(out[:, w.Q:] == 7.0), "columns beyond Q must be untouched"
     Wt = torch.from_numpy(W[H.perm]).cuda()
     Yt = torch.empty_like(Wt)
     hmx.hm_eval(M, Wt, Yt, prec=hmx.HM_PREC_BF16X3, flags=hmx.HM_TREE_ORDER)
     hmx.hm_check(M)
-    assert rel(Yt.cpu().numpy(), Yref[H.perm]) <= 5e-5
+    assert rel(Yt.cpu().numpy(), Yref[H.perm]) <= mixed_bar(w)
 
 
 @pytest.mark.timeout(900)

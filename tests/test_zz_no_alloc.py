@@ -84,7 +84,7 @@ def test_noalloc_fp32_mixed_and_tree_order(hmx):
     _say("[noalloc] split BF16 N=4096 Q=40")
     ref, got = _pair(hmx, M, W, prec=hmx.HM_PREC_BF16X3)
     assert np.array_equal(ref, got)
-    assert rel(got, H.eval(W)) <= 5e-5  # the split-BF16 bar of the parity tests
+    assert rel(got, H.eval(W)) <= BIG.tol  # compressed at 1e-5: the split path meets the tol
     _say("[noalloc] fp32 N=4096 Q=40")
     W32 = W.astype(np.float32)
     ref, got = _pair(hmx, M, W32)
