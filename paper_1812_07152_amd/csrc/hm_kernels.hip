@@ -677,7 +677,7 @@ constexpr int split_copy_lds_bytes() {
 // accumulators are dead.  Y and out16 never come together (the caller's Y
 // receives leaf outputs, the split copies are of Ŵ and Ŷ).
 // Every thread of the workgroup calls it (it holds barriers).
-template <typename OUT, typename ACC, int BM, int BN, int WAVES_M, int WAVES_N, bool F32_ROWS>
+template <typename OUT, typename ACC, int BM, int BN, int WAVES_M, int WAVES_N, bool F32_ROWS, bool BATCH_RMW = true>
 __device__ __forceinline__ void store_tile(const TileJob &task, OUT *buf0, OUT *buf1, OUT *buf2, OUT *buf3,
                                            int64_t ldq, int64_t n0, void *lds,
                                            const ACC (&acc)[Tile<BM, BN, WAVES_M, WAVES_N>::FM]
@@ -722,6 +722,10 @@ __device__ __forceinline__ void store_tile(const TileJob &task, OUT *buf0, OUT *
         OUT *base = task.out_buf == 0 ? buf0 : task.out_buf == 1 ? buf1 : task.out_buf == 2 ? buf2 : buf3;
         OUT *out = base + task.out_row * ldq + n0;
         const int64_t lim = task.Y ? task.Q - n0 : BN;  // columns of this tile to store
+        // BATCH_RMW: with task.accumulate, a row's earlier values are all
+        // loaded before any of them is stored, so that those loads are in
+        // flight together (a load after a store the compiler cannot tell
+        // apart from it waits for the store's round trip)
 #pragma unroll
         for (int i = 0; i < FM; i++)
 #pragma unroll
@@ -730,10 +734,24 @@ __device__ __forceinline__ void store_tile(const TileJob &task, OUT *buf0, OUT *
                 if (row >= task.M) continue;
                 gOUT *o = task.Y ? (gOUT *)((OUT *)task.Y + rows[row] * task.ldy + n0)
                                  : (gOUT *)(out + (int64_t)row * ldq);
+                if constexpr (BATCH_RMW) {
+                    OUT prev[FN];
 #pragma unroll
-                for (int j = 0; j < FN; j++) {
-                    const int col = wn * WN + j * 16 + (lane & 15);
-                    if (col < lim) o[col] = task.accumulate ? o[col] + (OUT)acc[i][j][r] : (OUT)acc[i][j][r];
+                    for (int j = 0; j < FN; j++) {
+                        const int col = wn * WN + j * 16 + (lane & 15);
+                        prev[j] = task.accumulate && col < lim ? o[col] : (OUT)0;
+                    }
+#pragma unroll
+                    for (int j = 0; j < FN; j++) {
+                        const int col = wn * WN + j * 16 + (lane & 15);
+                        if (col < lim) o[col] = prev[j] + (OUT)acc[i][j][r];
+                    }
+                } else {
+#pragma unroll
+                    for (int j = 0; j < FN; j++) {
+                        const int col = wn * WN + j * 16 + (lane & 15);
+                        if (col < lim) o[col] = task.accumulate ? o[col] + (OUT)acc[i][j][r] : (OUT)acc[i][j][r];
+                    }
                 }
             }
     }
@@ -802,7 +820,7 @@ __device__ __forceinline__ void block_product(const TileJob &task, const Seg *__
         product_loop<T, BM, BN, WAVES_M, WAVES_N, NT, ROWPERM, SYM>(segs, task.seg_begin, task.seg_end, task.m0,
                                                                     store, buf0, buf1, buf2, buf3, ldq, n0, As_,
                                                                     Bs_, acc);
-    store_tile<T, typename Mfma<T>::acc_t, BM, BN, WAVES_M, WAVES_N, ROWPERM || sizeof(T) == 4>(
+    store_tile<T, typename Mfma<T>::acc_t, BM, BN, WAVES_M, WAVES_N, ROWPERM || sizeof(T) == 4, NT == 512>(
         task, buf0, buf1, buf2, buf3, ldq, n0, As_, acc);
 }
 
