@@ -267,6 +267,12 @@ hm_status hm_profile_reset(hm_matrix h);
 typedef struct hm_batch_s *hm_batch;
 #define HM_BATCH_AUTOTUNE 1u   /* time the candidate column tiles and keep the fastest */
 #define HM_BATCH_NO_GRAPH 2u   /* enqueue the launches directly instead of a captured graph */
+/* Fix the column tile (16, 32, 64, 128 or 256) instead of taking the default
+ * or the autotuner's (not together with HM_BATCH_AUTOTUNE).  With 256, each
+ * matrix's last columns run in a tile no wider than they need (the smallest
+ * power of two, at least 16, that holds them); so does the default or tuned
+ * tile when it is 256. */
+#define HM_BATCH_TILE(bn) ((unsigned)(bn) << 8)
 
 typedef struct {
     int32_t n, column_tile, n_tasks, workgroups;

@@ -4,7 +4,7 @@
 The compute path is libhm.so (HIP kernels for gfx950) behind the C ABI of
 include/hm.h; this package is its Python binding.
 """
-from .hm import (HM_BATCH_AUTOTUNE, HM_BATCH_NO_GRAPH, Batch, hm_batch_check, hm_batch_create,  # noqa: F401
+from .hm import (HM_BATCH_AUTOTUNE, HM_BATCH_NO_GRAPH, HM_BATCH_TILE, Batch, hm_batch_check, hm_batch_create,  # noqa: F401
                  hm_batch_eval, hm_batch_free, hm_batch_info, hm_eval_batched)
 from .hm import (Server, hm_poll, hm_server_add, hm_server_create, hm_server_destroy,  # noqa: F401
                  hm_server_stats, hm_submit)

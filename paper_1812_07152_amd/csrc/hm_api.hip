@@ -145,7 +145,11 @@ hm_status eval_setup(const char *who, hm_matrix h, const void *W, int64_t ldw, v
     if (!o.level_sched) bk[1] = bk[2] = bk[3] = graph_bn(Q, o.es, o.mixed, h->task_k);  // one tile for the graph
     if (o.from_points && bk[3] == 64) bk[1] = bk[2] = bk[3] = 128;  // see k_persistent
     const int bn_max = std::max({bk[1], bk[2], bk[3]});
-    o.Qp = (Q + bn_max - 1) / bn_max * bn_max;  // workspace leading dimension
+    // a 256-column stored-block task graph in the launch's type (not the
+    // split-BF16, points or symmetric-store launches, nor per-level launches)
+    // ends a matrix's columns with a tile no wider than they need
+    o.narrow = !o.level_sched && !o.mixed && !o.from_points && !h->symmetric && bk[3] == 256;
+    o.Qp = padded_columns(Q, bn_max, o.narrow);
     o.perm = (flags & HM_TREE_ORDER) ? nullptr : h->d_perm;
     o.valid = true;
     return HM_OK;
@@ -285,7 +289,9 @@ hm_status hm_eval(hm_matrix h, const void *W, int64_t ldw, void *Y, int64_t ldy,
     int grid = 0;
     GraphPlan *plan = nullptr;
     if (!level_sched) {
-        const int workers = std::max(1, persistent_occupancy(es, bn_kind[3], mixed, h->symmetric) * h->n_cu);
+        const int workers =
+            std::max(1, persistent_occupancy(es, bn_kind[3], mixed, h->symmetric, e.narrow && Qp % bn_kind[3] != 0) *
+                            h->n_cu);
         hm_status pst = get_plan(h, slot, bn_kind[3], Qp, workers, &plan, mixed ? 1 : 0);
         if (pst != HM_OK) return pst;
         MatDesc md{h->prec[mixed ? HM_PREC_FP64 : prec].blocks, {bufs[0], bufs[1], bufs[2], bufs[3]},

@@ -74,10 +74,18 @@ hm_status configure(hm_batch b, int bn) {
     }
     b->bn = bn;
     b->ldq.resize(b->n);
+    bool sym = false;
+    for (int i = 0; i < b->n; i++) sym = sym || b->hs[i]->symmetric;
+    // with 256-column tiles, each matrix's last columns in a tile no wider
+    // than they need (not with symmetric stores, whose launch has no
+    // narrow-tile instantiation)
+    const bool narrow_tail = !sym && bn == 256;
+    bool narrow = false;
     size_t total = 0;
     std::vector<size_t> off(b->n);
     for (int i = 0; i < b->n; i++) {
-        b->ldq[i] = (b->Q[i] + bn - 1) / bn * bn;
+        b->ldq[i] = padded_columns(b->Q[i], bn, narrow_tail);
+        narrow = narrow || b->ldq[i] % bn != 0;
         off[i] = total;
         const size_t rows = 2 * (size_t)b->hs[i]->N + 2 * (size_t)b->hs[i]->skel_rows;
         total += (rows * (size_t)b->ldq[i] * b->es + 255) / 256 * 256;
@@ -107,12 +115,10 @@ hm_status configure(hm_batch b, int bn) {
         pd.perm = h->d_perm;
         pd.N = h->N;
         pd.Q = b->Q[i];
-        parts.push_back({h, i, (int)(b->ldq[i] / bn)});
+        parts.push_back({h, i, b->ldq[i]});
     }
     HM_HIP(hipMemcpy(b->d_mats, mats.data(), sizeof(MatDesc) * b->n, hipMemcpyHostToDevice));
-    bool sym = false;
-    for (int i = 0; i < b->n; i++) sym = sym || b->hs[i]->symmetric;
-    const int occ = persistent_occupancy(b->es, bn, false, sym);
+    const int occ = persistent_occupancy(b->es, bn, false, sym, narrow);
     const int workers = std::max(1, occ * b->hs[0]->n_cu);
     hm_status st = build_plan(parts, bn, b->es, workers, b->plan);
     if (st != HM_OK) return st;
@@ -174,8 +180,13 @@ hm_status hm_batch_create(int n, const hm_matrix *hs, const int64_t *Q, hm_dtype
     if (!out) return fail(HM_ERR_INVALID, "hm_batch_create: out is NULL");
     *out = nullptr;
     if (n < 1 || !hs || !Q) return fail(HM_ERR_INVALID, "hm_batch_create: need n >= 1 matrices and widths");
-    if (flags & ~(HM_BATCH_AUTOTUNE | HM_BATCH_NO_GRAPH))
+    if (flags & ~(HM_BATCH_AUTOTUNE | HM_BATCH_NO_GRAPH | HM_BATCH_TILE(0x1ff)))
         return fail(HM_ERR_INVALID, "hm_batch_create: unknown flags");
+    const int fixed_bn = (int)((flags >> 8) & 0x1ff);
+    if (fixed_bn && fixed_bn != 16 && fixed_bn != 32 && fixed_bn != 64 && fixed_bn != 128 && fixed_bn != 256)
+        return fail(HM_ERR_INVALID, "hm_batch_create: HM_BATCH_TILE takes 16, 32, 64, 128 or 256");
+    if (fixed_bn && (flags & HM_BATCH_AUTOTUNE))
+        return fail(HM_ERR_INVALID, "hm_batch_create: HM_BATCH_TILE and HM_BATCH_AUTOTUNE exclude each other");
     if (!((dtype == HM_F64 && prec == HM_PREC_FP64) || (dtype == HM_F32 && prec == HM_PREC_FP32)))
         return fail(HM_ERR_INVALID, "hm_batch_create: dtype and precision do not match");
     int64_t maxq = 0;
@@ -217,7 +228,7 @@ hm_status hm_batch_create(int n, const hm_matrix *hs, const int64_t *Q, hm_dtype
     HM_HIP(hipMemset(b->d_head, 0, 2 * sizeof(int32_t)));
     double tk = 0;
     for (int i = 0; i < n; i++) tk = std::max(tk, hs[i]->task_k);
-    const int default_bn = graph_bn(maxq, b->es, false, tk);
+    const int default_bn = fixed_bn ? fixed_bn : graph_bn(maxq, b->es, false, tk);
     if (flags & HM_BATCH_AUTOTUNE) {
         // time every candidate tile on the batch's own (zeroed) workspaces
         hipEvent_t t0, t1;

@@ -131,7 +131,9 @@ struct PTask {
     int32_t out_buf, M, m0, seg_begin, seg_end;
     int32_t bm;          // tile height: 32, 64, 96 or 128 (64 or 128 in a mixed-precision launch)
     int32_t accumulate;  // 1: out += product (a leaf's far part after its near part)
-    int32_t qtile;       // column tile: columns [qtile * BN, (qtile + 1) * BN)
+    int32_t n0;          // first column of the tile
+    int32_t bn;          // tile width: the launch's column tile, or (a plan with narrow tiles) a
+                         // narrower power of two for the last columns of a matrix
     int32_t mat;         // index into the MatDesc table
     int32_t ndeps;       // entries that must finish first
     int32_t succ_begin, succ_end;  // successor entries (queue positions) in the succ array
@@ -204,7 +206,7 @@ struct GJob {
 // Expanded, ordered graph of one matrix for one (column tile, Q) choice.
 struct GraphPlan {
     int bn = 0;
-    int64_t Q = -1;
+    int64_t Q = -1;      // cache key: padded columns (padded_columns)
     int mode = 0;        // 0: native job graph, 1: mixed-precision job graph
     int n_tasks = 0;
     PTask *d_tasks = nullptr;
@@ -212,6 +214,7 @@ struct GraphPlan {
     int32_t *d_counters = nullptr;
     double est_ms = 0;   // list-scheduling estimate (diagnostic)
     bool sym = false;    // some matrix of the plan has a symmetric store (mirror blocks)
+    bool narrow = false; // some tile is narrower than bn (launched with the narrow-tile instantiation)
 };
 
 // Output of inspector-p1 (Section 5 "Reusing Inspection"): everything the
@@ -395,7 +398,8 @@ struct EvalSetup {
     int es = 8, slot = 0; // element bytes of W and Y; workspace / plan slot (0 FP64, 1 FP32)
     bool mixed = false, level_sched = false, near_pts = false, far_pts = false, from_points = false;
     int bn_kind[4] = {0, 0, 0, 0};  // column tile per phase kind (1 up, 2 down, 3 leaf); one tile for the graph
-    int64_t Qp = 0;                 // workspace leading dimension (Q rounded up to the column tile)
+    int64_t Qp = 0;                 // workspace leading dimension (padded_columns)
+    bool narrow = false;            // the task graph may end a matrix's columns with a narrower tile
     const int64_t *perm = nullptr;  // tree position -> caller's row (null with HM_TREE_ORDER)
 };
 // Validate hm_eval's arguments against h (no device work, messages prefixed
@@ -409,7 +413,12 @@ hipError_t launch_persistent(const GraphPlan &plan, int elem_bytes, const MatDes
                              int32_t *d_head, int grid, hipStream_t s, const OutScatter &out = OutScatter{},
                              int32_t *counters = nullptr);
 // Resident workgroups per CU of the persistent kernel for (elem_bytes, bn).
-int persistent_occupancy(int elem_bytes, int bn, bool split = false, bool sym = false);
+int persistent_occupancy(int elem_bytes, int bn, bool split = false, bool sym = false, bool narrow = false);
+// Workspace columns for Q columns in tiles of bn: Q rounded up to bn, or with
+// narrow_tail, the last partial tile only to the smallest power of two (at
+// least 16) that holds it.  A plan's tiles are bn wide up to the last full
+// tile of bn in Qp and the rest is that narrower tile.
+int64_t padded_columns(int64_t Q, int bn, bool narrow_tail);
 
 // Expand the job graph for Q columns with column tile bn, order it by list
 // scheduling on `workers` simulated workgroups, and upload it (hm_sched.hip).
@@ -423,7 +432,7 @@ hm_status reserve_ws(hm_matrix h, int slot, int64_t ldq);
 struct PlanPart {
     hm_matrix h;
     int mat;  // index in the MatDesc table
-    int nq;   // column tiles
+    int64_t Qp;  // padded columns: tiles of bn, then at most one narrower tile (padded_columns)
     int mode = 0;  // which job graph of h: 0 native, 1 mixed precision
 };
 hm_status build_plan(const std::vector<PlanPart> &parts, int bn, int elem_bytes, int workers, GraphPlan &plan);

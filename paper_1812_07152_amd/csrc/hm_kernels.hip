@@ -349,6 +349,18 @@ template <int BM, int BN, bool ROWPERM>
 constexpr int f64_lds_bytes() {
     return f64_stages<BN, ROWPERM>() * (BM + BN) * kBK * 8;
 }
+// The largest f64_lds_bytes<128, W, false> over the widths W = BN, BN / 2,
+// ... 16 of a launch with narrow tiles (a narrower tile can take more stages:
+// 64 columns three, 128 columns two).
+template <int BN>
+constexpr int f64_lds_bytes_narrow() {
+    int most = 0;
+    for (int w = BN; w >= 16; w /= 2) {
+        const int b = ((w == 128) ? 2 : 3) * (128 + w) * kBK * 8;
+        most = b > most ? b : most;
+    }
+    return most;
+}
 
 // Blocks computed from points (matrix-free near and far field): with pts
 // set, a segment whose from_pts equals kind has the A block K(x_a, x_b): x_a
@@ -1134,6 +1146,57 @@ struct PLayout {
 constexpr int kPersistThreads = 512;
 constexpr int kWaitLimit = 1 << 20;  // polls (each followed by a sleep) before giving up
 
+// A tile of stored (or generated) blocks at column width W in the launch's
+// type: the row-tile height bm picks the instantiation.  Where W has no 32-
+// and 96-row tiles (fine_tiles) but the plan made them (a narrow tile in a
+// launch whose own width has them), the next taller tile covers the rows.
+template <typename T, int W, bool SPLIT, bool SYMGEN, int LDS_BYTES>
+__device__ __forceinline__ void native_tile(int bm, const TileJob &job, const Seg *__restrict__ segs,
+                                            const T *__restrict__ store, const MatDesc &md, int64_t n0, T *As,
+                                            T *Bs, const NearGen &ng) {
+    constexpr bool kFine = fine_tiles(sizeof(T), W, SPLIT);
+    // the tallest tile's stages fit the kernel's LDS (FP64: the direct-to-LDS
+    // stages from As; FP32: the register-staged As and Bs)
+    static_assert(sizeof(T) != 8 || f64_lds_bytes<128, W, SPLIT>() <= LDS_BYTES, "FP64 stages exceed the LDS");
+    static_assert(sizeof(T) != 4 ||
+                      (2 * kBK * (128 + lds_pad<T>()) + 2 * kBK * (W + lds_pad<T>())) * (int)sizeof(T) <= LDS_BYTES,
+                  "FP32 stages exceed the LDS");
+    if (bm == 128 || (!kFine && bm == 96)) {
+        block_product<T, 128, W, PLayout<128, W>::WMv, PLayout<128, W>::WN, kPersistThreads,
+                      SPLIT && sizeof(T) == 8, sizeof(T) == 8, SYMGEN>(job, segs, store, (T *)md.buf[0], (T *)md.buf[1],
+                                               (T *)md.buf[2], (T *)md.buf[3], md.ldq, n0, As, Bs, ng);
+    } else if (!kFine || bm == 64) {
+        block_product<T, 64, W, PLayout<64, W>::WMv, PLayout<64, W>::WN, kPersistThreads,
+                      SPLIT && sizeof(T) == 8, sizeof(T) == 8, SYMGEN>(job, segs, store, (T *)md.buf[0], (T *)md.buf[1],
+                                               (T *)md.buf[2], (T *)md.buf[3], md.ldq, n0, As, Bs, ng);
+    } else if constexpr (kFine) {
+        // 32- and 96-row tiles, for output blocks whose row count would
+        // waste most of a 64- or 128-row tile
+        if (bm == 96)
+            block_product<T, 96, W, PLayout<96, W>::WMv, PLayout<96, W>::WN, kPersistThreads, false,
+                          sizeof(T) == 8, SYMGEN>(job, segs, store, (T *)md.buf[0], (T *)md.buf[1], (T *)md.buf[2],
+                                                  (T *)md.buf[3], md.ldq, n0, As, Bs, ng);
+        else
+            block_product<T, 32, W, PLayout<32, W>::WMv, PLayout<32, W>::WN, kPersistThreads, false,
+                          sizeof(T) == 8, SYMGEN>(job, segs, store, (T *)md.buf[0], (T *)md.buf[1], (T *)md.buf[2],
+                                                  (T *)md.buf[3], md.ldq, n0, As, Bs, ng);
+    }
+}
+
+// native_tile at the task's own width bn (a power of two, 16 <= bn <= W).
+template <typename T, int W, bool SPLIT, bool SYMGEN, int LDS_BYTES>
+__device__ __forceinline__ void narrow_tile(int bn, int bm, const TileJob &job, const Seg *__restrict__ segs,
+                                            const T *__restrict__ store, const MatDesc &md, int64_t n0, T *As,
+                                            T *Bs, const NearGen &ng) {
+    if constexpr (W > 16) {
+        if (bn < W) {
+            narrow_tile<T, W / 2, SPLIT, SYMGEN, LDS_BYTES>(bn, bm, job, segs, store, md, n0, As, Bs, ng);
+            return;
+        }
+    }
+    native_tile<T, W, SPLIT, SYMGEN, LDS_BYTES>(bm, job, segs, store, md, n0, As, Bs, ng);
+}
+
 // Persistent task-graph launch: workgroups take queue entries in order with
 // an atomic head; an entry starts once its dependency counter is zero (a
 // bounded wait, see kWaitLimit), then decrements its successors' counters
@@ -1142,22 +1205,28 @@ constexpr int kWaitLimit = 1 << 20;  // polls (each followed by a sleep) before 
 // queue order is topological, so every awaited entry was taken earlier by a
 // running workgroup: the launch cannot deadlock and every workgroup exits
 // when the queue is drained.
+// NARROW: a 256-column launch whose plan has narrower tiles for the last
+// columns of a matrix (GraphPlan::narrow): a task runs at its own width pt.bn
+// (256, 128, ... 16); a separate instantiation, so that launches without such
+// tiles keep their registers and code.
 // GEN: the FP64 launch that computes the near blocks from the points (see
 // NearGen); a separate instantiation, so that the stored-block launch keeps
 // its registers and code.
-template <typename T, int BN, bool SPLIT, bool GEN = false, bool SYM = false>
-__global__ __launch_bounds__(kPersistThreads, BN <= 128 ? 4 : 1) void k_persistent(
+template <typename T, int BN, bool SPLIT, bool GEN = false, bool SYM = false, bool NARROW = false>
+__global__ __launch_bounds__(kPersistThreads, (NARROW && sizeof(T) == 4) || BN <= 128 ? 4 : 1)
+void k_persistent(
     const PTask *__restrict__ tasks, int n_tasks, const int32_t *__restrict__ succ,
     int32_t *counters, int32_t *head, int32_t *err, const MatDesc *__restrict__ mats, void *Y, int64_t ldy,
     int64_t Q, const int64_t *__restrict__ perm) {
     constexpr int kRegs = (2 * kBK * (128 + lds_pad<T>()) + 2 * kBK * (BN + lds_pad<T>())) * (int)sizeof(T);
-    constexpr int kNative = sizeof(T) == 8 ? f64_lds_bytes<128, BN, SPLIT>() : kRegs;
+    constexpr int kNative = sizeof(T) != 8 ? kRegs : NARROW ? f64_lds_bytes_narrow<BN>() : f64_lds_bytes<128, BN, SPLIT>();
     constexpr int kSplit = (SPLIT && sizeof(T) == 8) ? split_f64_lds_bytes<128, BN>() : 0;
     constexpr int kMain = kNative > kSplit ? kNative : kSplit;
     // (not at 64 columns, where the points' LDS would cost the second
     // workgroup per compute unit: hm_eval runs that mode at 128 columns)
     constexpr bool kGen = GEN;
     static_assert(!GEN || (sizeof(T) == 8 && !SPLIT && BN != 64), "near blocks from points: FP64 only");
+    static_assert(!NARROW || (!SPLIT && !GEN && BN == 256), "narrow tiles: 256-column stored-block launches only");
     __shared__ __attribute__((aligned(16))) char lds[kMain + (kGen ? kPointLds : 0)];
     T *As = reinterpret_cast<T *>(lds);
     T *Bs = As + 2 * kBK * (128 + lds_pad<T>());
@@ -1195,7 +1264,7 @@ __global__ __launch_bounds__(kPersistThreads, BN <= 128 ? 4 : 1) void k_persiste
                 job.out_split = pt.out_split;
             }
         }
-        const int64_t n0 = (int64_t)pt.qtile * BN;
+        const int64_t n0 = pt.n0;
         const T *store = (const T *)md.store;
         const Seg *segs = md.segs;
         NearGen ng;
@@ -1239,27 +1308,10 @@ __global__ __launch_bounds__(kPersistThreads, BN <= 128 ? 4 : 1) void k_persiste
                                                  kPersistThreads>(job, segs, (const double *)store, s16, w16, wh16,
                                                                   yh16, b0, b1, b2, b3, md.ldq, n0, lds);
             }
-        } else if (pt.bm == 128) {
-            block_product<T, 128, BN, PLayout<128, BN>::WMv, PLayout<128, BN>::WN, kPersistThreads,
-                          SPLIT && sizeof(T) == 8, sizeof(T) == 8, SYM || GEN>(job, segs, store, (T *)md.buf[0], (T *)md.buf[1],
-                                                   (T *)md.buf[2], (T *)md.buf[3], md.ldq, n0, As, Bs, ng);
-        } else if (!fine_tiles(sizeof(T), BN, SPLIT) || pt.bm == 64) {
-            block_product<T, 64, BN, PLayout<64, BN>::WMv, PLayout<64, BN>::WN, kPersistThreads,
-                          SPLIT && sizeof(T) == 8, sizeof(T) == 8, SYM || GEN>(job, segs, store, (T *)md.buf[0], (T *)md.buf[1],
-                                                   (T *)md.buf[2], (T *)md.buf[3], md.ldq, n0, As, Bs, ng);
-        } else if constexpr (fine_tiles(sizeof(T), BN, SPLIT)) {
-            // 32- and 96-row tiles, for output blocks whose row count would
-            // waste most of a 64- or 128-row tile
-            if (pt.bm == 96)
-                block_product<T, 96, BN, PLayout<96, BN>::WMv, PLayout<96, BN>::WN, kPersistThreads, false,
-                              sizeof(T) == 8, SYM || GEN>(
-                    job, segs, store, (T *)md.buf[0], (T *)md.buf[1], (T *)md.buf[2], (T *)md.buf[3],
-                    md.ldq, n0, As, Bs, ng);
-            else
-                block_product<T, 32, BN, PLayout<32, BN>::WMv, PLayout<32, BN>::WN, kPersistThreads, false,
-                              sizeof(T) == 8, SYM || GEN>(
-                    job, segs, store, (T *)md.buf[0], (T *)md.buf[1], (T *)md.buf[2], (T *)md.buf[3],
-                    md.ldq, n0, As, Bs, ng);
+        } else if constexpr (NARROW) {
+            narrow_tile<T, BN, SPLIT, SYM || GEN, kMain>(pt.bn, pt.bm, job, segs, store, md, n0, As, Bs, ng);
+        } else {
+            native_tile<T, BN, SPLIT, SYM || GEN, kMain>(pt.bm, job, segs, store, md, n0, As, Bs, ng);
         }
         __syncthreads();  // every wave's stores of this task are done
         if (threadIdx.x == 0 && pt.succ_end > pt.succ_begin) {
@@ -1518,6 +1570,7 @@ template <typename T, int BN>
 hipError_t run_persistent(const GraphPlan &plan, const MatDesc *mats, int32_t *head, int grid,
                           const OutScatter &out, int32_t *counters, hipStream_t s) {
     const int nt = plan.n_tasks;
+    if (plan.narrow && (plan.sym || plan.mode == 1 || out.from_points || BN != 256)) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_persistent_init, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s,
                        plan.d_tasks, nt, counters, head);
     if constexpr (sizeof(T) == 8 && BN != 64) {
@@ -1537,6 +1590,14 @@ hipError_t run_persistent(const GraphPlan &plan, const MatDesc *mats, int32_t *h
         hipLaunchKernelGGL((k_persistent<T, BN, false, false, true>), dim3((unsigned)grid), dim3(kPersistThreads),
                            0, s, plan.d_tasks, nt, plan.d_succ, counters, head, head + 1, mats, out.Y,
                            out.ldy, out.Q, out.perm);
+    else if (plan.narrow) {
+        if constexpr (BN == 256)
+            hipLaunchKernelGGL((k_persistent<T, BN, false, false, false, true>), dim3((unsigned)grid),
+                               dim3(kPersistThreads), 0, s, plan.d_tasks, nt, plan.d_succ, counters, head, head + 1,
+                               mats, out.Y, out.ldy, out.Q, out.perm);
+        else
+            return hipErrorInvalidValue;
+    }
     else
         hipLaunchKernelGGL((k_persistent<T, BN, false>), dim3((unsigned)grid), dim3(kPersistThreads), 0,
                            s, plan.d_tasks, nt, plan.d_succ, counters, head, head + 1, mats, out.Y,
@@ -1556,7 +1617,7 @@ hipError_t persistent_bn(const GraphPlan &plan, const MatDesc *mats, int32_t *he
     }
 }
 
-template <typename T, bool SPLIT, bool SYM = false>
+template <typename T, bool SPLIT, bool SYM = false, bool NARROW = false>
 int occupancy_bn(int bn) {
     int n = 0;
     hipError_t e = hipSuccess;
@@ -1565,7 +1626,7 @@ int occupancy_bn(int bn) {
         case 32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_persistent<T, 32, SPLIT, false, SYM>, kPersistThreads, 0); break;
         case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_persistent<T, 64, SPLIT, false, SYM>, kPersistThreads, 0); break;
         case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_persistent<T, 128, SPLIT, false, SYM>, kPersistThreads, 0); break;
-        default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_persistent<T, 256, SPLIT, false, SYM>, kPersistThreads, 0); break;
+        default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_persistent<T, 256, SPLIT, false, SYM, NARROW>, kPersistThreads, 0); break;
     }
     return e == hipSuccess ? std::max(n, 1) : 1;
 }
@@ -1581,11 +1642,13 @@ hipError_t launch_persistent(const GraphPlan &plan, int elem_bytes, const MatDes
                            : persistent_bn<float>(plan, d_mat, d_head, grid, out, c, s);
 }
 
-int persistent_occupancy(int elem_bytes, int bn, bool split, bool sym) {
+int persistent_occupancy(int elem_bytes, int bn, bool split, bool sym, bool narrow) {
+    narrow = narrow && !split && !sym && bn == 256;
     if (elem_bytes == 8)
         return split ? occupancy_bn<double, true>(bn) : sym ? occupancy_bn<double, false, true>(bn)
-                                                            : occupancy_bn<double, false>(bn);
-    return sym ? occupancy_bn<float, false, true>(bn) : occupancy_bn<float, false>(bn);
+               : narrow ? occupancy_bn<double, false, false, true>(bn) : occupancy_bn<double, false>(bn);
+    return sym ? occupancy_bn<float, false, true>(bn)
+               : narrow ? occupancy_bn<float, false, false, true>(bn) : occupancy_bn<float, false>(bn);
 }
 
 hipError_t launch_permute_in(const void *W, int64_t ldw, void *Wt, int64_t Qp, const int64_t *perm,

@@ -102,7 +102,9 @@ hm_status hm_eval_noalloc(hm_matrix h, const void *W, int64_t ldw, void *Y, int6
     if (ws_total > kScratchBytes) return too_big(ws_total);
     DeviceScope ds(h->device);
     if (ds.err != hipSuccess) return fail(HM_ERR_DEVICE, "hm_eval_noalloc: cannot select the device");
-    const int workers = std::max(1, persistent_occupancy(e.es, e.bn_kind[3], e.mixed, h->symmetric) * h->n_cu);
+    const int workers = std::max(
+        1, persistent_occupancy(e.es, e.bn_kind[3], e.mixed, h->symmetric, e.narrow && Qp % e.bn_kind[3] != 0) *
+               h->n_cu);
     GraphPlan *plan = nullptr;
     {
         hm_status pst = get_plan(h, e.slot, e.bn_kind[3], Qp, workers, &plan, e.mixed ? 1 : 0, false);

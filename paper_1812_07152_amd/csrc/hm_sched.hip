@@ -37,6 +37,7 @@ hm_status build_plan(const std::vector<PlanPart> &parts, int bn, int elem_bytes,
     struct P {
         const std::vector<GJob> *jobs;
         int mat, nq, per_q;
+        std::vector<std::pair<int32_t, int32_t>> cols;  // column tiles: (first column, width)
         int64_t base;
         std::vector<int32_t> rows, bm, first;  // bm: height of a job's row tiles (its last one: last_bm)
         std::vector<int32_t> last_bm;
@@ -50,7 +51,14 @@ hm_status build_plan(const std::vector<PlanPart> &parts, int bn, int elem_bytes,
         P &p = ps[i];
         p.jobs = parts[i].mode == 1 ? &parts[i].h->gjobs_mixed : &parts[i].h->gjobs;
         p.mat = parts[i].mat;
-        p.nq = parts[i].nq;
+        for (int64_t n0 = 0; n0 < parts[i].Qp; n0 += bn) {
+            const int64_t w = std::min<int64_t>(bn, parts[i].Qp - n0);
+            if (w < 16 || (w & (w - 1)) != 0 || (w < bn && n0 + w != parts[i].Qp))
+                return fail(HM_ERR_INTERNAL, "task graph: padded columns are not whole tiles");
+            p.cols.push_back({(int32_t)n0, (int32_t)w});
+        }
+        p.nq = (int)p.cols.size();
+        if (p.nq == 0) return fail(HM_ERR_INTERNAL, "task graph: no columns");
         const std::vector<GJob> &jobs = *p.jobs;
         const int nj = (int)jobs.size();
         p.rows.resize(nj);
@@ -155,10 +163,10 @@ hm_status build_plan(const std::vector<PlanPart> &parts, int bn, int elem_bytes,
         locate(e, pi, q, j, r);
         return ps[pi].blevel[ps[pi].first[j] + r];
     };
-    auto cost_of = [&](int e) {
+    auto cost_of = [&](int e) {  // the per-column part scales with the tile's width
         int pi, q, j, r;
         locate(e, pi, q, j, r);
-        return ps[pi].cost[ps[pi].first[j] + r];
+        return (ps[pi].cost[ps[pi].first[j] + r] - overhead) * ps[pi].cols[q].second / bn + overhead;
     };
     for (int e = 0; e < total; e++)
         if (remaining[e] == 0) avail.push({blevel_of(e), ekey[e], e});
@@ -225,7 +233,8 @@ hm_status build_plan(const std::vector<PlanPart> &parts, int bn, int elem_bytes,
         t.out16 = g.out16 >= 0 ? g.out16 + t.m0 : -1;
         t.out_split = g.out16 >= 0 ? g.out_split : 0;
         t.accumulate = g.accumulate;
-        t.qtile = q;
+        t.n0 = p.cols[q].first;
+        t.bn = p.cols[q].second;
         t.mat = p.mat;
         t.mode = g.mode;
         t.ndeps = ndeps[e];
@@ -251,6 +260,8 @@ hm_status build_plan(const std::vector<PlanPart> &parts, int bn, int elem_bytes,
                     std::string("uploading the task graph: ") + hipGetErrorString(err));
     }
     plan.bn = bn;
+    plan.narrow = false;
+    for (const P &p : ps) plan.narrow = plan.narrow || p.cols.back().second < bn;
     plan.sym = false;
     for (const PlanPart &pp : parts) plan.sym = plan.sym || pp.h->symmetric;
     plan.n_tasks = total;
@@ -258,11 +269,19 @@ hm_status build_plan(const std::vector<PlanPart> &parts, int bn, int elem_bytes,
     return HM_OK;
 }
 
+int64_t padded_columns(int64_t Q, int bn, bool narrow_tail) {
+    const int64_t full = Q / bn * bn, rest = Q - full;
+    if (rest == 0) return std::max<int64_t>(full, bn);
+    if (!narrow_tail) return full + bn;
+    int64_t w = 16;
+    while (w < rest) w *= 2;
+    return full + std::min<int64_t>(w, bn);
+}
+
 hm_status get_plan(hm_matrix h, int slot, int bn, int64_t ldq, int workers, GraphPlan **out,
                    int mode, bool build) {
-    const int nq = (int)(ldq / bn);
     for (GraphPlan &p : h->plans[slot])
-        if (p.bn == bn && p.Q == nq && p.mode == mode) {
+        if (p.bn == bn && p.Q == ldq && p.mode == mode) {
             *out = &p;
             return HM_OK;
         }
@@ -274,10 +293,10 @@ hm_status get_plan(hm_matrix h, int slot, int bn, int64_t ldq, int workers, Grap
         h->plans[slot].erase(h->plans[slot].begin());
     }
     GraphPlan p;
-    std::vector<PlanPart> parts{{h, 0, nq, mode}};
+    std::vector<PlanPart> parts{{h, 0, ldq, mode}};
     hm_status st = build_plan(parts, bn, slot == 0 ? 8 : 4, workers, p);
     if (st != HM_OK) return st;
-    p.Q = nq;  // cache key: column tiles
+    p.Q = ldq;  // cache key: padded columns
     p.mode = mode;
     h->plans[slot].push_back(p);
     *out = &h->plans[slot].back();

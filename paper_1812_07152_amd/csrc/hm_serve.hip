@@ -60,7 +60,7 @@ struct Req {
     hm_status status = HM_OK;
 };
 
-// Plans of one resident matrix, one per (column tile, column tiles) shape a
+// Plans of one resident matrix, one per (column tile, padded columns) shape a
 // sweep of 1..kServeMaxCols columns can take.
 struct Resident {
     hm_matrix h = nullptr;
@@ -128,10 +128,12 @@ namespace {
                         std::string(#call ": ") + hipGetErrorString(e_));            \
     } while (0)
 
-// Column tile and tile count of a sweep of `cols` columns.
+// Column tile and padded columns of a sweep of `cols` columns (in 256-column
+// launches the last tile no wider than it needs, except with a symmetric
+// store).
 std::pair<int, int> sweep_shape(hm_server S, hm_matrix h, int64_t cols) {
     const int bn = graph_bn(cols, S->es, false, h->task_k);
-    return {bn, (int)((cols + bn - 1) / bn)};
+    return {bn, (int)padded_columns(cols, bn, !h->symmetric && bn == 256)};
 }
 
 void finish(hm_server S, Req *r, hm_status st, double t) {
@@ -167,7 +169,7 @@ bool try_launch(hm_server S, int m, int si) {
     for (size_t i = 0; i < take.size(); i++) R.pending.pop_front();
     const std::pair<int, int> shape = sweep_shape(S, R.h, cols);
     const GraphPlan &plan = R.plans.at(shape);
-    const int64_t width = (int64_t)shape.first * shape.second;
+    const int64_t width = shape.second;
     // request table (pinned staging, copied on the slot's stream)
     int64_t off = 0;
     for (size_t i = 0; i < take.size(); i++) {
@@ -188,7 +190,8 @@ bool try_launch(hm_server S, int m, int si) {
         e = launch_gather_in(sl.d_reqs, sl.d_col2req, cols, width, sl.ws[BUF_WT], kServeMaxCols, R.h->d_perm,
                              R.h->N, S->es, st);
     if (e == hipSuccess) {
-        const int workers = std::max(1, persistent_occupancy(S->es, shape.first, false, R.h->symmetric) * R.h->n_cu);
+        const int workers =
+            std::max(1, persistent_occupancy(S->es, shape.first, false, R.h->symmetric, plan.narrow) * R.h->n_cu);
         e = launch_persistent(plan, S->es, sl.mats + m, sl.head, std::min(plan.n_tasks, workers), st,
                               OutScatter{}, sl.counters);
     }
@@ -407,7 +410,7 @@ hm_status hm_server_add(hm_server S, hm_matrix h, int *mat_id) {
         int d;
         ~Restore() { (void)hipSetDevice(d); }
     } restore{prev};
-    // a plan for every (column tile, tile count) shape of a 1..kServeMaxCols
+    // a plan for every (column tile, padded columns) shape of a 1..kServeMaxCols
     // column sweep, so that sweeps never plan, allocate or upload
     Resident R;
     R.h = h;
@@ -419,7 +422,9 @@ hm_status hm_server_add(hm_server S, hm_matrix h, int *mat_id) {
         if (R.plans.count(shape)) continue;
         GraphPlan p;
         std::vector<PlanPart> parts{{h, 0, shape.second, 0}};
-        st = build_plan(parts, shape.first, S->es, persistent_occupancy(S->es, shape.first, false, h->symmetric) * h->n_cu, p);
+        const bool narrow = shape.second % shape.first != 0;
+        st = build_plan(parts, shape.first, S->es,
+                        persistent_occupancy(S->es, shape.first, false, h->symmetric, narrow) * h->n_cu, p);
         if (st == HM_OK) {
             n_counters = std::max<int64_t>(n_counters, p.n_tasks);
             R.plans[shape] = p;

@@ -21,6 +21,11 @@ HM_PREC_FP64, HM_PREC_FP32, HM_PREC_BF16X3 = 0, 1, 2
 HM_TREE_ORDER, HM_PROFILE, HM_NEAR_FROM_POINTS, HM_FAR_FROM_POINTS, HM_LEVEL_LAUNCHES = 1, 2, 4, 8, 16
 HM_LOAD_NO_NEAR_BLOCKS, HM_LOAD_NO_FAR_BLOCKS, HM_LOAD_SYMMETRIC = 1 << 8, 1 << 9, 1 << 10
 HM_BATCH_AUTOTUNE, HM_BATCH_NO_GRAPH = 1, 2
+
+
+def HM_BATCH_TILE(bn: int) -> int:
+    """hm_batch_create flag: fix the column tile (16, 32, 64, 128 or 256)."""
+    return int(bn) << 8
 HM_NOALLOC_SCRATCH_BYTES = 64 << 20
 STATUS_NAMES = {0: "HM_OK", -1: "HM_ERR_INVALID", -2: "HM_ERR_FORMAT", -3: "HM_ERR_NOMEM",
                 -4: "HM_ERR_DEVICE", -5: "HM_ERR_BUSY", -6: "HM_ERR_PENDING", -7: "HM_ERR_INTERNAL"}

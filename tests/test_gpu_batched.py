@@ -78,3 +78,39 @@ def test_batch_rejects_bad_arguments(setup):
     Ws = [torch.zeros(H.N, 4, dtype=torch.float64, device="cuda") for H in Hs[:2]]
     with pytest.raises(ValueError):
         hmx.hm_batch_eval(B, Ws, [torch.zeros(10, 4, dtype=torch.float64, device="cuda")] * 2)
+
+
+@pytest.mark.parametrize("dtype", ["fp64", "fp32"])
+def test_batched_256_column_tile_narrow_last_tiles(setup, dtype):
+    """HM_BATCH_TILE(256): the widths 5, 17, 64, 100 and 300 end in tiles of
+    16, 32, 64, 128 and 64 columns (300 = 256 + 44); FP64 to the parity bar
+    and FP32 to its bar against the oracle, and each matrix as hm_eval
+    computes it alone (128-column tiles: the same products per column)."""
+    hmx, Hs, Ms = setup
+    f64 = dtype == "fp64"
+    tdt = torch.float64 if f64 else torch.float32
+    B = hmx.hm_batch_create(Ms, [w.Q for w in SPECS], dtype=hmx.HM_F64 if f64 else hmx.HM_F32,
+                            flags=hmx.HM_BATCH_TILE(256))
+    assert hmx.hm_batch_info(B)["column_tile"] == 256
+    for rep in range(2):
+        Ws, Ys = _inputs(tdt, seed_off=10 + rep)
+        hmx.hm_batch_eval(B, Ws, Ys)
+        hmx.hm_batch_check(B)
+        for H, W, Y, M in zip(Hs, Ws, Ys, Ms):
+            Wn = W.double().cpu().numpy()
+            Yb = Y.double().cpu().numpy()
+            ref = H.eval(Wn)
+            assert rel(Yb, ref) <= (1e-10 if f64 else 5e-6)
+            Ys_ = torch.empty_like(W)
+            hmx.hm_eval(M, W, Ys_)
+            torch.cuda.synchronize()
+            np.testing.assert_allclose(Yb, Ys_.double().cpu().numpy(), rtol=0,
+                                       atol=(1e-13 if f64 else 1e-6) * np.abs(ref).max())
+
+
+def test_batched_tile_flag_refusals(setup):
+    hmx, Hs, Ms = setup
+    Q = [w.Q for w in SPECS]
+    for bad in (hmx.HM_BATCH_TILE(48), hmx.HM_BATCH_TILE(512), hmx.HM_BATCH_TILE(128) | hmx.HM_BATCH_AUTOTUNE):
+        with pytest.raises(hmx.HMError):
+            hmx.hm_batch_create(Ms, Q, flags=bad)

@@ -126,6 +126,31 @@ def test_fp32_path(hmx):
         gpu_eval(hmx, M, W, prec_f64=True)
 
 
+@pytest.mark.parametrize("name", ["mix8", "tall"])
+def test_narrow_last_tiles(hmx, name, sched):
+    """Q past a whole number of column tiles: the task-graph launch ends the
+    columns with a tile of 16, 32 or 64 columns (Q = 144, 160, 192, 300 in
+    128-column launches; 320 and 384 are whole tiles); FP64 to the parity bar
+    and FP32 to its bar (5e-6) against the oracle, and the columns past Q of
+    the caller's Y untouched.  (The 256-column FP64 launch's narrower tiles
+    are checked at full size, test_c2_full_size_sampled_columns.)"""
+    w, H = built(name)
+    M = hmx.hm_load_compressed_mem(H, 0, hmx.precbit(hmx.HM_PREC_FP64) | hmx.precbit(hmx.HM_PREC_FP32))
+    for Q in (144, 160, 192, 300, 320, 384):
+        _say(f"[narrow] case={name} Q={Q} sched={sched}")
+        W = wl.gen_w(w, Q=Q, seed=900 + Q)
+        Yref = H.eval(W)
+        check_f64(gpu_eval(hmx, M, W), Yref)
+        Y32 = gpu_eval(hmx, M, W, prec_f64=False)
+        assert rel(Y32, H.eval(W.astype(np.float32).astype(np.float64))) <= 5e-6
+        big_y = torch.full((w.N, Q + 7), 3.0, dtype=torch.float64, device="cuda")
+        ev(hmx, M, torch.from_numpy(W).cuda(), big_y, Q=Q)
+        hmx.hm_check(M)
+        out = big_y.cpu().numpy()
+        check_f64(out[:, :Q], Yref)
+        assert np.all(out[:, Q:] == 3.0)
+
+
 def test_tree_order_flag_and_strided_views(hmx):
     w, H = built("mix8")
     M = hmx.hm_load_compressed_mem(H, 0)
@@ -191,6 +216,14 @@ def test_c2_full_size_sampled_columns(hmx, sched):
     Yref = H.eval(np.ascontiguousarray(W[:, cols]))
     check_f64(Y[:, cols], Yref)
     if sched == "graph":
+        # a narrower last tile in the 256-column FP64 launch (64 and 128
+        # columns): W's first columns repeated past column 256 come out as
+        # they did in the first tile, and the first 256 columns unchanged
+        for extra in (64, 128):
+            _say(f"[parity] c2 full size: gpu eval Q={256 + extra}")
+            Ye = gpu_eval(hmx, M, np.ascontiguousarray(np.concatenate([W, W[:, :extra]], axis=1)))
+            assert np.array_equal(Ye[:, :256], Y)
+            check_f64(Ye[:, 256:], Y[:, :extra])
         _say("[parity] c2 full size: split-BF16 eval Q=256")
         Wd = torch.from_numpy(W).cuda()
         Yd = torch.full_like(Wd, float("nan"))
