@@ -563,19 +563,32 @@ __device__ __forceinline__ void product_loop_f64_dma(
         const char *sa = lds + st * kStage;
         const char *sb_ = sa + BM * kBK * 8;
         double r2g[NV];
-#pragma unroll
-        for (int ks = 0; ks < kBK; ks += 4) {
-            double af[FM], bf[FN];
+        // 256-column tiles (registers to spare at two waves per SIMD): the
+        // next k-step's operands are read from LDS before this k-step's
+        // MFMAs, so that their latency hides behind them
+        constexpr bool kPipe = BN >= 256;
+        double af[2][FM], bf[2][FN];
+        auto frags = [&](int ks, double (&a)[FM], double (&b)[FN]) {
 #pragma unroll
             for (int i = 0; i < FM; i++)
-                af[i] = *reinterpret_cast<const double *>(sa + ks * BM * 8 + ((i & 1) ? a_odd : a_even) + i * 128);
+                a[i] = *reinterpret_cast<const double *>(sa + ks * BM * 8 + ((i & 1) ? a_odd : a_even) + i * 128);
 #pragma unroll
             for (int j = 0; j < FN; j++)
-                bf[j] = *reinterpret_cast<const double *>(sb_ + ks * BN * 8 + ((j & 1) ? b_odd : b_even) + j * 128);
+                b[j] = *reinterpret_cast<const double *>(sb_ + ks * BN * 8 + ((j & 1) ? b_odd : b_even) + j * 128);
+        };
+        if constexpr (kPipe) frags(0, af[0], bf[0]);
+#pragma unroll
+        for (int ks = 0; ks < kBK; ks += 4) {
+            const int cb = kPipe ? (ks / 4) & 1 : 0;
+            if constexpr (kPipe) {
+                if (ks + 4 < kBK) frags(ks + 4, af[cb ^ 1], bf[cb ^ 1]);
+            } else {
+                frags(ks, af[0], bf[0]);
+            }
 #pragma unroll
             for (int i = 0; i < FM; i++)
 #pragma unroll
-                for (int j = 0; j < FN; j++) acc[i][j] = Mfma<double>::mma(af[i], bf[j], acc[i][j]);
+                for (int j = 0; j < FN; j++) acc[i][j] = Mfma<double>::mma(af[cb][i], bf[cb][j], acc[i][j]);
             if (g && ks == 0) make_dist(gsg, gkk, r2g);
             if (g && ks == kStoreStep) make_store(gst, gsg, gkk, r2g);
         }
