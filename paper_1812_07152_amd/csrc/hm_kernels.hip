@@ -565,7 +565,8 @@ __device__ __forceinline__ void product_loop_f64_dma(
         double r2g[NV];
         // 256-column tiles (registers to spare at two waves per SIMD): the
         // next k-step's operands are read from LDS before this k-step's
-        // MFMAs, so that their latency hides behind them
+        // MFMAs, so that their latency hides behind them (128-column tiles,
+        // at four waves per SIMD, gained nothing from it)
         constexpr bool kPipe = BN >= 256;
         double af[2][FM], bf[2][FN];
         auto frags = [&](int ks, double (&a)[FM], double (&b)[FN]) {
