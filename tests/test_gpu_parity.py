@@ -216,10 +216,10 @@ def test_c2_full_size_sampled_columns(hmx, sched):
     Yref = H.eval(np.ascontiguousarray(W[:, cols]))
     check_f64(Y[:, cols], Yref)
     if sched == "graph":
-        # a narrower last tile in the 256-column FP64 launch (64 and 128
-        # columns): W's first columns repeated past column 256 come out as
-        # they did in the first tile, and the first 256 columns unchanged
-        for extra in (64, 128):
+        # narrower last tiles in the 256-column FP64 launch (64 columns for 48
+        # and 64, 128 for 128): W's first columns repeated past column 256
+        # come out as they did in the first tile, the first 256 unchanged
+        for extra in (64, 128, 48):
             _say(f"[parity] c2 full size: gpu eval Q={256 + extra}")
             Ye = gpu_eval(hmx, M, np.ascontiguousarray(np.concatenate([W, W[:, :extra]], axis=1)))
             assert np.array_equal(Ye[:, :256], Y)
