@@ -1164,7 +1164,7 @@ constexpr int kWaitLimit = 1 << 20;  // polls (each followed by a sleep) before 
 // type: the row-tile height bm picks the instantiation.  Where W has no 32-
 // and 96-row tiles (fine_tiles) but the plan made them (a narrow tile in a
 // launch whose own width has them), the next taller tile covers the rows.
-template <typename T, int W, bool SPLIT, bool SYMGEN, int LDS_BYTES>
+template <typename T, int W, bool SPLIT, bool SYM, int LDS_BYTES>
 __device__ __forceinline__ void native_tile(int bm, const TileJob &job, const Seg *__restrict__ segs,
                                             const T *__restrict__ store, const MatDesc &md, int64_t n0, T *As,
                                             T *Bs, const NearGen &ng) {
@@ -1177,38 +1177,38 @@ __device__ __forceinline__ void native_tile(int bm, const TileJob &job, const Se
                   "FP32 stages exceed the LDS");
     if (bm == 128 || (!kFine && bm == 96)) {
         block_product<T, 128, W, PLayout<128, W>::WMv, PLayout<128, W>::WN, kPersistThreads,
-                      SPLIT && sizeof(T) == 8, sizeof(T) == 8, SYMGEN>(job, segs, store, (T *)md.buf[0], (T *)md.buf[1],
+                      SPLIT && sizeof(T) == 8, sizeof(T) == 8, SYM>(job, segs, store, (T *)md.buf[0], (T *)md.buf[1],
                                                (T *)md.buf[2], (T *)md.buf[3], md.ldq, n0, As, Bs, ng);
     } else if (!kFine || bm == 64) {
         block_product<T, 64, W, PLayout<64, W>::WMv, PLayout<64, W>::WN, kPersistThreads,
-                      SPLIT && sizeof(T) == 8, sizeof(T) == 8, SYMGEN>(job, segs, store, (T *)md.buf[0], (T *)md.buf[1],
+                      SPLIT && sizeof(T) == 8, sizeof(T) == 8, SYM>(job, segs, store, (T *)md.buf[0], (T *)md.buf[1],
                                                (T *)md.buf[2], (T *)md.buf[3], md.ldq, n0, As, Bs, ng);
     } else if constexpr (kFine) {
         // 32- and 96-row tiles, for output blocks whose row count would
         // waste most of a 64- or 128-row tile
         if (bm == 96)
             block_product<T, 96, W, PLayout<96, W>::WMv, PLayout<96, W>::WN, kPersistThreads, false,
-                          sizeof(T) == 8, SYMGEN>(job, segs, store, (T *)md.buf[0], (T *)md.buf[1], (T *)md.buf[2],
+                          sizeof(T) == 8, SYM>(job, segs, store, (T *)md.buf[0], (T *)md.buf[1], (T *)md.buf[2],
                                                   (T *)md.buf[3], md.ldq, n0, As, Bs, ng);
         else
             block_product<T, 32, W, PLayout<32, W>::WMv, PLayout<32, W>::WN, kPersistThreads, false,
-                          sizeof(T) == 8, SYMGEN>(job, segs, store, (T *)md.buf[0], (T *)md.buf[1], (T *)md.buf[2],
+                          sizeof(T) == 8, SYM>(job, segs, store, (T *)md.buf[0], (T *)md.buf[1], (T *)md.buf[2],
                                                   (T *)md.buf[3], md.ldq, n0, As, Bs, ng);
     }
 }
 
 // native_tile at the task's own width bn (a power of two, 16 <= bn <= W).
-template <typename T, int W, bool SPLIT, bool SYMGEN, int LDS_BYTES>
+template <typename T, int W, bool SPLIT, bool SYM, int LDS_BYTES>
 __device__ __forceinline__ void narrow_tile(int bn, int bm, const TileJob &job, const Seg *__restrict__ segs,
                                             const T *__restrict__ store, const MatDesc &md, int64_t n0, T *As,
                                             T *Bs, const NearGen &ng) {
     if constexpr (W > 16) {
         if (bn < W) {
-            narrow_tile<T, W / 2, SPLIT, SYMGEN, LDS_BYTES>(bn, bm, job, segs, store, md, n0, As, Bs, ng);
+            narrow_tile<T, W / 2, SPLIT, SYM, LDS_BYTES>(bn, bm, job, segs, store, md, n0, As, Bs, ng);
             return;
         }
     }
-    native_tile<T, W, SPLIT, SYMGEN, LDS_BYTES>(bm, job, segs, store, md, n0, As, Bs, ng);
+    native_tile<T, W, SPLIT, SYM, LDS_BYTES>(bm, job, segs, store, md, n0, As, Bs, ng);
 }
 
 // Persistent task-graph launch: workgroups take queue entries in order with
@@ -1225,7 +1225,9 @@ __device__ __forceinline__ void narrow_tile(int bn, int bm, const TileJob &job, 
 // tiles keep their registers and code.
 // GEN: the FP64 launch that computes the near blocks from the points (see
 // NearGen); a separate instantiation, so that the stored-block launch keeps
-// its registers and code.
+// its registers and code.  With SYM as well for a symmetric store (its
+// stored blocks may be mirrors): the mirror-capable loop costs the points
+// launch about 5%, so it is not compiled into the plain one.
 template <typename T, int BN, bool SPLIT, bool GEN = false, bool SYM = false, bool NARROW = false>
 __global__ __launch_bounds__(kPersistThreads, (NARROW && sizeof(T) == 4) || BN <= 128 ? 4 : 1)
 void k_persistent(
@@ -1323,9 +1325,9 @@ void k_persistent(
                                                                   yh16, b0, b1, b2, b3, md.ldq, n0, lds);
             }
         } else if constexpr (NARROW) {
-            narrow_tile<T, BN, SPLIT, SYM || GEN, kMain>(pt.bn, pt.bm, job, segs, store, md, n0, As, Bs, ng);
+            narrow_tile<T, BN, SPLIT, SYM, kMain>(pt.bn, pt.bm, job, segs, store, md, n0, As, Bs, ng);
         } else {
-            native_tile<T, BN, SPLIT, SYM || GEN, kMain>(pt.bm, job, segs, store, md, n0, As, Bs, ng);
+            native_tile<T, BN, SPLIT, SYM, kMain>(pt.bm, job, segs, store, md, n0, As, Bs, ng);
         }
         __syncthreads();  // every wave's stores of this task are done
         if (threadIdx.x == 0 && pt.succ_end > pt.succ_begin) {
@@ -1589,9 +1591,14 @@ hipError_t run_persistent(const GraphPlan &plan, const MatDesc *mats, int32_t *h
                        plan.d_tasks, nt, counters, head);
     if constexpr (sizeof(T) == 8 && BN != 64) {
         if (out.from_points) {
-            hipLaunchKernelGGL((k_persistent<T, BN, false, true>), dim3((unsigned)grid), dim3(kPersistThreads), 0,
-                               s, plan.d_tasks, nt, plan.d_succ, counters, head, head + 1, mats, out.Y,
-                               out.ldy, out.Q, out.perm);
+            if (plan.sym)  // stored blocks of a symmetric store may be mirrors
+                hipLaunchKernelGGL((k_persistent<T, BN, false, true, true>), dim3((unsigned)grid),
+                                   dim3(kPersistThreads), 0, s, plan.d_tasks, nt, plan.d_succ, counters, head,
+                                   head + 1, mats, out.Y, out.ldy, out.Q, out.perm);
+            else
+                hipLaunchKernelGGL((k_persistent<T, BN, false, true>), dim3((unsigned)grid), dim3(kPersistThreads),
+                                   0, s, plan.d_tasks, nt, plan.d_succ, counters, head, head + 1, mats, out.Y,
+                                   out.ldy, out.Q, out.perm);
             return hipGetLastError();
         }
     }

@@ -184,3 +184,32 @@ def test_symmetric_store_full_size_headline(hmx):
     hmx.hm_eval(Ms, W, Ys)
     hmx.hm_check(Ms)
     assert torch.equal(Yf, Ys)
+
+
+@pytest.mark.parametrize("name", ["mix8", "tall", "tm_budget"])
+def test_symmetric_store_with_blocks_from_points(hmx, name):
+    """A symmetric store evaluated with blocks made from the points: near
+    blocks from the points with the far blocks read from the store (mirrors
+    among them), and far blocks from the skeletons with the near blocks read
+    from the store; each bitwise equal to the full store's evaluation with
+    the same flags, and within the FP64 parity bar of the oracle."""
+    w = CASES[name]
+    X = wl.gen_points(w)
+    H = OracleH2.from_workload(w, X)
+    Mf = hmx.hm_load_compressed_mem(H, 0)
+    Ms = hmx.hm_load_compressed_mem(H, 0, hmx.precbit(hmx.HM_PREC_FP64) | hmx.HM_LOAD_SYMMETRIC)
+    for M in (Mf, Ms):
+        hmx.hm_set_points(M, X, w.kernel, w.h)
+    W = wl.gen_w(w, Q=max(w.Q, 24))
+    Yref = H.eval(W)
+    Wd = torch.from_numpy(W).cuda()
+    for flags in (hmx.HM_NEAR_FROM_POINTS, hmx.HM_FAR_FROM_POINTS):
+        _say(f"[sym] case={name} points flags={flags}")
+        out = []
+        for M in (Mf, Ms):
+            Y = torch.full_like(Wd, float("nan"))
+            hmx.hm_eval(M, Wd, Y, flags=flags)
+            hmx.hm_check(M)
+            out.append(Y.cpu().numpy())
+        assert np.array_equal(out[0], out[1]), flags
+        assert rel(out[1], Yref) <= 1e-10
