@@ -101,15 +101,6 @@ __device__ __forceinline__ void load_lds16(const void *src, const char *lds_dst)
                  : "memory");
 }
 
-// The same with 4 bytes a lane: the 64 lanes' words land in 256 bytes of LDS,
-// lane l at lds_addr + 4 l.  Used for the A chunks of mirror blocks (see
-// product_loop_f64_dma), whose values are gathered along a stride.
-__device__ __forceinline__ void load_lds4(const void *src, const char *lds_dst) {
-    const uint32_t a = (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) char *)lds_dst;
-    asm volatile("global_load_lds_dword %0, off" ::"v"(src), "{m0}"(__builtin_amdgcn_readfirstlane(a))
-                 : "memory");
-}
-
 // Segment descriptor through a scalar (constant address space) load: it
 // counts against the scalar counter, so the compiler's wait for it never
 // covers the chunk loads in flight.  The descriptors are read-only during a
@@ -416,13 +407,12 @@ __device__ __forceinline__ void product_loop_f64_dma(
     // past K re-load row K - 1 (multiplied by zero rows of A).
     const bool gen = ng.pts != nullptr;
     // A mirror block (sg.trans) holds a row's contraction values
-    // contiguously, tstride apart from the next row's, so the 16-byte slots of
-    // the K-major stage layout (two rows' values at one contraction row) are
-    // gathered: four 4-byte direct loads per 1 KB block, lane l of load w
-    // fetching word l % 4 of slot 16 w + l / 4, i.e. one half of the value of
-    // row 2 pr + (l % 4) / 2.  The stage layout, and so the MFMA operand reads,
-    // are the ones of a stored K-major block.  Such a chunk issues
-    // MIRROR_EXTRA more loads a wave (see the waits below).
+    // contiguously, tstride apart from the next row's.  Its chunk goes into
+    // the A part of the stage pair-major instead: 16-byte slot P = s BM + r
+    // holds contraction values 2 s and 2 s + 1 of row r, one direct 16-byte
+    // load per slot as for any other block, and compute() reads such a stage
+    // with that layout (the 16 rows a 16-lane group reads at one contraction
+    // index sit 16 bytes apart, its two halves 8: no bank conflicts).
     auto issue = [&](int st, const Seg &sg, int kk) -> bool {
         const double *A = store + sg.a_off + m0 + (int64_t)kk * sg.lda;
         const char *AT = reinterpret_cast<const char *>(store + sg.a_off + (int64_t)m0 * sg.tstride + kk);
@@ -442,12 +432,8 @@ __device__ __forceinline__ void product_loop_f64_dma(
                 // not once per kernel and held through the task loop
                 int ml = lane;
                 asm volatile("" : "+v"(ml));
-#pragma unroll
-                for (int w = 0; w < 4; w++) {
-                    const int t = q * 64 + w * 16 + (ml >> 2), kr = t / (BM / 2);
-                    const int pr = (t % (BM / 2)) ^ ((kr & 1) ? SWA : 0), row = 2 * pr + ((ml >> 1) & 1);
-                    load_lds4(AT + ((int64_t)row * sg.tstride + kr) * 8 + (ml & 1) * 4, stage + q * 1024 + w * 256);
-                }
+                const int t = q * 64 + ml, sp = t / BM, r = t % BM;
+                load_lds16(AT + ((int64_t)r * sg.tstride + 2 * sp) * 8, stage + q * 1024);
                 continue;
             }
             const double *src;
@@ -462,18 +448,6 @@ __device__ __forceinline__ void product_loop_f64_dma(
         }
         return mirror;
     };
-    // Loads a wave issues beyond PER_WAVE for a mirror chunk: 3 more for each
-    // of its A blocks; the smallest count over the waves (a wave with more
-    // then waits a little longer than it must, never less).
-    constexpr int MIRROR_EXTRA = [] {
-        int lo = 1 << 20;
-        for (int w = 0; w < 8; w++) {
-            int na = 0;
-            for (int u = 0; u < PER_WAVE; u++) na += ((u * 8 + w < BLOCKS - 1 ? u * 8 + w : BLOCKS - 1) < A_BLOCKS);
-            lo = na < lo ? na : lo;
-        }
-        return 3 * lo;
-    }();
     // The A block of a chunk of a segment made from points: A[k][m] =
     // K(x_a[m], x_b[kk + k]), zero past the segment's K rows and the tile's
     // rows.  Wave w takes rows w and w + 8 (x_b through scalar loads), lanes
@@ -553,16 +527,24 @@ __device__ __forceinline__ void product_loop_f64_dma(
     const int a_lane = (lane >> 4) * BM * 8 + (wm * WM + arow) * 8, a_sw = (SWA && odd) ? 128 : 0;
     const int b_lane = (lane >> 4) * BN * 8 + (wn * WN + (lane & 15)) * 8, b_sw = (SWB && odd) ? 128 : 0;
     const int a_even = a_lane + a_sw, a_odd = a_lane - a_sw, b_even = b_lane + b_sw, b_odd = b_lane - b_sw;
+    // a mirror chunk's A (pair-major, see issue): value k = ks + lane / 16 of
+    // fragment i's row at ks BM 8 + a_mir + 256 i
+    const int a_mir = SYM ? (lane >> 5) * BM * 16 + ((lane >> 4) & 1) * 8 + (wm * WM + arow) * 16 : 0;
     // g: also make the A block of the chunk in stage gst (segment gsg, row
     // gkk) between MFMA steps, so that its VALU work runs while the other
     // wave of the SIMD keeps the MFMA pipe busy: the distances after the
     // first step, the exponentials after the third (after the first, too,
     // at BN < 256, where carrying the distances over two steps spills)
     constexpr int kStoreStep = BN >= 256 ? 8 : 0;
-    auto compute = [&](int st, bool g, int gst, const Seg &gsg, int gkk) {
+    auto compute = [&](int st, bool mir, bool g, int gst, const Seg &gsg, int gkk) {
         const char *sa = lds + st * kStage;
         const char *sb_ = sa + BM * kBK * 8;
         double r2g[NV];
+        int ai[FM];  // SYM: A fragment offsets within a k-step's rows, by the stage's layout
+        if constexpr (SYM) {
+#pragma unroll
+            for (int i = 0; i < FM; i++) ai[i] = mir ? a_mir + i * 256 : ((i & 1) ? a_odd : a_even) + i * 128;
+        }
         // 256-column tiles (registers to spare at two waves per SIMD): the
         // next k-step's operands are read from LDS before this k-step's
         // MFMAs, so that their latency hides behind them (128-column tiles,
@@ -572,7 +554,8 @@ __device__ __forceinline__ void product_loop_f64_dma(
         auto frags = [&](int ks, double (&a)[FM], double (&b)[FN]) {
 #pragma unroll
             for (int i = 0; i < FM; i++)
-                a[i] = *reinterpret_cast<const double *>(sa + ks * BM * 8 + ((i & 1) ? a_odd : a_even) + i * 128);
+                a[i] = *reinterpret_cast<const double *>(
+                    sa + ks * BM * 8 + (SYM ? ai[i] : ((i & 1) ? a_odd : a_even) + i * 128));
 #pragma unroll
             for (int j = 0; j < FN; j++)
                 b[j] = *reinterpret_cast<const double *>(sb_ + ks * BN * 8 + ((j & 1) ? b_odd : b_even) + j * 128);
@@ -595,9 +578,9 @@ __device__ __forceinline__ void product_loop_f64_dma(
         }
         if (g) asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");  // written before the next barrier
     };
-    auto compute_and_make = [&](int st, bool g, int gst, const Seg &gsg, int gkk) {
+    auto compute_and_make = [&](int st, bool mir, bool g, int gst, const Seg &gsg, int gkk) {
         if (computes)
-            compute(st, g, gst, gsg, gkk);
+            compute(st, mir, g, gst, gsg, gkk);
         else if (g)
             make_all(gst, gsg, gkk);
     };
@@ -638,7 +621,9 @@ __device__ __forceinline__ void product_loop_f64_dma(
         cur.kk = 0;
         cur.sg = load_seg_scalar(segs + sb);
         cur.nsg = sb + 1 < se ? load_seg_scalar(segs + sb + 1) : cur.sg;
-        issue(0, cur.sg, 0);  // chunk 0
+        // bit st: the chunk in stage st was loaded as a mirror block
+        int mbits = (SYM && issue(0, cur.sg, 0)) ? 1 : 0;  // chunk 0
+        if (!SYM) issue(0, cur.sg, 0);
         if (gen && cur.sg.from_pts == ng.kind) make_all(0, cur.sg, 0);
         cur = advance(cur);   // chunk 1
         int st = 0;           // stage of chunk c
@@ -647,23 +632,21 @@ __device__ __forceinline__ void product_loop_f64_dma(
         // register allocator copy every accumulator)
         if constexpr (STAGES == 3) {
             bool next_valid = cur.s < se;
-            // whether the chunk issued last (c + 1 at the wait) was loaded as
-            // a mirror block: it then has MIRROR_EXTRA more loads in flight
-            bool newest_mirror = SYM && issue(1, cur.sg, cur.kk);
+            if (SYM && issue(1, cur.sg, cur.kk)) mbits |= 2;
             if (!SYM) issue(1, cur.sg, cur.kk);
             if (gen && cur.sg.from_pts == ng.kind) make_all(1, cur.sg, cur.kk);
             cur = advance(cur);  // chunk c + 2
             bool more = true;
             do {
-                // chunk c landed; stage of c + 2 free
-                if (SYM && newest_mirror)
-                    wait_vm_barrier<PER_WAVE + MIRROR_EXTRA>();
-                else
-                    wait_vm_barrier<PER_WAVE>();
+                wait_vm_barrier<PER_WAVE>();  // chunk c landed; stage of c + 2 free
                 const bool after_valid = cur.s < se;
                 const int gst = st == 0 ? 2 : st - 1;
-                newest_mirror = issue(gst, cur.sg, cur.kk);
-                compute_and_make(st, gen && cur.sg.from_pts == ng.kind, gst, cur.sg, cur.kk);
+                const bool mir = SYM && ((mbits >> st) & 1);
+                if constexpr (SYM)
+                    mbits = __builtin_amdgcn_readfirstlane((mbits & ~(1 << gst)) | (issue(gst, cur.sg, cur.kk) ? 1 << gst : 0));
+                else
+                    issue(gst, cur.sg, cur.kk);
+                compute_and_make(st, mir, gen && cur.sg.from_pts == ng.kind, gst, cur.sg, cur.kk);
                 more = next_valid;
                 next_valid = after_valid;
                 cur = advance(cur);
@@ -674,8 +657,12 @@ __device__ __forceinline__ void product_loop_f64_dma(
             do {
                 wait_vm_barrier<0>();  // chunk c landed; the other stage is free
                 more = cur.s < se;     // chunk c + 1 exists
-                issue(st ^ 1, cur.sg, cur.kk);  // chunk c + 1 (or a repeat)
-                compute_and_make(st, gen && cur.sg.from_pts == ng.kind, st ^ 1, cur.sg, cur.kk);
+                const bool mir = SYM && ((mbits >> st) & 1);
+                if constexpr (SYM)  // chunk c + 1 (or a repeat)
+                    mbits = __builtin_amdgcn_readfirstlane((mbits & ~(1 << (st ^ 1))) | (issue(st ^ 1, cur.sg, cur.kk) ? 1 << (st ^ 1) : 0));
+                else
+                    issue(st ^ 1, cur.sg, cur.kk);
+                compute_and_make(st, mir, gen && cur.sg.from_pts == ng.kind, st ^ 1, cur.sg, cur.kk);
                 cur = advance(cur);
                 st = __builtin_amdgcn_readfirstlane(st ^ 1);
             } while (more);
