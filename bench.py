@@ -22,6 +22,7 @@ sys.path.insert(0, ROOT)
 PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 (vector = matrix)
 PEAK_FP32_TFLOPS = 157.3    # MI355X dense FP32
 PEAK_HBM_GBPS = 8000.0
+PEAK_BF16_TFLOPS = 2500.0   # MI355X dense BF16 MFMA
 
 
 def kernel_source_hash() -> str:
@@ -827,11 +828,24 @@ def main() -> int:
         # and leaf-basis products, FP64 transfers and final sum
         msm, phm, nm, Y = time_variant(hmx, torch, M, W64, args.steps, args.warmup, prec=hmx.HM_PREC_BF16X3)
         results["mixed_bf16x3"] = Y.cpu().numpy()
+        launch_m = phm[3] / max(nm[3], 1)
         out["mixed_bf16x3"] = {
             "ms_per_step": msm, "value": flops / (msm * 1e-3) / 1e9, "unit": "GFLOP/s",
-            "launch_ms": phm[3] / max(nm[3], 1), "speedup_vs_fp64": ms64 / msm,
+            "launch_ms": launch_m, "speedup_vs_fp64": ms64 / msm,
             "rel_err_vs_gpu_fp64": float(np.linalg.norm(results["mixed_bf16x3"] - results["fp64"])
                                          / np.linalg.norm(results["fp64"]))}
+        # the split-BF16 launch against both of its ceilings: its profiled
+        # memory-fabric bytes (HBM and Infinity Cache reads, the committed
+        # counter summary of the current kernel source) over the launch
+        # time, and its BF16 MFMA work (three products per stored product)
+        traffic_m = measured_traffic("task_graph_c2_mixed")
+        bf16_tflops = 3 * flops / (launch_m * 1e-3) / 1e12
+        out["mixed_bf16x3"]["roofline"] = {
+            "bound": "hbm", "unit": "GB/s", "peak": PEAK_HBM_GBPS, "traffic": traffic_m,
+            "achieved": traffic_m / (launch_m * 1e-3) / 1e9 if traffic_m else None,
+            "frac": traffic_m / (launch_m * 1e-3) / 1e9 / PEAK_HBM_GBPS if traffic_m else None,
+            "mfma_bf16": {"achieved": bf16_tflops, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                          "frac": bf16_tflops / PEAK_BF16_TFLOPS}}
     if args.symmetric:
         # symmetric store: each far and near block of a pair stored once, the
         # mirror product reading it transposed (same results bitwise)
