@@ -372,6 +372,12 @@ hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_mat
     }
 
     // ---- dependency graph for the persistent launch
+    // A down job whose far blocks outweigh the transfer from its parent (at
+    // least 4x the contraction rows) is cut in two: its far blocks (which
+    // wait only for the partners' up jobs) and then the transfer, added to
+    // them, which waits for the parent's Ŷ.  The chain down the tree then
+    // holds the short transfers only, not every node's far field.
+    auto split_down = [&](int64_t k_far, int64_t k_td) { return k_far > 0 && k_td > 0 && k_far >= 4 * k_td; };
     std::vector<GJob> jobs;
     {
         std::vector<int32_t> up_job(n, -1), down_job(n, -1), near_job(n, -1);
@@ -398,9 +404,27 @@ hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_mat
                 for (int64_t e = r.far_ptr[a]; e < r.far_ptr[a + 1]; e++)
                     if (r.rank[r.far_col[e]] > 0) j.preds.push_back(up_job[r.far_col[e]]);
                 const int32_t p = r.parent[a];
-                if (p >= 0 && r.level[p] >= 1 && r.rank[p] > 0) j.preds.push_back(down_job[p]);
-                down_job[a] = (int32_t)jobs.size();
-                jobs.push_back(j);
+                const bool has_td = p >= 0 && r.level[p] >= 1 && r.rank[p] > 0;
+                // segments: the far blocks, then (with has_td) the transfer from the parent
+                const int64_t k_td = has_td ? P.segs[pl.seg_end - 1].Kpad : 0;
+                if (has_td && split_down(pl.kpad - k_td, k_td)) {
+                    GJob fj = j;  // far blocks
+                    fj.seg_end = pl.seg_end - 1;
+                    fj.kpad = pl.kpad - k_td;
+                    const int32_t far_job = (int32_t)jobs.size();
+                    jobs.push_back(fj);
+                    GJob tj = j;  // transfer from the parent, added
+                    tj.seg_begin = pl.seg_end - 1;
+                    tj.kpad = k_td;
+                    tj.accumulate = 1;
+                    tj.preds = {far_job, down_job[p]};
+                    down_job[a] = (int32_t)jobs.size();
+                    jobs.push_back(tj);
+                } else {
+                    if (has_td) j.preds.push_back(down_job[p]);
+                    down_job[a] = (int32_t)jobs.size();
+                    jobs.push_back(j);
+                }
             } else {
                 // the leaf block's segments are its near blocks followed by
                 // the leaf far part (present when the leaf has a basis)
@@ -481,9 +505,31 @@ hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_mat
                 }
                 for (int64_t e = r.far_ptr[a]; e < r.far_ptr[a + 1]; e++)
                     if (r.rank[r.far_col[e]] > 0) dj.preds.push_back(up_job[r.far_col[e]]);
-                if (has_td) dj.preds.push_back(down_job[p]);
-                down_job[a] = (int32_t)mjobs.size();
-                mjobs.push_back(dj);
+                const int64_t k_td = has_td ? P.segs[pl.seg_end - 1].Kpad : 0;
+                if (dj.mode == 2 && !leaf(a) && split_down(dj.kpad_split, k_td)) {
+                    // cut as in the native graph (internal nodes: their Ŷ is
+                    // FP64 only): the far blocks in split BF16 written as
+                    // FP64, then the FP64 transfer added to them
+                    GJob fj = dj;
+                    fj.mode = 1;
+                    fj.seg_end = far_end;
+                    fj.kpad = dj.kpad_split;
+                    const int32_t far_job = (int32_t)mjobs.size();
+                    mjobs.push_back(fj);
+                    GJob tj = dj;
+                    tj.mode = 0;
+                    tj.seg_begin = far_end;
+                    tj.kpad = k_td;
+                    tj.kpad_split = 0;
+                    tj.accumulate = 1;
+                    tj.preds = {far_job, down_job[p]};
+                    down_job[a] = (int32_t)mjobs.size();
+                    mjobs.push_back(tj);
+                } else {
+                    if (has_td) dj.preds.push_back(down_job[p]);
+                    down_job[a] = (int32_t)mjobs.size();
+                    mjobs.push_back(dj);
+                }
             } else {
                 const bool far_part = r.rank[a] > 0 && r.level[a] >= 1;
                 GJob nj = j;
