@@ -506,14 +506,17 @@ hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_mat
                 for (int64_t e = r.far_ptr[a]; e < r.far_ptr[a + 1]; e++)
                     if (r.rank[r.far_col[e]] > 0) dj.preds.push_back(up_job[r.far_col[e]]);
                 const int64_t k_td = has_td ? P.segs[pl.seg_end - 1].Kpad : 0;
-                if (dj.mode == 2 && !leaf(a) && split_down(dj.kpad_split, k_td)) {
-                    // cut as in the native graph (internal nodes: their Ŷ is
-                    // FP64 only): the far blocks in split BF16 written as
-                    // FP64, then the FP64 transfer added to them
+                if (dj.mode == 2 && split_down(dj.kpad_split, k_td)) {
+                    // cut as in the native graph: the far blocks in split
+                    // BF16 written as FP64, then the FP64 transfer added to
+                    // them (a leaf's transfer job writes the split copy of the
+                    // sum, the only form its leaf far part reads)
                     GJob fj = dj;
                     fj.mode = 1;
                     fj.seg_end = far_end;
                     fj.kpad = dj.kpad_split;
+                    fj.out16 = -1;
+                    fj.out_split = 0;
                     const int32_t far_job = (int32_t)mjobs.size();
                     mjobs.push_back(fj);
                     GJob tj = dj;

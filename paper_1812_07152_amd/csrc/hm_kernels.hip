@@ -711,6 +711,10 @@ __device__ __forceinline__ void store_tile(const TileJob &task, OUT *buf0, OUT *
     if constexpr (kSplitCopy) {
         if (split_copy && computes) {
             float *tile = reinterpret_cast<float *>(lds);
+            // with task.accumulate, the copy is of the output's earlier value
+            // plus this tile (a transfer added to far blocks written before)
+            const OUT *prev = (task.out_buf == 0 ? buf0 : task.out_buf == 1 ? buf1 : task.out_buf == 2 ? buf2 : buf3) +
+                              task.out_row * ldq + n0;
             // registers r = 0..3 of a lane are rows 4(l/16) + r of one column
 #pragma unroll
             for (int i = 0; i < FM; i++)
@@ -718,8 +722,14 @@ __device__ __forceinline__ void store_tile(const TileJob &task, OUT *buf0, OUT *
                 for (int j = 0; j < FN; j++) {
                     const int col = wn * WN + j * 16 + (lane & 15);
                     const int row = wm * WM + i * 16 + 4 * (lane >> 4);
-                    *reinterpret_cast<f4_t *>(tile + col * kPitch + row) =
-                        f4_t{(float)acc[i][j][0], (float)acc[i][j][1], (float)acc[i][j][2], (float)acc[i][j][3]};
+                    f4_t v;
+#pragma unroll
+                    for (int u = 0; u < 4; u++) {
+                        OUT x = (OUT)acc[i][j][u];
+                        if (task.accumulate && row + u < task.M) x += prev[(int64_t)(row + u) * ldq + col];
+                        v[u] = (float)x;
+                    }
+                    *reinterpret_cast<f4_t *>(tile + col * kPitch + row) = v;
                 }
         }
     }
