@@ -115,7 +115,7 @@ hm_status configure(hm_batch b, int bn) {
         pd.perm = h->d_perm;
         pd.N = h->N;
         pd.Q = b->Q[i];
-        parts.push_back({h, i, b->ldq[i]});
+        parts.push_back({h, i, b->ldq[i], 0, false});
     }
     HM_HIP(hipMemcpy(b->d_mats, mats.data(), sizeof(MatDesc) * b->n, hipMemcpyHostToDevice));
     const int occ = persistent_occupancy(b->es, bn, false, sym, narrow);

@@ -376,10 +376,13 @@ hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_mat
     // least 4x the contraction rows) is cut in two: its far blocks (which
     // wait only for the partners' up jobs) and then the transfer, added to
     // them, which waits for the parent's Ŷ.  The chain down the tree then
-    // holds the short transfers only, not every node's far field.
+    // holds the short transfers only, not every node's far field.  The cut
+    // costs one more read and write of the output tile; it pays where one
+    // matrix's graph has the launch to itself.  A launch of many graphs (a
+    // batch, concurrent served sweeps) is not bound by any one chain and
+    // takes the whole down jobs (the second native graph).
     auto split_down = [&](int64_t k_far, int64_t k_td) { return k_far > 0 && k_td > 0 && k_far >= 4 * k_td; };
-    std::vector<GJob> jobs;
-    {
+    auto native_graph = [&](bool cut, std::vector<GJob> &jobs) -> hm_status {
         std::vector<int32_t> up_job(n, -1), down_job(n, -1), near_job(n, -1);
         for (const Planner::Placed &pl : P.placed) {
             GJob j{};
@@ -407,7 +410,7 @@ hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_mat
                 const bool has_td = p >= 0 && r.level[p] >= 1 && r.rank[p] > 0;
                 // segments: the far blocks, then (with has_td) the transfer from the parent
                 const int64_t k_td = has_td ? P.segs[pl.seg_end - 1].Kpad : 0;
-                if (has_td && split_down(pl.kpad - k_td, k_td)) {
+                if (cut && has_td && split_down(pl.kpad - k_td, k_td)) {
                     GJob fj = j;  // far blocks
                     fj.seg_end = pl.seg_end - 1;
                     fj.kpad = pl.kpad - k_td;
@@ -450,6 +453,13 @@ hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_mat
         for (const GJob &j : jobs)
             for (int32_t q : j.preds)
                 if (q < 0) return fail(HM_ERR_INTERNAL, "dependency graph: missing predecessor job");
+        return HM_OK;
+    };
+    std::vector<GJob> jobs, jobs_whole;
+    {
+        hm_status gst = native_graph(true, jobs);
+        if (gst == HM_OK) gst = native_graph(false, jobs_whole);
+        if (gst != HM_OK) return gst;
     }
     // Mixed precision: the same jobs with the products of the leaf bases, far
     // blocks and near blocks in split BF16 and the transfers in FP64; a down
@@ -619,6 +629,7 @@ hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_mat
     h->phases = P.phases;
     h->task_k = job_task_k(jobs);
     h->gjobs = std::move(jobs);
+    h->gjobs_whole = std::move(jobs_whole);
     h->gjobs_mixed = std::move(mjobs);
 
     hipStream_t s = nullptr;

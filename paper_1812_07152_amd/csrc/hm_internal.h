@@ -256,7 +256,8 @@ struct hm_matrix_s {
     hm::Task *d_tasks = nullptr;
     hm::Seg *d_segs = nullptr;
     std::vector<hm::Phase> phases;
-    std::vector<hm::GJob> gjobs;           // dependency graph of one evaluation
+    std::vector<hm::GJob> gjobs;           // dependency graph of one evaluation (down jobs cut)
+    std::vector<hm::GJob> gjobs_whole;     // same, every down job whole (launches of many graphs)
     std::vector<hm::GJob> gjobs_mixed;     // same, with split-BF16 and FP64 parts separated
     double task_k = 0;                     // job_task_k(gjobs)
     void *store16 = nullptr;               // split-BF16 block store (HM_PREC_BF16X3)
@@ -434,6 +435,7 @@ struct PlanPart {
     int mat;  // index in the MatDesc table
     int64_t Qp;  // padded columns: tiles of bn, then at most one narrower tile (padded_columns)
     int mode = 0;  // which job graph of h: 0 native, 1 mixed precision
+    bool cut_down = true;  // native graph: down jobs cut (one matrix alone) or whole (many graphs)
 };
 hm_status build_plan(const std::vector<PlanPart> &parts, int bn, int elem_bytes, int workers, GraphPlan &plan);
 void free_plan(GraphPlan &p);

@@ -49,7 +49,9 @@ hm_status build_plan(const std::vector<PlanPart> &parts, int bn, int elem_bytes,
     const double overhead = 2.0 * 128 * 64 * 256;  // fixed per-entry cost, in flops
     for (size_t i = 0; i < parts.size(); i++) {
         P &p = ps[i];
-        p.jobs = parts[i].mode == 1 ? &parts[i].h->gjobs_mixed : &parts[i].h->gjobs;
+        p.jobs = parts[i].mode == 1 ? &parts[i].h->gjobs_mixed
+                 : parts[i].cut_down ? &parts[i].h->gjobs
+                                     : &parts[i].h->gjobs_whole;
         p.mat = parts[i].mat;
         for (int64_t n0 = 0; n0 < parts[i].Qp; n0 += bn) {
             const int64_t w = std::min<int64_t>(bn, parts[i].Qp - n0);

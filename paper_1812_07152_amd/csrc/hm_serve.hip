@@ -421,7 +421,7 @@ hm_status hm_server_add(hm_server S, hm_matrix h, int *mat_id) {
         const std::pair<int, int> shape = sweep_shape(S, h, q);
         if (R.plans.count(shape)) continue;
         GraphPlan p;
-        std::vector<PlanPart> parts{{h, 0, shape.second, 0}};
+        std::vector<PlanPart> parts{{h, 0, shape.second, 0, false}};
         const bool narrow = shape.second % shape.first != 0;
         st = build_plan(parts, shape.first, S->es,
                         persistent_occupancy(S->es, shape.first, false, h->symmetric, narrow) * h->n_cu, p);
