@@ -406,7 +406,7 @@ static int orc_pair_cmp(const void *x, const void *y)
 
 static void orc_to_csr(int n, orc_pairs *P, int64_t **ptr, int **col)
 {
-    qsort(P->v, (size_t)P->n, sizeof(orc_pair), orc_pair_cmp);
+    if (P->n > 1) qsort(P->v, (size_t)P->n, sizeof(orc_pair), orc_pair_cmp);  /* v is NULL when empty */
     *ptr = calloc((size_t)n + 1, sizeof(int64_t));
     *col = malloc(sizeof(int) * (P->n ? P->n : 1));
     for (int64_t e = 0; e < P->n; e++) { (*ptr)[P->v[e].a + 1]++; (*col)[e] = P->v[e].b; }

@@ -171,7 +171,7 @@ hm_status validate(const HostRepr &r) {
     std::vector<int> child_of((size_t)n, 0);
     int32_t depth = 0;
     for (int64_t a = 0; a < n; a++) {
-        if (r.size[a] < 1 || r.start[a] < 0 || r.start[a] + r.size[a] > N)
+        if (r.size[a] < 1 || r.start[a] < 0 || r.start[a] > N || r.size[a] > N - r.start[a])
             return fail(HM_ERR_FORMAT, "node range out of bounds or empty");
         if (r.rank[a] < 0) return fail(HM_ERR_FORMAT, "negative rank");
         int32_t l = r.left[a], rr = r.right[a];
@@ -204,11 +204,17 @@ hm_status validate(const HostRepr &r) {
     auto disjoint = [&](int64_t a, int64_t b) {
         return r.start[a] + r.size[a] <= r.start[b] || r.start[b] + r.size[b] <= r.start[a];
     };
-    if ((int64_t)r.far_ptr.size() != n + 1 || r.far_ptr[0] != 0 ||
-        r.far_ptr[n] != (int64_t)r.far_col.size())
+    // CSR pointers: every one checked before any pair is read, so that a
+    // damaged pointer cannot send the walk past the column array
+    auto csr_ok = [&](const std::vector<int64_t> &ptr, size_t cols) {
+        if ((int64_t)ptr.size() != n + 1 || ptr[0] != 0 || ptr[(size_t)n] != (int64_t)cols) return false;
+        for (int64_t a = 0; a < n; a++)
+            if (ptr[(size_t)a + 1] < ptr[(size_t)a]) return false;
+        return true;
+    };
+    if (!csr_ok(r.far_ptr, r.far_col.size()) || r.far_off.size() != r.far_col.size())
         return fail(HM_ERR_FORMAT, "far CSR pointers are inconsistent");
     for (int64_t a = 0; a < n; a++) {
-        if (r.far_ptr[a + 1] < r.far_ptr[a]) return fail(HM_ERR_FORMAT, "far CSR pointers decrease");
         for (int64_t e = r.far_ptr[a]; e < r.far_ptr[a + 1]; e++) {
             int64_t b = r.far_col[e];
             if (b < 0 || b >= n || !disjoint(a, b)) return fail(HM_ERR_FORMAT, "invalid far pair");
@@ -217,25 +223,22 @@ hm_status validate(const HostRepr &r) {
                 return fail(HM_ERR_FORMAT, "B offset out of range");
         }
     }
-    if ((int64_t)r.near_ptr.size() != n + 1 || r.near_ptr[0] != 0 ||
-        r.near_ptr[n] != (int64_t)r.near_col.size())
+    if (!csr_ok(r.near_ptr, r.near_col.size()) || r.near_off.size() != r.near_col.size())
         return fail(HM_ERR_FORMAT, "near CSR pointers are inconsistent");
     for (int64_t a = 0; a < n; a++) {
-        if (r.near_ptr[a + 1] < r.near_ptr[a]) return fail(HM_ERR_FORMAT, "near CSR pointers decrease");
         for (int64_t e = r.near_ptr[a]; e < r.near_ptr[a + 1]; e++) {
             int64_t b = r.near_col[e];
             if (b < 0 || b >= n || r.left[a] >= 0 || r.left[b] >= 0)
                 return fail(HM_ERR_FORMAT, "near pairs must join two leaves");
             if (a != b && !disjoint(a, b)) return fail(HM_ERR_FORMAT, "invalid near pair");
+            if (r.size[b] > r.D_len / r.size[a]) return fail(HM_ERR_FORMAT, "D offset out of range");
             int64_t len = r.size[a] * r.size[b];
             if (r.near_off[e] < 0 || r.near_off[e] > r.D_len - len)
                 return fail(HM_ERR_FORMAT, "D offset out of range");
         }
     }
     if (!r.skel_ptr.empty()) {  // optional skeletons: k_a original point indices per node
-        if ((int64_t)r.skel_ptr.size() != n + 1 || r.skel_ptr[0] != 0 ||
-            r.skel_ptr[n] != (int64_t)r.skel.size())
-            return fail(HM_ERR_FORMAT, "skeleton pointers are inconsistent");
+        if (!csr_ok(r.skel_ptr, r.skel.size())) return fail(HM_ERR_FORMAT, "skeleton pointers are inconsistent");
         for (int64_t a = 0; a < n; a++)
             if (r.skel_ptr[a + 1] - r.skel_ptr[a] != r.rank[a])
                 return fail(HM_ERR_FORMAT, "a node's skeleton size differs from its rank");
