@@ -381,7 +381,16 @@ hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_mat
     // matrix's graph has the launch to itself.  A launch of many graphs (a
     // batch, concurrent served sweeps) is not bound by any one chain and
     // takes the whole down jobs (the second native graph).
-    auto split_down = [&](int64_t k_far, int64_t k_td) { return k_far > 0 && k_td > 0 && k_far >= 4 * k_td; };
+    auto split_down = [&](int64_t k_far, int64_t k_td, int64_t ratio) {
+        return k_far > 0 && k_td > 0 && k_far >= ratio * k_td;
+    };
+    // The thresholds, in contraction rows: 4x for the native graph, 2x for the
+    // mixed one, whose far blocks run in split BF16 and so cost less against
+    // the FP64 transfer than their length says (measured on the two-means
+    // budget structure: native 4x over 1x, 2x and 8x; mixed 2x over 4x and
+    // 8x, with 1x cutting the HSS down jobs, far block and transfer of equal
+    // length, to a loss).
+    constexpr int64_t kCutRatio = 4, kCutRatioMixed = 2;
     auto native_graph = [&](bool cut, std::vector<GJob> &jobs) -> hm_status {
         std::vector<int32_t> up_job(n, -1), down_job(n, -1), near_job(n, -1);
         for (const Planner::Placed &pl : P.placed) {
@@ -410,7 +419,7 @@ hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_mat
                 const bool has_td = p >= 0 && r.level[p] >= 1 && r.rank[p] > 0;
                 // segments: the far blocks, then (with has_td) the transfer from the parent
                 const int64_t k_td = has_td ? P.segs[pl.seg_end - 1].Kpad : 0;
-                if (cut && has_td && split_down(pl.kpad - k_td, k_td)) {
+                if (cut && has_td && split_down(pl.kpad - k_td, k_td, kCutRatio)) {
                     GJob fj = j;  // far blocks
                     fj.seg_end = pl.seg_end - 1;
                     fj.kpad = pl.kpad - k_td;
@@ -516,7 +525,7 @@ hm_status build_matrix(const HostRepr &r, int device, unsigned prec_mask, hm_mat
                 for (int64_t e = r.far_ptr[a]; e < r.far_ptr[a + 1]; e++)
                     if (r.rank[r.far_col[e]] > 0) dj.preds.push_back(up_job[r.far_col[e]]);
                 const int64_t k_td = has_td ? P.segs[pl.seg_end - 1].Kpad : 0;
-                if (dj.mode == 2 && split_down(dj.kpad_split, k_td)) {
+                if (dj.mode == 2 && split_down(dj.kpad_split, k_td, kCutRatioMixed)) {
                     // cut as in the native graph: the far blocks in split
                     // BF16 written as FP64, then the FP64 transfer added to
                     // them (a leaf's transfer job writes the split copy of the
