@@ -349,6 +349,12 @@ int pick_bn(int64_t Q, int kind);
 constexpr bool fine_tiles(int elem_bytes, int bn, bool split) {
     return !split && !(elem_bytes == 8 && bn == 128);
 }
+// Whether it has 48-, 80- and 112-row tiles as well (row tiles in steps of 16):
+// FP32 at 256 columns, where every such tile keeps all 8 waves busy (one
+// wave per 32 columns, each over the tile's full height).
+constexpr bool fine16_tiles(int elem_bytes, int bn, bool split) {
+    return !split && elem_bytes == 4 && bn == 256;
+}
 // Column tile of the persistent task-graph launch for Q columns of elem_bytes
 // (split: the launch runs split-BF16 tiles; task_k: the flop-weighted mean
 // contraction length of the graph's jobs, see job_task_k).

@@ -1158,13 +1158,32 @@ constexpr int kPersistThreads = 512;
 constexpr int kWaitLimit = 1 << 20;  // polls (each followed by a sleep) before giving up
 
 // A tile of stored (or generated) blocks at column width W in the launch's
-// type: the row-tile height bm picks the instantiation.  Where W has no 32-
-// and 96-row tiles (fine_tiles) but the plan made them (a narrow tile in a
-// launch whose own width has them), the next taller tile covers the rows.
+// type: the row-tile height bm picks the instantiation.  Where W lacks the
+// height the plan made (a narrow tile in a launch whose own width has finer
+// tiles, see fine_tiles and fine16_tiles), the next taller tile covers the
+// rows.
 template <typename T, int W, bool SPLIT, bool SYM, int LDS_BYTES>
 __device__ __forceinline__ void native_tile(int bm, const TileJob &job, const Seg *__restrict__ segs,
                                             const T *__restrict__ store, const MatDesc &md, int64_t n0, T *As,
                                             T *Bs, const NearGen &ng) {
+    if constexpr (fine16_tiles(sizeof(T), W, SPLIT)) {
+        if (bm == 48 || bm == 80 || bm == 112) {
+            if (bm == 48)
+                block_product<T, 48, W, PLayout<48, W>::WMv, PLayout<48, W>::WN, kPersistThreads, false, false,
+                              SYM>(job, segs, store, (T *)md.buf[0], (T *)md.buf[1], (T *)md.buf[2],
+                                   (T *)md.buf[3], md.ldq, n0, As, Bs, ng);
+            else if (bm == 80)
+                block_product<T, 80, W, PLayout<80, W>::WMv, PLayout<80, W>::WN, kPersistThreads, false, false,
+                              SYM>(job, segs, store, (T *)md.buf[0], (T *)md.buf[1], (T *)md.buf[2],
+                                   (T *)md.buf[3], md.ldq, n0, As, Bs, ng);
+            else
+                block_product<T, 112, W, PLayout<112, W>::WMv, PLayout<112, W>::WN, kPersistThreads, false, false,
+                              SYM>(job, segs, store, (T *)md.buf[0], (T *)md.buf[1], (T *)md.buf[2],
+                                   (T *)md.buf[3], md.ldq, n0, As, Bs, ng);
+            return;
+        }
+    }
+    bm = bm <= 32 ? 32 : bm <= 64 ? 64 : bm <= 96 ? 96 : 128;
     constexpr bool kFine = fine_tiles(sizeof(T), W, SPLIT);
     // the tallest tile's stages fit the kernel's LDS (FP64: the direct-to-LDS
     // stages from As; FP32: the register-staged As and Bs)

@@ -69,14 +69,17 @@ hm_status build_plan(const std::vector<PlanPart> &parts, int bn, int elem_bytes,
         p.first.assign(nj + 1, 0);
         for (int j = 0; j < nj; j++) {
             // row tiles of 128 rows; a job's last (or only) tile takes the
-            // smallest height that holds its remaining rows: 32, 64, 96 or
-            // 128 where the launch has the fine tiles (fine_tiles), else 64 or
-            // 128
+            // smallest height that holds its remaining rows: a multiple of
+            // 16 from 32 where the launch has those tiles (fine16_tiles), 32,
+            // 64, 96 or 128 where it has the fine tiles (fine_tiles), else 64
+            // or 128
             const int M = std::max(1, jobs[j].M);
             p.bm[j] = 128;
             p.rows[j] = (M + 127) / 128;
             const int rem = M - (p.rows[j] - 1) * 128;
-            p.last_bm[j] = !fine_tiles(elem_bytes, bn, parts[i].mode == 1)
+            const bool split = parts[i].mode == 1;
+            p.last_bm[j] = fine16_tiles(elem_bytes, bn, split) ? std::max(32, (rem + 15) / 16 * 16)
+                           : !fine_tiles(elem_bytes, bn, split)
                                ? (rem <= 64 ? 64 : 128)
                                : rem <= 32 ? 32 : rem <= 64 ? 64 : rem <= 96 ? 96 : 128;
             p.first[j + 1] = p.first[j] + p.rows[j];
