@@ -17,6 +17,9 @@ SPECS = [
     wl.small("b2", N=3000, d=3, m=64, Q=64, h=0.4, seed=13),
     wl.small("b3", N=2048, d=3, m=40, adm=wl.ADM_HSS, kernel=wl.KERNEL_LAPLACE, h=2.0, rmax=40, Q=100, seed=14),
     wl.small("b4", N=4096, d=8, points="mixture", m=64, h=1.2, Q=300, seed=15),
+    # leaves of 100 points and ranks 76..91: the 80-, 96- and 112-row tiles
+    # of FP32 256-column launches (b1 and b2 take the 48-row ones)
+    wl.small("b5", N=1600, d=3, m=128, h=0.5, tol=1e-9, rmax=128, Q=260, seed=16),
 ]
 
 
@@ -82,8 +85,8 @@ def test_batch_rejects_bad_arguments(setup):
 
 @pytest.mark.parametrize("dtype", ["fp64", "fp32"])
 def test_batched_256_column_tile_narrow_last_tiles(setup, dtype):
-    """HM_BATCH_TILE(256): the widths 5, 17, 64, 100 and 300 end in tiles of
-    16, 32, 64, 128 and 64 columns (300 = 256 + 44); FP64 to the parity bar
+    """HM_BATCH_TILE(256): the widths 5, 17, 64, 100, 300 and 260 end in tiles
+    of 16, 32, 64, 128, 64 and 16 columns (300 = 256 + 44); FP64 to the parity bar
     and FP32 to its bar against the oracle, and each matrix as hm_eval
     computes it alone (128-column tiles: the same products per column)."""
     hmx, Hs, Ms = setup
