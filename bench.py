@@ -732,7 +732,7 @@ def main() -> int:
                          "known traffic for calibrating HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: the benchmark runs on one GPU; --gpus {args.gpus} is not supported "
               "(on several GPUs the path would shard by columns of W, with no exchange between them)",
               file=sys.stderr)
         return 2
